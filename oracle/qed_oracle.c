@@ -1,0 +1,939 @@
+/*
+ * qed_oracle.c -- CPU oracle for the per-particle radiation-and-QED step of
+ * Lobet et al. (arXiv:1311.1107).  TEST INFRASTRUCTURE: used only by tests,
+ * by the smoke check and by the benchmark's CPU-baseline leg; never by the
+ * product.  Everything is FP64 and serial in particle-index order, written to
+ * be checked against the paper by eye rather than to be fast.
+ *
+ * Readings of passages the paper leaves garbled or open are marked READING.
+ */
+#include "qed_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ======================================================================== *
+ * 1. Constants (Sec. 2: E_s after Eq. 1, alpha_f and tau_c after Eq. 2,
+ *    tau_0 after Eq. 4).  CODATA 2018 values.
+ * ======================================================================== */
+void or_units_init(double lambda_m, or_units *u)
+{
+    const double c    = 299792458.0;
+    const double e    = 1.602176634e-19;
+    const double h    = 6.62607015e-34;
+    const double hbar = h / (2.0 * M_PI);
+    const double m    = 9.1093837015e-31;
+    const double eps0 = 8.8541878128e-12;
+
+    u->lambda  = lambda_m;
+    u->omega_r = 2.0 * M_PI * c / lambda_m;
+    u->alpha_f = e * e / (4.0 * M_PI * eps0 * hbar * c);
+    u->E_s     = m * m * c * c * c / (e * hbar);            /* after Eq. 1 */
+    u->B_s     = u->E_s / c;
+    /* READING: the paper calls tau_c = hbar/(m c^2) a "Compton length"; the
+     * prefactor alpha_f/(tau_c gamma^2) of Eq. 2 is a rate, so tau_c is the
+     * Compton time. */
+    u->tau_c   = hbar / (m * c * c);
+    u->tau_0   = 2.0 * e * e / (12.0 * M_PI * eps0 * m * c * c * c);  /* after Eq. 4 */
+    u->E_ref   = m * c * u->omega_r / e;
+    u->B_ref   = m * u->omega_r / e;
+    u->Es_hat  = u->E_s / u->E_ref;
+    u->A_hat   = u->alpha_f / (u->tau_c * u->omega_r);
+    u->tau0_hat = u->tau_0 * u->omega_r;
+}
+
+/* ======================================================================== *
+ * 2. Modified Bessel functions used by Eqs. 2-3.
+ *
+ *   K_nu(x)          = int_0^inf exp(-x cosh t) cosh(nu t) dt
+ *   int_x^inf K_nu   = int_0^inf exp(-x cosh t) cosh(nu t)/cosh t dt
+ *
+ * (the second by exchanging the order of integration).  Both integrands are
+ * even and analytic in a strip about the real t axis, so the trapezoidal rule
+ * with step h converges like exp(-2 pi d/h).  We return the values scaled by
+ * e^x, i.e. with exp(-x (cosh t - 1)) = exp(-2 x sinh^2(t/2)) in the
+ * integrand, which keeps them representable for large x.
+ * ======================================================================== */
+#define BK_H      0.125
+#define BK_NMAX   1400
+
+static double bk_c[BK_NMAX];       /* 2 sinh^2(t_k/2) = cosh t_k - 1 */
+static double bk_t[BK_NMAX];
+static double bk_cosh[BK_NMAX];
+static int bk_ready = 0;
+
+static void bk_init(void)
+{
+    if (bk_ready) return;
+    for (int k = 0; k < BK_NMAX; ++k) {
+        double t = k * BK_H;
+        double sh = sinh(0.5 * t);
+        bk_t[k] = t;
+        bk_c[k] = 2.0 * sh * sh;
+        bk_cosh[k] = cosh(t);
+    }
+    bk_ready = 1;
+}
+
+/* e^x K_nu(x) (kind 0) or e^x int_x^inf K_nu (kind 1) */
+static double bessel_scaled(double nu, double x, int kind)
+{
+    if (x <= 16.0) {
+        double sum = 0.0;
+        for (int k = 0; k < BK_NMAX; ++k) {
+            double t = bk_t[k];
+            double ex = x * bk_c[k];
+            double term = exp(-ex) * cosh(nu * t);
+            if (kind) term /= bk_cosh[k];
+            sum += (k == 0) ? 0.5 * term : term;
+            if (ex > 50.0 + t) break;
+        }
+        return sum * BK_H;
+    }
+    /* large x: the integrand is a narrow Gaussian-like bump; shrink h so
+     * that exp(-2 pi^2/(h^2 x)) stays negligible. */
+    double h = 0.5 / sqrt(x);
+    double sum = 0.0;
+    for (int k = 0; k < 100000; ++k) {
+        double t = k * h;
+        double sh = sinh(0.5 * t);
+        double ex = 2.0 * x * sh * sh;
+        double term = exp(-ex) * cosh(nu * t);
+        if (kind) term /= cosh(t);
+        sum += (k == 0) ? 0.5 * term : term;
+        if (ex > 60.0) break;
+    }
+    return sum * h;
+}
+
+double or_bessel_k(double nu, double x)
+{
+    bk_init();
+    return exp(-x) * bessel_scaled(nu, x, 0);
+}
+
+double or_bessel_ki(double nu, double x)
+{
+    bk_init();
+    return exp(-x) * bessel_scaled(nu, x, 1);
+}
+
+/* ======================================================================== *
+ * 3. Spectra.
+ *
+ * Eq. 2 with xi = chi_gamma/chi_e: y = xi/(3 chi_e (1-xi)), 2y = delta,
+ * 3 chi_gamma y = xi^2/(1-xi), and d gamma_gamma = gamma_e d xi, so
+ *   d^2N_gamma/dt dxi = alpha_f/(pi sqrt3 tau_c gamma_e) * B_gamma(xi),
+ *   B_gamma = (2 + xi^2/(1-xi)) K_{2/3}(delta) - int_delta^inf K_{1/3}.
+ * READING: the bracket printed in Eq. 2 has the opposite overall sign, which
+ * is negative for every y > 0; we use the positive (standard) spectrum.
+ *
+ * Eq. 3 with eta = chi_-/chi_gamma.  READING: y is not redefined for Eq. 3;
+ * we take y = chi_gamma/(3 chi_-(chi_gamma - chi_-)) = 1/(3 chi_gamma
+ * eta (1-eta)), so 3 chi_gamma y = 1/(eta(1-eta)) and
+ *   B_pm = int_delta^inf K_{1/3} + (1/(eta(1-eta)) - 2) K_{2/3}(delta),
+ *   delta = 2/(3 chi_gamma eta (1-eta)).
+ * ======================================================================== */
+double or_emit_bracket(double chi_e, double xi)
+{
+    if (!(xi > 0.0) || !(xi < 1.0)) return 0.0;
+    double delta = 2.0 * xi / (3.0 * chi_e * (1.0 - xi));
+    return (2.0 + xi * xi / (1.0 - xi)) * or_bessel_k(2.0 / 3.0, delta)
+           - or_bessel_ki(1.0 / 3.0, delta);
+}
+
+double or_pair_bracket(double chi_g, double eta)
+{
+    if (!(eta > 0.0) || !(eta < 1.0)) return 0.0;
+    double e1 = eta * (1.0 - eta);
+    double delta = 2.0 / (3.0 * chi_g * e1);
+    return or_bessel_ki(1.0 / 3.0, delta) + (1.0 / e1 - 2.0) * or_bessel_k(2.0 / 3.0, delta);
+}
+
+/*
+ * Quadrature variable.  Both spectra are integrated over s = logit of the
+ * fraction (xi = 1/(1+e^-s), or eta likewise), which maps (0,1) to the real
+ * line, turns the xi^(-2/3) endpoint behaviour into an exponential tail e^{s/3}
+ * and keeps the integrand analytic; composite 20-point Gauss-Legendre panels
+ * then give close to machine accuracy for totals and partial integrals alike.
+ *
+ * emit_f(s)  = B_gamma(xi(s)) dxi/ds
+ * pair_f(s)  = B_pm(eta(s)) deta/ds * exp(8/(3 chi))   (scaled: the pair
+ *              rate carries exp(-8/(3chi)) which would underflow at small chi)
+ */
+static double emit_f(double chi, double s)
+{
+    double es = exp(s);
+    double xi = es / (1.0 + es);
+    double omx = 1.0 / (1.0 + es);
+    if (isinf(es)) { xi = 1.0; omx = 0.0; }
+    double delta = 2.0 * es / (3.0 * chi);
+    if (delta > 740.0) return 0.0;
+    double k23 = bessel_scaled(2.0 / 3.0, delta, 0);
+    double ki13 = bessel_scaled(1.0 / 3.0, delta, 1);
+    double br = (2.0 + xi * es) * k23 - ki13;          /* e^delta B_gamma */
+    return exp(-delta) * br * (xi * omx);
+}
+
+static double pair_f(double chi, double s)
+{
+    double c2 = cosh(0.5 * s), s2 = sinh(0.5 * s);
+    double inv_e1 = 4.0 * c2 * c2;                       /* 1/(eta(1-eta)) */
+    double delta = (8.0 / (3.0 * chi)) * c2 * c2;
+    double excess = (8.0 / (3.0 * chi)) * s2 * s2;       /* delta - 8/(3chi) */
+    if (excess > 740.0) return 0.0;
+    double k23 = bessel_scaled(2.0 / 3.0, delta, 0);
+    double ki13 = bessel_scaled(1.0 / 3.0, delta, 1);
+    double br = ki13 + (inv_e1 - 2.0) * k23;             /* e^delta B_pm */
+    return exp(-excess) * br / inv_e1;
+}
+
+/* 20-point Gauss-Legendre rule on [-1,1], nodes by Newton on P_20. */
+#define GL_N 20
+static double gl_x[GL_N], gl_w[GL_N];
+static int gl_ready = 0;
+
+static void gl_init(void)
+{
+    if (gl_ready) return;
+    for (int i = 0; i < GL_N; ++i) {
+        double x = cos(M_PI * (i + 0.75) / (GL_N + 0.5));
+        double dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = x;
+            for (int n = 2; n <= GL_N; ++n) {
+                double p2 = ((2.0 * n - 1.0) * x * p1 - (n - 1.0) * p0) / n;
+                p0 = p1; p1 = p2;
+            }
+            dp = GL_N * (x * p1 - p0) / (x * x - 1.0);
+            double dx = p1 / dp;
+            x -= dx;
+            if (fabs(dx) < 1e-16) break;
+        }
+        /* recompute derivative at the converged node */
+        {
+            double p0 = 1.0, p1 = x;
+            for (int n = 2; n <= GL_N; ++n) {
+                double p2 = ((2.0 * n - 1.0) * x * p1 - (n - 1.0) * p0) / n;
+                p0 = p1; p1 = p2;
+            }
+            dp = GL_N * (x * p1 - p0) / (x * x - 1.0);
+        }
+        gl_x[i] = x;
+        gl_w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+    }
+    gl_ready = 1;
+}
+
+typedef double (*spec_fn)(double chi, double s);
+
+/* int_a^b f(chi, s) ds, optionally weighted by xi(s) (moment = 1) */
+static double gl_panel(spec_fn f, double chi, double a, double b, int moment)
+{
+    double half = 0.5 * (b - a), mid = 0.5 * (b + a), sum = 0.0;
+    for (int i = 0; i < GL_N; ++i) {
+        double s = mid + half * gl_x[i];
+        double v = f(chi, s);
+        if (moment) v *= 1.0 / (1.0 + exp(-s));
+        sum += gl_w[i] * v;
+    }
+    return sum * half;
+}
+
+/* panel layout over s for each spectrum */
+typedef struct {
+    int n;
+    double edge[1200];
+} panels;
+
+static void emit_panels(double chi, panels *p)
+{
+    /* below s = -20 the integrand is a smooth e^{s/3} tail; above, the
+     * double-exponential cut-off exp(-(2/(3chi)) e^s) needs finer panels. */
+    double s_lo = -120.0, s_mid = -20.0;
+    double s_hi = log(1.5 * chi * 760.0) + 0.5;
+    int n = 0;
+    for (double s = s_lo; s < s_mid - 1e-9; s += 2.0) p->edge[n++] = s;
+    int nfine = (int)ceil((s_hi - s_mid) / 0.5);
+    for (int k = 0; k <= nfine; ++k) p->edge[n++] = s_mid + (s_hi - s_mid) * k / nfine;
+    p->n = n - 1;
+}
+
+static void pair_panels(double chi, panels *p)
+{
+    double S = acosh(1.0 + 570.0 * chi) + 0.25;
+    int np = (int)ceil(2.0 * S / 0.25);
+    if (np < 8) np = 8;
+    for (int k = 0; k <= np; ++k) p->edge[k] = -S + 2.0 * S * k / np;
+    p->n = np;
+}
+
+static double spec_total(spec_fn f, double chi, const panels *p, int moment)
+{
+    double sum = 0.0;
+    for (int k = 0; k < p->n; ++k) sum += gl_panel(f, chi, p->edge[k], p->edge[k + 1], moment);
+    return sum;
+}
+
+double or_h_rad(double chi_e)
+{
+    gl_init(); bk_init();
+    panels p; emit_panels(chi_e, &p);
+    return spec_total(emit_f, chi_e, &p, 0) / (M_PI * sqrt(3.0));
+}
+
+/* Eq. 5: P_rad = int (d^2N/dt dgamma) gamma m c^2 dgamma.  READING: the
+ * printed lower limit 1 is taken as 0, so that P_rad/P_cl depends on chi only:
+ *   g = (sqrt3/(2 pi chi^2)) int_0^1 xi B_gamma dxi.                       */
+double or_g(double chi_e)
+{
+    gl_init(); bk_init();
+    panels p; emit_panels(chi_e, &p);
+    return sqrt(3.0) / (2.0 * M_PI * chi_e * chi_e) * spec_total(emit_f, chi_e, &p, 1);
+}
+
+double or_h_pair(double chi_g)
+{
+    gl_init(); bk_init();
+    panels p; pair_panels(chi_g, &p);
+    return exp(-8.0 / (3.0 * chi_g)) * spec_total(pair_f, chi_g, &p, 0) / (M_PI * sqrt(3.0));
+}
+
+static double cdf_generic(spec_fn f, double chi, const panels *p, double s_target)
+{
+    double num = 0.0, tot = 0.0;
+    for (int k = 0; k < p->n; ++k) {
+        double a = p->edge[k], b = p->edge[k + 1];
+        double full = gl_panel(f, chi, a, b, 0);
+        tot += full;
+        if (b <= s_target) num += full;
+        else if (a < s_target) num += gl_panel(f, chi, a, s_target, 0);
+    }
+    return num / tot;
+}
+
+double or_emit_cdf(double chi_e, double xi)
+{
+    gl_init(); bk_init();
+    if (!(xi > 0.0)) return 0.0;
+    if (!(xi < 1.0)) return 1.0;
+    panels p; emit_panels(chi_e, &p);
+    return cdf_generic(emit_f, chi_e, &p, log(xi) - log1p(-xi));
+}
+
+double or_pair_cdf(double chi_g, double eta)
+{
+    gl_init(); bk_init();
+    if (!(eta > 0.0)) return 0.0;
+    if (!(eta < 1.0)) return 1.0;
+    panels p; pair_panels(chi_g, &p);
+    return cdf_generic(pair_f, chi_g, &p, log(eta) - log1p(-eta));
+}
+
+/* ======================================================================== *
+ * 4. Tables: rates at log-spaced chi nodes and quantiles of the CDF of
+ *    Eq. 7 (emission) and of the pair CDF, at logit-spaced levels.
+ *    READING: node layout, quantile levels and interpolation are not given
+ *    by the paper; 128 log-spaced chi nodes and 128 logit levels in [-18,18].
+ * ======================================================================== */
+
+/* Solve CDF(s) = level for s, the CDF being the running integral over the
+ * panels.  Levels below one half are solved on the lower running sum,
+ * levels above on the upper (tail) sum so that the extreme quantiles keep
+ * their relative accuracy.  Safeguarded Newton inside the bracketing panel. */
+static double invert_level(spec_fn f, double chi, const panels *p,
+                           const double *panel_int, const double *cum_lo,
+                           const double *cum_hi, double total, double t_level)
+{
+    int upper = t_level > 0.0;
+    /* r = 1/(1+e^-t) below one half; 1-r = 1/(1+e^t) above */
+    double target = upper ? total / (1.0 + exp(t_level)) : total / (1.0 + exp(-t_level));
+    int np = p->n, k;
+    if (!upper) {
+        for (k = 0; k < np - 1; ++k) if (cum_lo[k + 1] > target) break;
+    } else {
+        for (k = np - 1; k > 0; --k) if (cum_hi[k] > target) break;
+    }
+    double a = p->edge[k], b = p->edge[k + 1];
+    double lo = a, hi = b;
+    /* linear first guess inside the panel */
+    double s = upper ? b - (target - cum_hi[k + 1]) / panel_int[k] * (b - a)
+                     : a + (target - cum_lo[k]) / panel_int[k] * (b - a);
+    if (!(s > lo && s < hi)) s = 0.5 * (lo + hi);
+    for (int it = 0; it < 100; ++it) {
+        double F, dF;
+        if (!upper) { F = cum_lo[k] + gl_panel(f, chi, a, s, 0) - target; dF = f(chi, s); }
+        else        { F = cum_hi[k + 1] + gl_panel(f, chi, s, b, 0) - target; dF = -f(chi, s); }
+        /* F is increasing in s for the lower sum and decreasing for the tail */
+        if ((F > 0.0) == (!upper)) hi = s; else lo = s;
+        double sn = (dF != 0.0) ? s - F / dF : 0.5 * (lo + hi);
+        if (!(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);
+        if (fabs(sn - s) <= 1e-15 * (1.0 + fabs(s))) { s = sn; break; }
+        s = sn;
+        if (hi - lo <= 1e-15 * (1.0 + fabs(s))) break;
+    }
+    return s;
+}
+
+static void quantile_row(spec_fn f, double chi, const panels *p, int n_q,
+                         double logit_max, double *row_s)
+{
+    double *pi = (double *)malloc(sizeof(double) * p->n);
+    double *lo = (double *)malloc(sizeof(double) * (p->n + 1));
+    double *hi = (double *)malloc(sizeof(double) * (p->n + 1));
+    for (int k = 0; k < p->n; ++k) pi[k] = gl_panel(f, chi, p->edge[k], p->edge[k + 1], 0);
+    lo[0] = 0.0;
+    for (int k = 0; k < p->n; ++k) lo[k + 1] = lo[k] + pi[k];
+    hi[p->n] = 0.0;
+    for (int k = p->n - 1; k >= 0; --k) hi[k] = hi[k + 1] + pi[k];
+    for (int q = 0; q < n_q; ++q) {
+        double t = -logit_max + 2.0 * logit_max * q / (n_q - 1);
+        double total = (t > 0.0) ? hi[0] : lo[p->n];
+        row_s[q] = invert_level(f, chi, p, pi, lo, hi, total, t);
+    }
+    free(pi); free(lo); free(hi);
+}
+
+int or_tables_compute(const or_table_spec *emit, const or_table_spec *pair,
+                      double *ln_hrad, double *ln_g, double *emit_q,
+                      double *pair_lnh, double *pair_q, int n_threads)
+{
+    gl_init(); bk_init();
+    if (emit->n_chi < 2 || emit->n_q < 2 || pair->n_chi < 2 || pair->n_q < 2) return 1;
+    int ne = emit->n_chi, npc = pair->n_chi;
+    double le0 = log(emit->chi_min), le1 = log(emit->chi_max);
+    double lp0 = log(pair->chi_min), lp1 = log(pair->chi_max);
+    (void)n_threads;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads > 0 ? n_threads : 1)
+    for (int job = 0; job < ne + npc; ++job) {
+        if (job < ne) {
+            int i = job;
+            double chi = exp(le0 + (le1 - le0) * i / (ne - 1));
+            panels p; emit_panels(chi, &p);
+            double tot = spec_total(emit_f, chi, &p, 0);
+            double mom = spec_total(emit_f, chi, &p, 1);
+            ln_hrad[i] = log(tot / (M_PI * sqrt(3.0)));
+            ln_g[i] = log(sqrt(3.0) / (2.0 * M_PI * chi * chi) * mom);
+            double *row = emit_q + (size_t)i * emit->n_q;
+            quantile_row(emit_f, chi, &p, emit->n_q, emit->logit_max, row);
+            for (int q = 0; q < emit->n_q; ++q) row[q] = -log1p(exp(-row[q]));  /* ln xi */
+        } else {
+            int i = job - ne;
+            double chi = exp(lp0 + (lp1 - lp0) * i / (npc - 1));
+            panels p; pair_panels(chi, &p);
+            double tot = spec_total(pair_f, chi, &p, 0);
+            pair_lnh[i] = log(tot / (M_PI * sqrt(3.0)));            /* + 8/(3chi) implied */
+            quantile_row(pair_f, chi, &p, pair->n_q, pair->logit_max,
+                         pair_q + (size_t)i * pair->n_q);
+        }
+    }
+    return 0;
+}
+
+void or_tables_bind(or_tables *t, const or_table_spec *emit, const or_table_spec *pair,
+                    const double *ln_hrad, const double *ln_g, const double *emit_q,
+                    const double *pair_lnh, const double *pair_q)
+{
+    t->e_n_chi = emit->n_chi; t->e_n_q = emit->n_q;
+    t->e_lnchi0 = log(emit->chi_min);
+    t->e_inv_dlnchi = (emit->n_chi - 1) / (log(emit->chi_max) - log(emit->chi_min));
+    t->e_logit_max = emit->logit_max;
+    t->e_inv_dt = (emit->n_q - 1) / (2.0 * emit->logit_max);
+    t->ln_hrad = ln_hrad; t->ln_g = ln_g; t->emit_q = emit_q;
+    t->p_n_chi = pair->n_chi; t->p_n_q = pair->n_q;
+    t->p_chi_min = pair->chi_min;
+    t->p_lnchi0 = log(pair->chi_min);
+    t->p_inv_dlnchi = (pair->n_chi - 1) / (log(pair->chi_max) - log(pair->chi_min));
+    t->p_logit_max = pair->logit_max;
+    t->p_inv_dt = (pair->n_q - 1) / (2.0 * pair->logit_max);
+    t->pair_lnh = pair_lnh; t->pair_q = pair_q;
+}
+
+/* Linear interpolation in (ln chi, ln h).  Outside the node range the end
+ * segment is extended (READING: the paper gives no table range); lookups above
+ * the last node are reported through *out_of_range. */
+static double lerp_rate(const double *tab, int n, double lnchi0, double inv_d,
+                        double chi, int *oor)
+{
+    double u = (log(chi) - lnchi0) * inv_d;
+    int i;
+    if (u < 0.0) i = 0;
+    else if (u >= (double)(n - 1)) { i = n - 2; if (oor) *oor = 1; }
+    else i = (int)u;
+    double w = u - (double)i;
+    return tab[i] + w * (tab[i + 1] - tab[i]);
+}
+
+double or_lookup_h_rad(const or_tables *t, double chi, int *oor)
+{
+    if (!(chi > 0.0)) return 0.0;
+    return exp(lerp_rate(t->ln_hrad, t->e_n_chi, t->e_lnchi0, t->e_inv_dlnchi, chi, oor));
+}
+
+double or_lookup_g(const or_tables *t, double chi)
+{
+    if (!(chi > 0.0)) return 1.0;
+    return exp(lerp_rate(t->ln_g, t->e_n_chi, t->e_lnchi0, t->e_inv_dlnchi, chi, NULL));
+}
+
+double or_lookup_h_pair(const or_tables *t, double chi, int *oor)
+{
+    if (!(chi >= t->p_chi_min)) return 0.0;
+    double v = lerp_rate(t->pair_lnh, t->p_n_chi, t->p_lnchi0, t->p_inv_dlnchi, chi, oor);
+    return exp(v - 8.0 / (3.0 * chi));
+}
+
+/* Bilinear in (ln chi, logit r), chi clamped to the node range. */
+static double bilerp_quantile(const double *q, int n_chi, int n_q, double lnchi0,
+                              double inv_d, double logit_max, double inv_dt,
+                              double chi, double r)
+{
+    double u = (log(chi) - lnchi0) * inv_d;
+    if (!(u > 0.0)) u = 0.0;
+    if (u > (double)(n_chi - 1)) u = (double)(n_chi - 1);
+    int i = (int)u;
+    if (i > n_chi - 2) i = n_chi - 2;
+    double w = u - (double)i;
+    /* logit of r; r = 1 gives +inf and lands on the top clamp */
+    double t = log(r) - log(1.0 - r);
+    if (!(t > -logit_max)) t = -logit_max;
+    if (t > logit_max) t = logit_max;
+    double v = (t + logit_max) * inv_dt;
+    int j = (int)v;
+    if (j > n_q - 2) j = n_q - 2;
+    double z = v - (double)j;
+    const double *r0 = q + (size_t)i * n_q, *r1 = r0 + n_q;
+    double a = r0[j] + z * (r0[j + 1] - r0[j]);
+    double b = r1[j] + z * (r1[j + 1] - r1[j]);
+    return a + w * (b - a);
+}
+
+double or_sample_xi(const or_tables *t, double chi, double r)
+{
+    double lnxi = bilerp_quantile(t->emit_q, t->e_n_chi, t->e_n_q, t->e_lnchi0, t->e_inv_dlnchi,
+                                  t->e_logit_max, t->e_inv_dt, chi, r);
+    double xi = exp(lnxi);
+    return xi < 1.0 ? xi : 1.0;
+}
+
+double or_sample_eta(const or_tables *t, double chi, double r)
+{
+    double s = bilerp_quantile(t->pair_q, t->p_n_chi, t->p_n_q, t->p_lnchi0, t->p_inv_dlnchi,
+                               t->p_logit_max, t->p_inv_dt, chi, r);
+    return 1.0 / (1.0 + exp(-s));
+}
+
+/* ======================================================================== *
+ * 5. Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of
+ *    (c0,c1,c2,c3) -> (hi(M1 c2)^c1^k0, lo(M1 c2), hi(M0 c0)^c3^k1, lo(M0 c0))
+ *    with the key bumped by the Weyl constants between rounds.
+ *    The uniform draws xi, xi', xi'' of Sec. 3 are ((b>>11)+1) 2^-53, in ]0,1].
+ * ======================================================================== */
+void or_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+    uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) { k0 += W0; k1 += W1; }
+        unsigned __int128 p0 = (unsigned __int128)M0 * c0;
+        unsigned __int128 p1 = (unsigned __int128)M1 * c2;
+        uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        uint64_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+double or_u01(uint64_t bits)
+{
+    return (double)((bits >> 11) + 1ULL) * (1.0 / 9007199254740992.0);
+}
+
+static void draw(uint64_t seed, uint64_t uid, uint32_t n_ev, uint64_t purpose, uint64_t out[4])
+{
+    uint64_t ctr[4] = { uid, (uint64_t)n_ev, purpose, 0ULL };
+    uint64_t key[2] = { seed, 0ULL };
+    or_philox4x64_10(ctr, key, out);
+}
+
+/* Sec. 3: a new particle's final optical depth tau^f = -log xi. */
+static double initial_tau(uint64_t seed, uint64_t uid)
+{
+    uint64_t o[4];
+    draw(seed, uid, 0, OR_RNG_INIT, o);
+    return -log(or_u01(o[0]));
+}
+
+void or_init_tau(or_species *s, uint64_t seed)
+{
+    for (int64_t i = 0; i < s->n; ++i) s->tau[i] = initial_tau(seed, s->uid[i]);
+}
+
+/* ======================================================================== *
+ * 6. Fields at a particle.
+ * ======================================================================== */
+
+/* Yee staggering of Ex Ey Ez Bx By Bz, in cells along x, y, z. */
+static const double yee_stag[6][3] = {
+    {0.5, 0.0, 0.0}, {0.0, 0.5, 0.0}, {0.0, 0.0, 0.5},
+    {0.0, 0.5, 0.5}, {0.5, 0.0, 0.5}, {0.5, 0.5, 0.0},
+};
+
+/* quadratic (triangular-shaped-cloud) weights around the nearest node */
+static void tsc_weights(double g, int64_t *i0, double w[3])
+{
+    double f = floor(g + 0.5);
+    double d = g - f;
+    *i0 = (int64_t)f;
+    w[0] = 0.5 * (0.5 - d) * (0.5 - d);
+    w[1] = 0.75 - d * d;
+    w[2] = 0.5 * (0.5 + d) * (0.5 + d);
+}
+
+void or_field_at(const or_field *f, double t, double x, double y, double z,
+                 double E[3], double B[3])
+{
+    E[0] = E[1] = E[2] = B[0] = B[1] = B[2] = 0.0;
+    if (f->kind == OR_FIELD_UNIFORM) {
+        for (int c = 0; c < 3; ++c) { E[c] = f->E[c]; B[c] = f->B[c]; }
+    } else if (f->kind == OR_FIELD_PLANE_WAVE) {
+        /* Linearly polarised plane wave along +x from the vector potential
+         * a_y(phi) = a0 sin^2(pi phi/Phi) sin(phi), phi = t - x, Phi = 2 pi N:
+         * E_y = -da_y/dt = -a_y', B_z = da_y/dx = -a_y'. */
+        double phi = t - x;
+        double Phi = 2.0 * M_PI * f->n_periods;
+        if (phi > 0.0 && phi < Phi) {
+            double arg = M_PI * phi / Phi;
+            double se = sin(arg), ce = cos(arg);
+            double sp = sin(phi), cp = cos(phi);
+            double da = f->a0 * ((M_PI / Phi) * (2.0 * se * ce) * sp + se * se * cp);
+            E[1] = -da;
+            B[2] = -da;
+        }
+    } else if (f->kind == OR_FIELD_YEE) {
+        double out[6];
+        for (int c = 0; c < 6; ++c) {
+            int64_t i0, j0, k0;
+            double wx[3], wy[3], wz[3];
+            tsc_weights((x - f->x0) / f->dx - yee_stag[c][0], &i0, wx);
+            tsc_weights((y - f->y0) / f->dy - yee_stag[c][1], &j0, wy);
+            tsc_weights((z - f->z0) / f->dz - yee_stag[c][2], &k0, wz);
+            double acc = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                int64_t i = i0 - 1 + a;
+                if (i < 0 || i >= f->nx) continue;
+                for (int b = 0; b < 3; ++b) {
+                    int64_t j = j0 - 1 + b;
+                    if (j < 0 || j >= f->ny) continue;
+                    for (int cc = 0; cc < 3; ++cc) {
+                        int64_t k = k0 - 1 + cc;
+                        if (k < 0 || k >= f->nz) continue;
+                        double v = (double)f->grid[c][(i * f->ny + j) * f->nz + k];
+                        acc += (wx[a] * wy[b]) * wz[cc] * v;
+                    }
+                }
+            }
+            out[c] = acc;
+        }
+        E[0] = out[0]; E[1] = out[1]; E[2] = out[2];
+        B[0] = out[3]; B[1] = out[4]; B[2] = out[5];
+    }
+}
+
+/* Separable laser pulse on the Yee grid: value = (float)((a0 * T_perp[j,k]) * T_par[i]),
+ * per component; tperp6 is [6][ny*nz], tpar6 is [6][nx]. */
+void or_yee_fill_separable(float *grid6, int64_t nx, int64_t ny, int64_t nz,
+                           double a0, const double *tperp6, const double *tpar6)
+{
+    int64_t plane = ny * nz, ncell = nx * plane;
+    for (int c = 0; c < 6; ++c)
+        for (int64_t i = 0; i < nx; ++i)
+            for (int64_t jk = 0; jk < plane; ++jk)
+                grid6[c * ncell + i * plane + jk] =
+                    (float)((a0 * tperp6[c * plane + jk]) * tpar6[c * nx + i]);
+}
+
+/* ======================================================================== *
+ * 7. Quantum parameters, Eq. 1, in covariant form (equal to the printed
+ *    E_par/E_perp form):
+ *      chi_e     = sqrt((gamma E + u x B)^2 - (u.E)^2) / E_s
+ *      chi_gamma = sqrt((|k| E + k x B)^2 - (k.E)^2) / E_s
+ *    READING: "c x B" in the printed chi_gamma is c k_hat x B.
+ * ======================================================================== */
+static double chi_generic(double es_hat, double g, const double p[3],
+                          const double E[3], const double B[3])
+{
+    double fx = g * E[0] + (p[1] * B[2] - p[2] * B[1]);
+    double fy = g * E[1] + (p[2] * B[0] - p[0] * B[2]);
+    double fz = g * E[2] + (p[0] * B[1] - p[1] * B[0]);
+    double pe = p[0] * E[0] + p[1] * E[1] + p[2] * E[2];
+    double q = (fx * fx + fy * fy + fz * fz) - pe * pe;
+    return (q > 0.0 ? sqrt(q) : 0.0) / es_hat;
+}
+
+double or_chi_lepton(const or_units *u, const double p[3], double gamma,
+                     const double E[3], const double B[3])
+{
+    return chi_generic(u->Es_hat, gamma, p, E, B);
+}
+
+double or_chi_photon(const or_units *u, const double k[3],
+                     const double E[3], const double B[3])
+{
+    double kk = sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+    return chi_generic(u->Es_hat, kk, k, E, B);
+}
+
+/* ======================================================================== *
+ * 8. Lepton step (Secs. 2-3).
+ *
+ * Order within a step (READING: the paper does not fix it): fields at x^n;
+ * Lorentz push u^{n-1/2} -> u_L (Boris); chi_e from (u_L, E, B); then either
+ * the Sokolov continuous scheme (Eqs. 4-5) or the optical-depth Monte Carlo
+ * (Eqs. 6-8); then x^{n+1} = x^n + dt dx/dt.
+ * ======================================================================== */
+static int append_ok(or_species *s)
+{
+    return s && s->n < s->capacity;
+}
+
+int or_push_emit(const or_tables *tab, const or_units *un, double q,
+                 or_species *L, const or_field *f,
+                 or_species *Pp, or_species *Pr,
+                 const or_step *st, uint64_t *uid_next,
+                 double *tally, int64_t *count)
+{
+    const double dt = st->dt, Es = un->Es_hat, A = un->A_hat, tau0 = un->tau0_hat;
+    int overflow = 0;
+    for (int64_t i = 0; i < L->n; ++i) {
+        double x[3] = { L->x[i], L->y[i], L->z[i] };
+        double u[3] = { L->ux[i], L->uy[i], L->uz[i] };
+        double E[3], B[3];
+        or_field_at(f, st->t, x[0], x[1], x[2], E, B);
+
+        double g_old = sqrt(1.0 + (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]));
+
+        /* --- Lorentz force f_l, Boris rotation ------------------------- */
+        double h = 0.5 * q * dt;
+        double um[3] = { u[0] + h * E[0], u[1] + h * E[1], u[2] + h * E[2] };
+        double gm = sqrt(1.0 + (um[0] * um[0] + um[1] * um[1] + um[2] * um[2]));
+        double tv[3] = { h * B[0] / gm, h * B[1] / gm, h * B[2] / gm };
+        double t2 = tv[0] * tv[0] + tv[1] * tv[1] + tv[2] * tv[2];
+        double sv[3] = { 2.0 * tv[0] / (1.0 + t2), 2.0 * tv[1] / (1.0 + t2), 2.0 * tv[2] / (1.0 + t2) };
+        double up[3] = { um[0] + (um[1] * tv[2] - um[2] * tv[1]),
+                         um[1] + (um[2] * tv[0] - um[0] * tv[2]),
+                         um[2] + (um[0] * tv[1] - um[1] * tv[0]) };
+        double uq[3] = { um[0] + (up[1] * sv[2] - up[2] * sv[1]),
+                         um[1] + (up[2] * sv[0] - up[0] * sv[2]),
+                         um[2] + (up[0] * sv[1] - up[1] * sv[0]) };
+        double uL[3] = { uq[0] + h * E[0], uq[1] + h * E[1], uq[2] + h * E[2] };
+        double gL = sqrt(1.0 + (uL[0] * uL[0] + uL[1] * uL[1] + uL[2] * uL[2]));
+        tally[OR_T_WORK] += L->w[i] * (gL - g_old);
+
+        /* --- chi_e, Eq. 1 ------------------------------------------------- */
+        double chi = chi_generic(Es, gL, uL, E, B);
+        double unew[3] = { uL[0], uL[1], uL[2] };
+        double dv[3] = { 0.0, 0.0, 0.0 };
+        int rad = st->rad_model;
+        if (!isfinite(chi) || !isfinite(gL)) { count[OR_C_NAN]++; rad = OR_RAD_NONE; }
+
+        if (rad == OR_RAD_SOKOLOV || (rad == OR_RAD_HYBRID && chi < st->chi_switch)) {
+            /* --- Sokolov scheme, Eq. 4 with P_rad of Eq. 5 ----------------
+             * READING (units of Eq. 4): delta_v = tau_0 (f_l - v (v.f_l))
+             * / (1 + tau_0 v.f_l) in normalised units, and the delta_v x B
+             * force carries the particle's charge q. */
+            count[OR_C_SOKOLOV]++;
+            double v[3] = { uL[0] / gL, uL[1] / gL, uL[2] / gL };
+            double fl[3] = { q * (E[0] + (v[1] * B[2] - v[2] * B[1])),
+                             q * (E[1] + (v[2] * B[0] - v[0] * B[2])),
+                             q * (E[2] + (v[0] * B[1] - v[1] * B[0])) };
+            double vf = v[0] * fl[0] + v[1] * fl[1] + v[2] * fl[2];
+            double den = 1.0 + tau0 * vf;
+            for (int c = 0; c < 3; ++c) dv[c] = tau0 * (fl[c] - v[c] * vf) / den;
+            double P = (2.0 / 3.0) * A * chi * chi * or_lookup_g(tab, chi);
+            double dvB[3] = { dv[1] * B[2] - dv[2] * B[1],
+                              dv[2] * B[0] - dv[0] * B[2],
+                              dv[0] * B[1] - dv[1] * B[0] };
+            for (int c = 0; c < 3; ++c) unew[c] = uL[c] + dt * (q * dvB[c] - P * uL[c] / gL);
+            tally[OR_T_ERAD] += L->w[i] * P * dt;
+        } else if (rad == OR_RAD_MC || rad == OR_RAD_HYBRID) {
+            /* --- optical-depth Monte Carlo, Eqs. 6-8 -----------------------
+             * tau holds tau^f - tau (what is left before the next emission);
+             * dtau/dt = W = A h_rad(chi)/gamma (Eq. 6).  READING: several
+             * emissions may fall in one step; each is placed at the local
+             * time where tau reaches tau^f, up to max_events per step. */
+            count[OR_C_MC]++;
+            double p = sqrt(uL[0] * uL[0] + uL[1] * uL[1] + uL[2] * uL[2]);
+            double uh[3] = { 0.0, 0.0, 0.0 };
+            if (p > 0.0) { uh[0] = uL[0] / p; uh[1] = uL[1] / p; uh[2] = uL[2] / p; }
+            double gam = gL, c_e = chi;
+            int oor = 0;
+            double W = (p > 0.0) ? A * or_lookup_h_rad(tab, c_e, &oor) / gam : 0.0;
+            if (oor) { count[OR_C_RANGE]++; oor = 0; }
+            double tau = L->tau[i], t_left = dt;
+            int k = 0, emitted = 0;
+            for (;;) {
+                if (!(W > 0.0) || tau > W * t_left) { tau -= W * t_left; break; }
+                if (k == st->max_events) { tau -= W * t_left; count[OR_C_CAP]++; break; }
+                t_left -= (tau > 0.0 ? tau : 0.0) / W;
+                uint64_t o[4];
+                draw(st->seed, L->uid[i], L->n_ev[i], OR_RNG_EMIT, o);
+                double r1 = or_u01(o[0]), r2 = or_u01(o[1]);
+                /* Eq. 7 inverted: chi_gamma = xi chi_e; gamma_gamma = xi gamma_e */
+                double xi = or_sample_xi(tab, c_e, r1);
+                double gg = xi * gam;
+                double wgt = L->w[i];
+                count[OR_C_EMIT]++;
+                if (gg > st->gamma_photon_min) {
+                    /* Sec. 3: photon along the electron velocity, born at x^n,
+                     * stored at level n+1: x^n + dt k_hat. */
+                    double chig = xi * c_e;
+                    or_species *dst = NULL;
+                    int which;
+                    if (Pp && chig > st->chi_photon_push_min) { dst = Pp; which = 0; }
+                    else if (Pr) { dst = Pr; which = 1; }
+                    else which = 2;
+                    if (which == 2) {
+                        count[OR_C_DROP]++; tally[OR_T_EDROP] += wgt * gg;
+                    } else {
+                        uint64_t nid = (*uid_next)++;
+                        if (append_ok(dst)) {
+                            int64_t j = dst->n++;
+                            dst->x[j] = x[0] + dt * uh[0];
+                            dst->y[j] = x[1] + dt * uh[1];
+                            dst->z[j] = x[2] + dt * uh[2];
+                            dst->ux[j] = gg * uh[0];
+                            dst->uy[j] = gg * uh[1];
+                            dst->uz[j] = gg * uh[2];
+                            dst->w[j] = wgt;
+                            dst->chi[j] = chig;
+                            dst->uid[j] = nid;
+                            dst->n_ev[j] = 0;
+                            dst->tau[j] = initial_tau(st->seed, nid);
+                        } else {
+                            overflow = 1; count[OR_C_OVERFLOW]++;
+                        }
+                        if (which == 0) { count[OR_C_PUSH]++; tally[OR_T_EPUSH] += wgt * gg; }
+                        else            { count[OR_C_REC]++;  tally[OR_T_EREC]  += wgt * gg; }
+                    }
+                } else {
+                    /* READING: below 2 m c^2 no super-photon is created, the
+                     * electron still recoils and the energy is tallied. */
+                    count[OR_C_SUB]++; tally[OR_T_ESUB] += wgt * gg;
+                }
+                /* Eq. 8: p_f = (p - eps_gamma/c) p_hat, clamped at zero */
+                if (!st->no_recoil) {
+                    p = p - gg;
+                    if (p < 0.0) p = 0.0;
+                    gam = sqrt(1.0 + p * p);
+                    double pv[3] = { p * uh[0], p * uh[1], p * uh[2] };
+                    c_e = chi_generic(Es, gam, pv, E, B);
+                    W = (p > 0.0) ? A * or_lookup_h_rad(tab, c_e, &oor) / gam : 0.0;
+                    if (oor) { count[OR_C_RANGE]++; oor = 0; }
+                }
+                tau = -log(r2);              /* new tau^f = -log xi */
+                L->n_ev[i]++;
+                ++k; emitted = 1;
+            }
+            L->tau[i] = tau;
+            if (emitted) { unew[0] = p * uh[0]; unew[1] = p * uh[1]; unew[2] = p * uh[2]; }
+        }
+
+        /* --- position: dx/dt = v (+ delta_v for Sokolov, Eq. 4) ---------- */
+        double gn = sqrt(1.0 + (unew[0] * unew[0] + unew[1] * unew[1] + unew[2] * unew[2]));
+        L->x[i] = x[0] + dt * (unew[0] / gn + dv[0]);
+        L->y[i] = x[1] + dt * (unew[1] / gn + dv[1]);
+        L->z[i] = x[2] + dt * (unew[2] / gn + dv[2]);
+        L->ux[i] = unew[0]; L->uy[i] = unew[1]; L->uz[i] = unew[2];
+    }
+    return overflow;
+}
+
+/* ======================================================================== *
+ * 9. Photon step (Sec. 3, pair creation with Eq. 3).
+ *    dtau_gamma/dt = A h_pair(chi_gamma)/gamma_gamma for gamma_gamma > 2.
+ *    At the event the photon is deleted and an e- e+ pair is created at its
+ *    position; chi_- from P_pm(0 -> chi_-) = xi'', chi_+ = chi_gamma - chi_-.
+ *    READING: energies gamma_pm = 1 + (gamma_gamma - 2) chi_pm/chi_gamma
+ *    (total energy conserved), momenta along k_hat; the pair is stored at
+ *    level n+1 (x^n + dt v_pm) and inherits the photon weight.
+ * ======================================================================== */
+int or_pair_create(const or_tables *tab, const or_units *un,
+                   or_species *P, const or_field *f,
+                   or_species *Em, or_species *Ep,
+                   const or_step *st, uint64_t *uid_next,
+                   double *tally, int64_t *count)
+{
+    const double dt = st->dt, A = un->A_hat;
+    int overflow = 0;
+    int64_t keep = 0;
+    for (int64_t j = 0; j < P->n; ++j) {
+        double x[3] = { P->x[j], P->y[j], P->z[j] };
+        double k[3] = { P->ux[j], P->uy[j], P->uz[j] };
+        double E[3], B[3];
+        or_field_at(f, st->t, x[0], x[1], x[2], E, B);
+        double kk = sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+        double chig = chi_generic(un->Es_hat, kk, k, E, B);
+        int oor = 0;
+        double W = (kk > 2.0) ? A * or_lookup_h_pair(tab, chig, &oor) / kk : 0.0;
+        if (oor) count[OR_C_RANGE]++;
+        count[OR_C_PHSTEP]++;
+        double tau = P->tau[j] - W * dt;
+        double kh[3] = { k[0] / kk, k[1] / kk, k[2] / kk };
+        if (W > 0.0 && tau <= 0.0) {
+            uint64_t o[4];
+            draw(st->seed, P->uid[j], P->n_ev[j], OR_RNG_PAIR, o);
+            double eta = or_sample_eta(tab, chig, or_u01(o[0]));
+            double chim = eta * chig;
+            double chip = chig - chim;
+            double gmn = 1.0 + (kk - 2.0) * (chim / chig);
+            double gpl = 1.0 + (kk - 2.0) * (chip / chig);
+            double pm = sqrt(gmn * gmn - 1.0), pp = sqrt(gpl * gpl - 1.0);
+            double wgt = P->w[j];
+            count[OR_C_PAIR]++;
+            tally[OR_T_EPAIR] += wgt * kk;
+            for (int side = 0; side < 2; ++side) {
+                or_species *D = side == 0 ? Em : Ep;
+                double pmag = side == 0 ? pm : pp, gmag = side == 0 ? gmn : gpl;
+                uint64_t nid = (*uid_next)++;
+                if (append_ok(D)) {
+                    int64_t m = D->n++;
+                    double ux = pmag * kh[0], uy = pmag * kh[1], uz = pmag * kh[2];
+                    D->x[m] = x[0] + dt * (ux / gmag);
+                    D->y[m] = x[1] + dt * (uy / gmag);
+                    D->z[m] = x[2] + dt * (uz / gmag);
+                    D->ux[m] = ux; D->uy[m] = uy; D->uz[m] = uz;
+                    D->w[m] = wgt;
+                    if (D->chi) D->chi[m] = side == 0 ? chim : chip;
+                    D->uid[m] = nid;
+                    D->n_ev[m] = 0;
+                    D->tau[m] = initial_tau(st->seed, nid);
+                } else {
+                    overflow = 1; count[OR_C_OVERFLOW]++;
+                }
+            }
+            continue;  /* photon deleted */
+        }
+        /* survivor: straight line at c, stable compaction in place */
+        P->x[keep] = x[0] + dt * kh[0];
+        P->y[keep] = x[1] + dt * kh[1];
+        P->z[keep] = x[2] + dt * kh[2];
+        P->ux[keep] = k[0]; P->uy[keep] = k[1]; P->uz[keep] = k[2];
+        P->tau[keep] = tau;
+        P->w[keep] = P->w[j];
+        P->chi[keep] = P->chi[j];
+        P->uid[keep] = P->uid[j];
+        P->n_ev[keep] = P->n_ev[j];
+        ++keep;
+    }
+    P->n = keep;
+    return overflow;
+}

@@ -1,0 +1,164 @@
+"""Seeded synthetic inputs: initial particles and external laser fields.
+
+This module holds no arithmetic of the radiation/QED step itself.  It draws
+the initial super-particles (positions, momenta, weights, ids) and describes
+the external field (plane-wave parameters, or the separable factors of a
+focused pulse sampled on a Yee grid).  Both the HIP path and the CPU oracle
+take its arrays as input; nothing here depends on either of them.
+
+The paper's own runs (laser-electron collisions, Sec. 1, and a constant-field
+test, Sec. 4) used no public dataset; these generators stand in for them.
+
+Normalised units: time 1/omega_r, length c/omega_r (lambda = 2 pi),
+momentum m c, fields m c omega_r/e.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+LAMBDA_M = 0.8e-6                   # reference wavelength [m]
+TWO_PI = 2.0 * math.pi
+LAM = TWO_PI                        # one wavelength in c/omega_r
+DT = TWO_PI / 100.0                 # T/100
+OMEGA_R = TWO_PI * 299792458.0 / LAMBDA_M
+
+
+@dataclass
+class PlaneWave:
+    """a_y(phi) = a0 sin^2(pi phi/Phi) sin(phi), phi = t - x, Phi = 2 pi n_periods."""
+    a0: float
+    n_periods: float = 10.0
+
+
+@dataclass
+class YeePulse:
+    """Focused pulse on a Yee grid, value[c,i,j,k] = a0 * tperp[c,j,k] * tpar[step,c,i]."""
+    shape: tuple
+    spacing: tuple
+    origin: tuple
+    a0: float
+    tperp: np.ndarray           # [6, ny*nz] float64
+    tpar: np.ndarray            # [steps, 6, nx] float64
+
+
+@dataclass
+class Workload:
+    name: str
+    electrons: dict             # x y z ux uy uz w uid (float64 / uint64)
+    field: object
+    steps: int
+    dt: float = DT
+    seed: int = 1
+    push_photons: bool = False
+    chi_photon_push_min: float = 1e-3
+    record_photons: bool = True
+    extra: dict = field(default_factory=dict)
+
+
+def _electrons(x, y, z, ux, uy, uz):
+    n = len(x)
+    return {"x": x.astype(np.float64), "y": y.astype(np.float64), "z": z.astype(np.float64),
+            "ux": ux.astype(np.float64), "uy": uy.astype(np.float64), "uz": uz.astype(np.float64),
+            "w": np.ones(n, np.float64), "uid": np.arange(n, dtype=np.uint64)}
+
+
+def beam_in_box(n: int, gamma0: float, spread: float, rng: np.random.Generator,
+                box: float = 20.0 * LAM):
+    """Electrons uniform in [0, box)^3 moving along -x, |u| = gamma0 (1 + spread N(0,1))."""
+    x = rng.uniform(0.0, box, n)
+    y = rng.uniform(0.0, box, n)
+    z = rng.uniform(0.0, box, n)
+    ux = -gamma0 * (1.0 + spread * rng.standard_normal(n))
+    zero = np.zeros(n)
+    return _electrons(x, y, z, ux, zero, zero.copy())
+
+
+def plane_wave_beam(n=100_000, a0=100.0, gamma0=2000.0, spread=0.01, steps=1000, seed=1,
+                    name="plane-wave beam") -> Workload:
+    """1e5 electrons, gamma0 2000 (1 % spread) against an a0 = 100 plane wave, 1000 steps."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return Workload(name, beam_in_box(n, gamma0, spread, rng), PlaneWave(a0), steps, seed=seed)
+
+
+def cascade_beam(n=50_000_000, a0=1000.0, gamma0=1.0e4, steps=500, seed=5) -> Workload:
+    """5e7 electrons, gamma0 1e4 (1 % spread), a0 = 1000 plane wave, 500 steps."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    w = Workload("high-chi cascade", beam_in_box(n, gamma0, 0.01, rng), PlaneWave(a0), steps,
+                 seed=seed, push_photons=True, chi_photon_push_min=0.2, record_photons=False)
+    return w
+
+
+def bunches(n_bunches=64, seed=4, scale=1.0, lo=3.0, hi=6.0):
+    """Independent bunches: sizes round(10^U(lo,hi)) (times scale), a0 ~ U(50,500),
+    gamma0 ~ U(500,5000), each in the plane-wave geometry."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sizes = np.maximum(1, np.round(10.0 ** rng.uniform(lo, hi, n_bunches) * scale)).astype(np.int64)
+    a0s = rng.uniform(50.0, 500.0, n_bunches)
+    g0s = rng.uniform(500.0, 5000.0, n_bunches)
+    parts = [beam_in_box(int(s), float(g), 0.01, rng) for s, g in zip(sizes, g0s)]
+    out = {k: np.concatenate([p[k] for p in parts]) for k in parts[0]}
+    out["uid"] = np.arange(len(out["x"]), dtype=np.uint64)
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    return out, offsets, a0s, g0s
+
+
+# --------------------------------------------------------------------------
+# focused pulse on a Yee grid
+# --------------------------------------------------------------------------
+YEE_STAGGER = np.array([[0.5, 0.0, 0.0], [0.0, 0.5, 0.0], [0.0, 0.0, 0.5],
+                        [0.0, 0.5, 0.5], [0.5, 0.0, 0.5], [0.5, 0.5, 0.0]])
+
+
+def yee_pulse(steps: int, shape=(256, 128, 128), cells_per_lambda=8, a0=200.0, w0_lambda=3.0,
+              fwhm_fs=30.0, x_center0=0.0, dt=DT) -> YeePulse:
+    """Non-diffracting Gaussian pulse polarised along y, moving along +x:
+    E_y = B_z = a0 exp(-(y^2+z^2)/w0^2) exp(-2 ln2 (s/tau)^2) cos(s), s = x - t - x_c0,
+    tau = intensity FWHM in 1/omega_r.  Box x in [0, nx dx), y, z centred on 0."""
+    nx, ny, nz = shape
+    d = LAM / cells_per_lambda
+    origin = (0.0, -0.5 * ny * d, -0.5 * nz * d)
+    w0 = w0_lambda * LAM
+    tau = fwhm_fs * 1e-15 * OMEGA_R
+    tperp = np.zeros((6, ny * nz))
+    tpar = np.zeros((steps, 6, nx))
+    for c in (1, 5):                                   # E_y and B_z
+        yy = origin[1] + (np.arange(ny) + YEE_STAGGER[c, 1]) * d
+        zz = origin[2] + (np.arange(nz) + YEE_STAGGER[c, 2]) * d
+        tperp[c] = np.exp(-(yy[:, None] ** 2 + zz[None, :] ** 2) / w0 ** 2).ravel()
+        xx = origin[0] + (np.arange(nx) + YEE_STAGGER[c, 0]) * d
+        t = np.arange(steps)[:, None] * dt
+        s = xx[None, :] - t - x_center0
+        tpar[:, c, :] = np.exp(-2.0 * math.log(2.0) * (s / tau) ** 2) * np.cos(s)
+    return YeePulse(shape, (d, d, d), origin, a0, tperp, tpar)
+
+
+def yee_beam(n=10_000_000, steps=2000, seed=2, shape=(256, 128, 128), a0=200.0) -> Workload:
+    """1e7 electrons, ln gamma0 ~ N(ln 2000, 0.3^2), uniform in the cylinder r <= 2 lambda,
+    x in [20, 28) lambda, moving along -x; sorted by grid cell (as a PIC code keeps them)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pulse = yee_pulse(steps, shape=shape, a0=a0)
+    d = pulse.spacing[0]
+    x = rng.uniform(20.0 * LAM, 28.0 * LAM, n)
+    r = 2.0 * LAM * np.sqrt(rng.uniform(0.0, 1.0, n))
+    th = rng.uniform(0.0, TWO_PI, n)
+    y, z = r * np.cos(th), r * np.sin(th)
+    g = np.exp(math.log(2000.0) + 0.3 * rng.standard_normal(n))
+    ux = -np.sqrt(g * g - 1.0)
+    ci = np.floor((x - pulse.origin[0]) / d).astype(np.int64)
+    cj = np.floor((y - pulse.origin[1]) / d).astype(np.int64)
+    ck = np.floor((z - pulse.origin[2]) / d).astype(np.int64)
+    order = np.lexsort((ck, cj, ci))
+    zero = np.zeros(n)
+    e = _electrons(x[order], y[order], z[order], ux[order], zero, zero.copy())
+    return Workload("Yee-grid focused pulse", e, pulse, steps, seed=seed, push_photons=True,
+                    chi_photon_push_min=1e-3, record_photons=True)
+
+
+def subset(wl: Workload, idx) -> Workload:
+    """The same workload restricted to the electrons idx (uids kept)."""
+    e = {k: v[idx].copy() for k, v in wl.electrons.items()}
+    return Workload(wl.name + " (subset)", e, wl.field, wl.steps, wl.dt, wl.seed,
+                    wl.push_photons, wl.chi_photon_push_min, wl.record_photons, dict(wl.extra))
