@@ -273,9 +273,18 @@ static void pair_panels(double chi, panels *p)
     p->n = np;
 }
 
+/* Mass of the emission integrand below the first panel edge s0.  For s -> -inf,
+ * xi ~ e^s and K_{2/3}(delta) ~ (Gamma(2/3)/2)(2/delta)^{2/3}, so
+ * emit_f(s) = C e^{s/3} (1 + O(e^{2s/3})) and the tail equals 3 emit_f(s0) up
+ * to a relative O(e^{2 s0/3}).  The pair integrand has no such tail. */
+static double lower_tail(spec_fn f, double chi, double s0)
+{
+    return (f == emit_f) ? 3.0 * emit_f(chi, s0) : 0.0;
+}
+
 static double spec_total(spec_fn f, double chi, const panels *p, int moment)
 {
-    double sum = 0.0;
+    double sum = moment ? 0.0 : lower_tail(f, chi, p->edge[0]);
     for (int k = 0; k < p->n; ++k) sum += gl_panel(f, chi, p->edge[k], p->edge[k + 1], moment);
     return sum;
 }
@@ -306,7 +315,7 @@ double or_h_pair(double chi_g)
 
 static double cdf_generic(spec_fn f, double chi, const panels *p, double s_target)
 {
-    double num = 0.0, tot = 0.0;
+    double num = lower_tail(f, chi, p->edge[0]), tot = num;
     for (int k = 0; k < p->n; ++k) {
         double a = p->edge[k], b = p->edge[k + 1];
         double full = gl_panel(f, chi, a, b, 0);
@@ -387,10 +396,11 @@ static void quantile_row(spec_fn f, double chi, const panels *p, int n_q,
     double *lo = (double *)malloc(sizeof(double) * (p->n + 1));
     double *hi = (double *)malloc(sizeof(double) * (p->n + 1));
     for (int k = 0; k < p->n; ++k) pi[k] = gl_panel(f, chi, p->edge[k], p->edge[k + 1], 0);
-    lo[0] = 0.0;
+    lo[0] = lower_tail(f, chi, p->edge[0]);
     for (int k = 0; k < p->n; ++k) lo[k + 1] = lo[k] + pi[k];
     hi[p->n] = 0.0;
     for (int k = p->n - 1; k >= 0; --k) hi[k] = hi[k + 1] + pi[k];
+    hi[0] += lo[0];
     for (int q = 0; q < n_q; ++q) {
         double t = -logit_max + 2.0 * logit_max * q / (n_q - 1);
         double total = (t > 0.0) ? hi[0] : lo[p->n];
