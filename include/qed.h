@@ -1,0 +1,322 @@
+/*
+ * qed.h -- C interface of libqed, an MI355X (gfx950) implementation of the
+ * per-particle radiation and QED step of Lobet et al., "Modeling of radiative
+ * and quantum electrodynamics effects in PIC simulations of ultra-relativistic
+ * laser-plasma interaction" (arXiv:1311.1107).
+ *
+ * For every super-particle the step gathers E and B, computes the Lorentz
+ * invariant chi (Eq. 1) and advances the particle either with the Sokolov
+ * radiation-damped push (Eqs. 4-5) or with the optical-depth Monte Carlo
+ * (Eqs. 6-8), which emits super-photons; super-photons decay into e- e+ pairs
+ * by the same Monte Carlo over the pair spectrum (Eq. 3, Sec. 3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Units: time 1/omega_r, length c/omega_r, momentum m_e c, E in
+ *    m_e c omega_r/e, B in m_e omega_r/e, with omega_r = 2 pi c/lambda.
+ *  - Every call returns a qed_status: QED_OK (0) or a negative error code.
+ *    qed_last_error() returns a message for the calling host thread.
+ *    Nothing is thrown across this interface.
+ *  - Pointers marked [device] are device memory of the current HIP device;
+ *    [host] pointers are host memory.  The caller owns all particle, field
+ *    and tally memory; the library owns only qed_tables and qed_workspace
+ *    handles.  Struct arguments themselves are host memory and are copied at
+ *    the call; they may be reused immediately.
+ *  - `stream` is a hipStream_t (NULL = legacy default stream).  Work is
+ *    enqueued asynchronously; particle counts live in device memory, so a
+ *    sequence of calls needs no host synchronisation and can be captured in
+ *    a HIP graph.  Errors detected on the device (append past capacity,
+ *    non-finite momenta, chi beyond the tables) are sticky in the workspace
+ *    and read with qed_sync_status().
+ *  - Particles are structure-of-arrays.  Within a launch, appended particles
+ *    keep the serial order of their parents (stable append), so results do
+ *    not depend on the launch configuration.
+ *  - Random numbers are Philox4x64-10 keyed by (seed, 0) with counter
+ *    (uid, n_event, purpose, 0): event decisions are reproducible for a given
+ *    seed whatever the launch configuration or particle order.
+ */
+#ifndef QED_H
+#define QED_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t qed_status;
+#define QED_OK            0
+#define QED_ERR_ARG      (-1)   /* invalid argument, detected on the host     */
+#define QED_ERR_HIP      (-2)   /* a HIP runtime call or launch failed          */
+#define QED_ERR_CAPACITY (-3)   /* an append did not fit (device, sticky)       */
+#define QED_ERR_RANGE    (-4)   /* non-finite state met on the device (sticky)  */
+#define QED_ERR_NOMEM    (-5)   /* allocation failed                            */
+
+const char *qed_last_error(void);
+
+/* ------------------------------------------------------------------------ *
+ * Units (Sec. 2 definitions of E_s, alpha_f, tau_c; tau_0 after Eq. 4).
+ * Es_hat = E_s in units of m c omega_r/e, A_hat = alpha_f/(tau_c omega_r)
+ * (the rate prefactor of Eqs. 2, 3 and 6), tau0_hat = tau_0 omega_r.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    double lambda;     /* [m]                                              */
+    double omega_r;    /* [1/s]                                            */
+    double alpha_f;
+    double Es_hat;
+    double A_hat;
+    double tau0_hat;
+} qed_units;
+
+/* CODATA 2018 constants for the reference wavelength lambda_m [m] > 0. */
+qed_status qed_units_init(double lambda_m, qed_units *out /* [host] */);
+
+/* ------------------------------------------------------------------------ *
+ * Rate and quantile tables (Eqs. 2, 3, 5, 6, 7 and the pair CDF of Sec. 3).
+ *
+ * Emission tables at n_chi log-spaced chi_e in [chi_min, chi_max]:
+ *   ln_hrad[i]  = ln h_rad(chi_i), dN_gamma/dt = alpha_f h_rad/(tau_c gamma)
+ *   ln_g[i]     = ln g(chi_i), P_rad = (2/3) alpha_f m c^2 chi^2 g/tau_c
+ *   emit_q[i][k]= ln xi at CDF level r_k of Eq. 7 (xi = chi_gamma/chi_e),
+ *                 r_k = 1/(1+exp(-t_k)), t_k = -L + 2 L k/(n_q-1), L = logit_max
+ * Pair tables at n_chi log-spaced chi_gamma:
+ *   pair_lnh[i] = ln h_pair(chi_i) + 8/(3 chi_i),
+ *                 dN_pm/dt = alpha_f h_pair/(tau_c gamma_gamma)
+ *   pair_q[i][k]= logit eta at level r_k of the pair CDF (eta = chi_-/chi_gamma)
+ * Arrays are row-major, FP64.  Limits: 2 <= n_chi <= 256, 2 <= n_q <= 256,
+ * 0 < chi_min < chi_max, logit_max > 0.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    double chi_min, chi_max;
+    int32_t n_chi, n_q;
+    double logit_max;
+} qed_table_spec;
+
+typedef struct qed_tables qed_tables;          /* immutable device-resident tables */
+
+/* FP64 Bessel quadrature on the host (multithreaded) into host arrays sized
+ * n_chi, n_chi, n_chi*n_q (emission) and n_chi, n_chi*n_q (pair). */
+qed_status qed_tables_compute_host(const qed_table_spec *emit, const qed_table_spec *pair,
+                                   double *ln_hrad, double *ln_g, double *emit_q,
+                                   double *pair_lnh, double *pair_q);
+/* qed_tables_compute_host followed by upload to the current device. */
+qed_status qed_tables_build(const qed_table_spec *emit, const qed_table_spec *pair,
+                            qed_tables **out);
+/* Upload tables given as host arrays (same layout as above), e.g. a saved set. */
+qed_status qed_tables_load(const qed_table_spec *emit, const qed_table_spec *pair,
+                           const double *ln_hrad, const double *ln_g, const double *emit_q,
+                           const double *pair_lnh, const double *pair_q, qed_tables **out);
+/* Copy one table back to the host: which = 0 ln_hrad, 1 ln_g, 2 emit_q,
+ * 3 pair_lnh, 4 pair_q; n must equal its element count. */
+qed_status qed_tables_export(const qed_tables *t, int32_t which, double *host, size_t n);
+void qed_tables_free(qed_tables *t);
+
+/* ------------------------------------------------------------------------ *
+ * Particles (super-particles of Sec. 3), structure of arrays.
+ * prec selects the element type of x..uz, w and chi: QED_F64 (double) or
+ * QED_F32 (float).  tau is always FP64 (optical depth left before the next
+ * event, tau^f - tau of Eq. 6).  For photons u holds k with |k| = gamma_gamma
+ * and chi the chi_gamma at creation; for leptons chi may be NULL.
+ * A photon whose tau is +INFINITY has decayed; qed_compact() removes it.
+ * ------------------------------------------------------------------------ */
+enum { QED_F64 = 0, QED_F32 = 1 };
+
+typedef struct {
+    int32_t prec;
+    int32_t reserved;
+    void *x, *y, *z;          /* [device] positions                              */
+    void *ux, *uy, *uz;       /* [device] u = p/(m c)                            */
+    double *tau;              /* [device]                                        */
+    void *w;                  /* [device] weight                                 */
+    void *chi;                /* [device] or NULL (leptons)                      */
+    uint64_t *uid;            /* [device] unique id (Philox counter word 0)      */
+    uint32_t *n_event;        /* [device] events so far (Philox counter word 1)  */
+    int64_t *d_count;         /* [device] number of live entries                 */
+    int64_t capacity;         /* [host] allocated entries                        */
+} qed_species;
+
+/* Sec. 3: initial optical depth tau^f = -log xi for entries [0, *d_count). */
+qed_status qed_init_optical_depth(qed_species *s, uint64_t seed, void *stream);
+
+/* ------------------------------------------------------------------------ *
+ * External fields at the particles.
+ *  UNIFORM:    E, B constant (the constant-field test of Sec. 4).
+ *  PLANE_WAVE: linearly polarised along y, moving along +x, from the vector
+ *              potential a_y = a0 sin^2(pi phi/Phi) sin(phi), phi = t - x,
+ *              Phi = 2 pi n_periods: E_y = B_z = -da_y/dphi.
+ *  YEE:        FP32 grid of 6 components Ex Ey Ez Bx By Bz, each [nx][ny][nz]
+ *              (z fastest) on Yee staggered positions, gathered with quadratic
+ *              (TSC) weights; zero outside the grid.
+ * ------------------------------------------------------------------------ */
+enum { QED_FIELD_UNIFORM = 0, QED_FIELD_PLANE_WAVE = 1, QED_FIELD_YEE = 2 };
+
+typedef struct {
+    int32_t kind;
+    int32_t reserved;
+    double E[3], B[3];
+    double a0, n_periods;
+    const float *grid;        /* [device] 6*nx*ny*nz floats                     */
+    int64_t nx, ny, nz;
+    double dx, dy, dz, x0, y0, z0;
+} qed_field;
+
+/* Separable pulse onto the Yee grid: grid[c][i][j][k] =
+ * (float)((a0 * tperp[c][j*nz+k]) * tpar[c][i]), tperp [device] 6*ny*nz,
+ * tpar [device] 6*nx FP64. */
+qed_status qed_yee_fill_separable(float *grid, int64_t nx, int64_t ny, int64_t nz, double a0,
+                                  const double *tperp, const double *tpar, void *stream);
+
+/* ------------------------------------------------------------------------ *
+ * Step parameters.
+ *  rad_model: NONE (Lorentz force only), SOKOLOV (Eqs. 4-5 for everyone),
+ *  MC (Eqs. 6-8 for everyone), HYBRID (Sokolov where chi_e < chi_switch,
+ *  Monte Carlo elsewhere: the classical and quantum regimes of Sec. 2).
+ *  Emitted photons with gamma_gamma <= gamma_photon_min are not created
+ *  (energy tallied; the paper's 2 m c^2 threshold, Sec. 3).  Created photons
+ *  go to the pushed buffer if chi_gamma > chi_photon_push_min and that buffer
+ *  is given, else to the recorded buffer if given, else are tallied only.
+ *  max_events (1..4) bounds the emissions per particle and step.
+ *  If d_step is not NULL the time is t + (*d_step) * dt (graph replays).
+ * ------------------------------------------------------------------------ */
+enum { QED_RAD_NONE = 0, QED_RAD_SOKOLOV = 1, QED_RAD_MC = 2, QED_RAD_HYBRID = 3 };
+
+typedef struct {
+    double t, dt;
+    uint64_t seed;
+    int32_t rad_model;
+    int32_t max_events;
+    double chi_switch;
+    double gamma_photon_min;
+    double chi_photon_push_min;
+    int32_t no_recoil;        /* test switch: emit without recoil (frozen chi) */
+    int32_t reserved;
+    const int64_t *d_step;    /* [device] or NULL                               */
+} qed_step;
+
+/* ------------------------------------------------------------------------ *
+ * Tallies: FP64 energies (m c^2 x weight), accumulated per tile slot so that
+ * the sums are reproducible, and integer event counts (one set; integer sums
+ * do not depend on order).  qed_tally_reduce() adds the energy slots in
+ * slot order.
+ * energy: 0 field work on leptons, 1 Sokolov radiated, 2 photons pushed,
+ *   3 photons recorded, 4 photons tallied only, 5 below gamma_photon_min,
+ *   6 photons converted to pairs.
+ * count: 0 emissions, 1 pushed, 2 recorded, 3 tallied only, 4 below
+ *   threshold, 5 max_events cap hit, 6 chi above table, 7 Sokolov steps,
+ *   8 Monte Carlo steps, 9 pairs, 10 photon steps, 11 non-finite, 12 lost
+ *   to capacity.
+ * ------------------------------------------------------------------------ */
+#define QED_N_ENERGY 8
+#define QED_N_COUNT 16
+typedef struct {
+    double *energy;           /* [device] n_slots * QED_N_ENERGY, zeroed by caller */
+    int64_t *count;           /* [device] QED_N_COUNT, zeroed by caller              */
+    int64_t n_slots;          /* [host] >= 1; reproducible sums need >= tiles/launch */
+} qed_tally;
+
+qed_status qed_tally_reduce(const qed_tally *t, double energy[QED_N_ENERGY] /* [host] */,
+                            int64_t count[QED_N_COUNT] /* [host] */, void *stream);
+
+/* ------------------------------------------------------------------------ *
+ * Workspace: tile-status words of the decoupled look-back used for stable
+ * appends, launch tickets and the sticky device status.  One workspace per
+ * stream; calls sharing a workspace must not overlap in time.
+ * ------------------------------------------------------------------------ */
+typedef struct qed_workspace qed_workspace;
+
+qed_status qed_workspace_create(int64_t max_particles, qed_workspace **out);
+void qed_workspace_free(qed_workspace *ws);
+
+typedef struct {
+    int64_t flags;            /* bit 0 capacity, bit 1 non-finite, bit 2 tally slots */
+    int64_t needed[4];        /* largest count requested: photons pushed, photons
+                                 recorded, electrons, positrons                    */
+    int64_t chi_above_table;  /* lookups above the table's chi range              */
+} qed_status_report;
+
+/* Synchronises `stream`, copies the sticky status out, returns QED_OK,
+ * QED_ERR_CAPACITY or QED_ERR_RANGE accordingly and clears it if clear != 0. */
+qed_status qed_sync_status(qed_workspace *ws, qed_status_report *out /* [host] */,
+                           int32_t clear, void *stream);
+
+/* Launch shape of the persistent kernels: threads per block (64..1024,
+ * multiple of 64), particles per thread (1, 2 or 4), and blocks per compute
+ * unit.  Zero fields take the library defaults. */
+typedef struct {
+    int32_t block;
+    int32_t items_per_thread;
+    int32_t blocks_per_cu;
+    int32_t reserved;
+} qed_schedule;
+
+/* ------------------------------------------------------------------------ *
+ * One step of the leptons of `charge` (-1 electrons, +1 positrons), Secs. 2-3:
+ * field at x^n, Lorentz push to u^{n+1/2}, chi_e (Eq. 1), Sokolov (Eqs. 4-5)
+ * or optical-depth Monte Carlo emission (Eqs. 6-8) with photon appends, then
+ * x^{n+1}.  New photons are stored at level n+1 (x^n + dt k_hat), with
+ * k = gamma_gamma u_hat (collinear emission, Sec. 3) and ids from *d_uid_next.
+ * ph_push / ph_rec may be NULL.  sched may be NULL.
+ * ------------------------------------------------------------------------ */
+qed_status qed_push_emit(const qed_tables *tab, qed_workspace *ws, const qed_units *u,
+                         double charge, qed_species *lep, const qed_field *f,
+                         qed_species *ph_push, qed_species *ph_rec, qed_tally *tally,
+                         const qed_step *st, uint64_t *d_uid_next /* [device] */,
+                         const qed_schedule *sched, void *stream);
+
+/* One step of pushed photons (Sec. 3 with Eq. 3): chi_gamma, optical depth
+ * against the pair rate, decay into an e- e+ pair at the photon's position
+ * (chi_- from the pair CDF, chi_+ = chi_gamma - chi_-, energies
+ * 1 + (gamma_gamma - 2) chi_pm/chi_gamma along k_hat), straight-line push of
+ * the others.  Decayed photons get tau = +INFINITY (see qed_compact). */
+qed_status qed_pair_create(const qed_tables *tab, qed_workspace *ws, const qed_units *u,
+                           qed_species *ph, const qed_field *f, qed_species *elec,
+                           qed_species *posi, qed_tally *tally, const qed_step *st,
+                           uint64_t *d_uid_next /* [device] */, const qed_schedule *sched,
+                           void *stream);
+
+/* Stable in-place removal of decayed photons (tau == +INFINITY). */
+qed_status qed_compact(qed_workspace *ws, qed_species *ph, const qed_schedule *sched,
+                       void *stream);
+
+/* ------------------------------------------------------------------------ *
+ * Batched form: many independent bunches, concatenated in `lep`, each in its
+ * own plane wave, advanced by one persistent launch.  offsets [device] has
+ * n_bunches+1 entries (bunch b is [offsets[b], offsets[b+1])), a0 and
+ * n_periods [device] one per bunch; *lep->d_count must equal offsets[n_bunches].
+ * Appends follow bunch order, then particle order.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n_bunches;
+    int32_t reserved;
+    const int64_t *offsets;   /* [device] */
+    const double *a0;         /* [device] */
+    const double *n_periods;  /* [device] */
+} qed_bunches;
+
+qed_status qed_push_emit_batched(const qed_tables *tab, qed_workspace *ws, const qed_units *u,
+                                 double charge, qed_species *lep, const qed_bunches *b,
+                                 qed_species *ph_push, qed_species *ph_rec, qed_tally *tally,
+                                 const qed_step *st, uint64_t *d_uid_next,
+                                 const qed_schedule *sched, void *stream);
+
+/* Autotuner: times each candidate schedule of qed_push_emit_batched over
+ * `trial_steps` steps on a scratch copy of the lepton state (the caller's
+ * particles, counters and tallies are left as they were) and returns the
+ * fastest in *best.  candidates [host] has n_candidates entries; if cache_path
+ * is not NULL, a result stored there for the same problem is reused and a new
+ * one is written. */
+qed_status qed_autotune_batched(const qed_tables *tab, qed_workspace *ws, const qed_units *u,
+                                double charge, qed_species *lep, const qed_bunches *b,
+                                qed_species *ph_rec, const qed_step *st,
+                                const qed_schedule *candidates, int32_t n_candidates,
+                                int32_t trial_steps, const char *cache_path,
+                                qed_schedule *best, double *best_ms, void *stream);
+
+/* Advance a device step counter by one (for graph-captured step sequences). */
+qed_status qed_step_advance(int64_t *d_step, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

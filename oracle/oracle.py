@@ -24,7 +24,7 @@ HDR = os.path.join(HERE, "qed_oracle.h")
 LIB = os.path.join(HERE, "libqed_oracle.so")
 
 RAD_NONE, RAD_SOKOLOV, RAD_MC, RAD_HYBRID = 0, 1, 2, 3
-FIELD_UNIFORM, FIELD_PLANE_WAVE, FIELD_YEE = 0, 1, 2
+FIELD_UNIFORM, FIELD_PLANE_WAVE, FIELD_YEE, FIELD_YEE_SEPARABLE = 0, 1, 2, 3
 RNG_EMIT, RNG_PAIR, RNG_INIT = 1, 2, 3
 
 T_NAMES = ["work", "erad", "epush", "erec", "edrop", "esub", "epair", "_t7"]
@@ -82,7 +82,8 @@ class Species(C.Structure):
 class Field(C.Structure):
     _fields_ = [("kind", C.c_int32), ("E", C.c_double * 3), ("B", C.c_double * 3),
                 ("a0", C.c_double), ("n_periods", C.c_double),
-                ("grid", _fp * 6), ("nx", C.c_int64), ("ny", C.c_int64), ("nz", C.c_int64),
+                ("grid", _fp * 6), ("tperp6", _dp), ("tpar6", _dp),
+                ("nx", C.c_int64), ("ny", C.c_int64), ("nz", C.c_int64),
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
                 ("x0", C.c_double), ("y0", C.c_double), ("z0", C.c_double)]
 
@@ -138,7 +139,7 @@ def lib():
                                    C.POINTER(Field), C.POINTER(Species), C.POINTER(Species),
                                    C.POINTER(Step), _u64p, _dp, C.POINTER(C.c_int64)]
         L.or_push_emit.restype = C.c_int
-        L.or_pair_create.argtypes = [C.POINTER(Tables), C.POINTER(Units), C.POINTER(Species),
+        L.or_pair_create.argtypes = [C.POINTER(Tables), C.POINTER(Units), C.POINTER(Species), C.c_int64,
                                      C.POINTER(Field), C.POINTER(Species), C.POINTER(Species),
                                      C.POINTER(Step), _u64p, _dp, C.POINTER(C.c_int64)]
         L.or_pair_create.restype = C.c_int
@@ -340,7 +341,7 @@ def init_tau(s: dict, seed: int):
 
 
 def make_field(kind, E=(0, 0, 0), B=(0, 0, 0), a0=0.0, n_periods=10.0, grid=None,
-               shape=(0, 0, 0), spacing=(1, 1, 1), origin=(0, 0, 0)):
+               shape=(0, 0, 0), spacing=(1, 1, 1), origin=(0, 0, 0), tperp=None, tpar=None):
     f = Field()
     f.kind = kind
     f.E = (C.c_double * 3)(*E)
@@ -353,6 +354,11 @@ def make_field(kind, E=(0, 0, 0), B=(0, 0, 0), a0=0.0, n_periods=10.0, grid=None
         per = g6.reshape(6, -1)
         for c in range(6):
             f.grid[c] = per[c].ctypes.data_as(_fp)
+    if tperp is not None:
+        tp = np.ascontiguousarray(tperp, dtype=np.float64)
+        tq = np.ascontiguousarray(tpar, dtype=np.float64)
+        keep += [tp, tq]
+        f.tperp6, f.tpar6 = _ptr(tp), _ptr(tq)
     f.nx, f.ny, f.nz = shape
     f.dx, f.dy, f.dz = spacing
     f.x0, f.y0, f.z0 = origin
@@ -425,11 +431,12 @@ def push_emit(tabs: BoundTables, lambda_m, charge, lep: dict, field: Field,
 
 
 def pair_create(tabs: BoundTables, lambda_m, ph: dict, field: Field, elec: dict, posi: dict,
-                step: Step, uid_next: list, tally: Tally) -> int:
+                step: Step, uid_next: list, tally: Tally, n_limit: int | None = None) -> int:
     U = _units_struct(lambda_m)
     P, Em, Ep = _species_struct(ph), _species_struct(elec), _species_struct(posi)
     un = (C.c_uint64 * 1)(uid_next[0])
-    rc = lib().or_pair_create(C.byref(tabs.t), C.byref(U), C.byref(P), C.byref(field),
+    lim = int(ph["n"]) if n_limit is None else int(n_limit)
+    rc = lib().or_pair_create(C.byref(tabs.t), C.byref(U), C.byref(P), lim, C.byref(field),
                               C.byref(Em), C.byref(Ep), C.byref(step), un, _ptr(tally.t),
                               tally.c.ctypes.data_as(C.POINTER(C.c_int64)))
     uid_next[0] = int(un[0])

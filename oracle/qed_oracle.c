@@ -628,7 +628,7 @@ void or_field_at(const or_field *f, double t, double x, double y, double z,
             E[1] = -da;
             B[2] = -da;
         }
-    } else if (f->kind == OR_FIELD_YEE) {
+    } else if (f->kind == OR_FIELD_YEE || f->kind == OR_FIELD_YEE_SEPARABLE) {
         double out[6];
         for (int c = 0; c < 6; ++c) {
             int64_t i0, j0, k0;
@@ -646,7 +646,12 @@ void or_field_at(const or_field *f, double t, double x, double y, double z,
                     for (int cc = 0; cc < 3; ++cc) {
                         int64_t k = k0 - 1 + cc;
                         if (k < 0 || k >= f->nz) continue;
-                        double v = (double)f->grid[c][(i * f->ny + j) * f->nz + k];
+                        double v;
+                        if (f->kind == OR_FIELD_YEE)
+                            v = (double)f->grid[c][(i * f->ny + j) * f->nz + k];
+                        else   /* the node value the separable fill would store */
+                            v = (double)(float)((f->a0 * f->tperp6[c * f->ny * f->nz + j * f->nz + k])
+                                                * f->tpar6[c * f->nx + i]);
                         acc += (wx[a] * wy[b]) * wz[cc] * v;
                     }
                 }
@@ -877,7 +882,7 @@ int or_push_emit(const or_tables *tab, const or_units *un, double q,
  *    level n+1 (x^n + dt v_pm) and inherits the photon weight.
  * ======================================================================== */
 int or_pair_create(const or_tables *tab, const or_units *un,
-                   or_species *P, const or_field *f,
+                   or_species *P, int64_t n_limit, const or_field *f,
                    or_species *Em, or_species *Ep,
                    const or_step *st, uint64_t *uid_next,
                    double *tally, int64_t *count)
@@ -885,7 +890,8 @@ int or_pair_create(const or_tables *tab, const or_units *un,
     const double dt = st->dt, A = un->A_hat;
     int overflow = 0;
     int64_t keep = 0;
-    for (int64_t j = 0; j < P->n; ++j) {
+    int64_t n_step = n_limit < P->n ? n_limit : P->n;
+    for (int64_t j = 0; j < n_step; ++j) {
         double x[3] = { P->x[j], P->y[j], P->z[j] };
         double k[3] = { P->ux[j], P->uy[j], P->uz[j] };
         double E[3], B[3];
@@ -943,6 +949,14 @@ int or_pair_create(const or_tables *tab, const or_units *un,
         P->uid[keep] = P->uid[j];
         P->n_ev[keep] = P->n_ev[j];
         ++keep;
+    }
+    /* photons created during this step (beyond n_limit) are first pushed at
+     * the next step; they keep their order behind the survivors */
+    for (int64_t j = n_step; j < P->n; ++j, ++keep) {
+        P->x[keep] = P->x[j]; P->y[keep] = P->y[j]; P->z[keep] = P->z[j];
+        P->ux[keep] = P->ux[j]; P->uy[keep] = P->uy[j]; P->uz[keep] = P->uz[j];
+        P->tau[keep] = P->tau[j]; P->w[keep] = P->w[j]; P->chi[keep] = P->chi[j];
+        P->uid[keep] = P->uid[j]; P->n_ev[keep] = P->n_ev[j];
     }
     P->n = keep;
     return overflow;

@@ -120,13 +120,14 @@ typedef struct {
     uint32_t *n_ev;                     /* events so far (Philox counter word)   */
 } or_species;
 
-enum { OR_FIELD_UNIFORM = 0, OR_FIELD_PLANE_WAVE = 1, OR_FIELD_YEE = 2 };
+enum { OR_FIELD_UNIFORM = 0, OR_FIELD_PLANE_WAVE = 1, OR_FIELD_YEE = 2, OR_FIELD_YEE_SEPARABLE = 3 };
 
 typedef struct {
     int32_t kind;
     double E[3], B[3];                 /* uniform field                           */
     double a0, n_periods;              /* plane wave a_y = a0 sin^2(pi phi/Phi) sin phi, phi = t - x */
     const float *grid[6];              /* Yee: Ex Ey Ez Bx By Bz, [i][j][k], k fastest */
+    const double *tperp6, *tpar6;      /* Yee separable: node value (float)((a0 tperp[c][j,k]) tpar[c][i]) */
     int64_t nx, ny, nz;
     double dx, dy, dz, x0, y0, z0;
 } or_field;
@@ -171,10 +172,12 @@ int or_push_emit(const or_tables *tab, const or_units *u, double q,
                  const or_step *st, uint64_t *uid_next,
                  double *tally, int64_t *count);
 
-/* One step of the pushed photons: Breit-Wheeler decay into pairs (Sec. 3),
- * straight-line push of the survivors and stable removal of decayed photons. */
+/* One step of the pushed photons [0, n_limit): Breit-Wheeler decay into pairs
+ * (Sec. 3), straight-line push of the survivors and stable removal of decayed
+ * photons.  Photons from n_limit on were created in the current step and are
+ * left as they are (moved down behind the survivors). */
 int or_pair_create(const or_tables *tab, const or_units *u,
-                   or_species *ph, const or_field *f,
+                   or_species *ph, int64_t n_limit, const or_field *f,
                    or_species *elec, or_species *posi,
                    const or_step *st, uint64_t *uid_next,
                    double *tally, int64_t *count);

@@ -1,0 +1,574 @@
+// qed_api.cpp -- the C interface declared in include/qed.h: argument checks,
+// handle management and kernel launches on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "qed.h"
+#include "qed_kernels.h"
+
+namespace qedtab {
+int build_tables(double e_chi_min, double e_chi_max, int e_n_chi, int e_n_q, double e_logit,
+                 double p_chi_min, double p_chi_max, int p_n_chi, int p_n_q, double p_logit,
+                 double *ln_hrad, double *ln_g, double *emit_q, double *pair_lnh, double *pair_q);
+}
+
+namespace {
+
+thread_local std::string g_err;
+
+qed_status fail(qed_status code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) return fail(QED_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+bool spec_ok(const qed_table_spec *s) {
+    return s && s->n_chi >= 2 && s->n_chi <= qed::kMaxChiNodes && s->n_q >= 2 && s->n_q <= 256 &&
+           s->chi_min > 0.0 && s->chi_max > s->chi_min && std::isfinite(s->chi_max) && s->logit_max > 0.0;
+}
+
+}  // namespace
+
+struct qed_tables {
+    qed_table_spec emit, pair;
+    int device;
+    double *d64;      // ln_hrad | ln_g | emit_q | pair_lnh | pair_q
+    float *d32;
+    size_t off[6];    // element offsets of the five tables (and the total)
+    qed::TablesDev dev;
+};
+
+struct qed_workspace {
+    int device;
+    int n_cu;
+    int64_t max_tiles;
+    uint64_t *d_ticket;
+    uint64_t *d_lb;
+    unsigned long long *d_status;
+    qed::WsDev dev;
+};
+
+extern "C" {
+
+const char *qed_last_error(void) { return g_err.c_str(); }
+
+qed_status qed_units_init(double lambda_m, qed_units *out) {
+    if (!out || !(lambda_m > 0.0) || !std::isfinite(lambda_m)) return fail(QED_ERR_ARG, "qed_units_init: lambda must be > 0");
+    // CODATA 2018 (exact SI definitions for c, e, h; measured m_e and eps0)
+    const double c = 299792458.0, e = 1.602176634e-19, h = 6.62607015e-34;
+    const double me = 9.1093837015e-31, eps0 = 8.8541878128e-12;
+    const double hbar = h / (2.0 * qed::kPi);
+    out->lambda = lambda_m;
+    out->omega_r = 2.0 * qed::kPi * c / lambda_m;
+    out->alpha_f = e * e / (4.0 * qed::kPi * eps0 * hbar * c);
+    // E_s = m^2 c^3/(e hbar) over the field unit m c omega_r/e
+    out->Es_hat = (me * c * c) / (hbar * out->omega_r);
+    // alpha_f/(tau_c omega_r) with tau_c = hbar/(m c^2)
+    out->A_hat = out->alpha_f * me * c * c / (hbar * out->omega_r);
+    // tau_0 = 2 e^2/(12 pi eps0 m c^3)
+    out->tau0_hat = 2.0 * e * e / (12.0 * qed::kPi * eps0 * me * c * c * c) * out->omega_r;
+    return QED_OK;
+}
+
+// ------------------------------------------------------------------ tables --
+qed_status qed_tables_compute_host(const qed_table_spec *emit, const qed_table_spec *pair,
+                                   double *ln_hrad, double *ln_g, double *emit_q,
+                                   double *pair_lnh, double *pair_q) {
+    if (!spec_ok(emit) || !spec_ok(pair)) return fail(QED_ERR_ARG, "qed_tables_compute_host: invalid table spec");
+    if (!ln_hrad || !ln_g || !emit_q || !pair_lnh || !pair_q) return fail(QED_ERR_ARG, "qed_tables_compute_host: null output");
+    int rc = qedtab::build_tables(emit->chi_min, emit->chi_max, emit->n_chi, emit->n_q, emit->logit_max,
+                                  pair->chi_min, pair->chi_max, pair->n_chi, pair->n_q, pair->logit_max,
+                                  ln_hrad, ln_g, emit_q, pair_lnh, pair_q);
+    if (rc) return fail(QED_ERR_RANGE, "qed_tables_compute_host: non-finite table entry");
+    return QED_OK;
+}
+
+qed_status qed_tables_load(const qed_table_spec *emit, const qed_table_spec *pair,
+                           const double *ln_hrad, const double *ln_g, const double *emit_q,
+                           const double *pair_lnh, const double *pair_q, qed_tables **out) {
+    if (!out) return fail(QED_ERR_ARG, "qed_tables_load: null out");
+    *out = nullptr;
+    if (!spec_ok(emit) || !spec_ok(pair)) return fail(QED_ERR_ARG, "qed_tables_load: invalid table spec");
+    if (!ln_hrad || !ln_g || !emit_q || !pair_lnh || !pair_q) return fail(QED_ERR_ARG, "qed_tables_load: null input");
+    qed_tables *t = new qed_tables();
+    t->emit = *emit;
+    t->pair = *pair;
+    HIP_TRY(hipGetDevice(&t->device));
+    const size_t ne = emit->n_chi, nq = emit->n_q, np = pair->n_chi, npq = pair->n_q;
+    const size_t sizes[5] = {ne, ne, ne * nq, np, np * npq};
+    t->off[0] = 0;
+    for (int k = 0; k < 5; ++k) t->off[k + 1] = t->off[k] + sizes[k];
+    const double *src[5] = {ln_hrad, ln_g, emit_q, pair_lnh, pair_q};
+    std::vector<double> h64(t->off[5]);
+    std::vector<float> h32(t->off[5]);
+    for (int k = 0; k < 5; ++k)
+        for (size_t j = 0; j < sizes[k]; ++j) {
+            const double v = src[k][j];
+            if (!std::isfinite(v)) { delete t; return fail(QED_ERR_ARG, "qed_tables_load: non-finite entry in table %d", k); }
+            h64[t->off[k] + j] = v;
+            h32[t->off[k] + j] = (float)v;
+        }
+    if (hipMalloc(&t->d64, sizeof(double) * t->off[5]) != hipSuccess ||
+        hipMalloc(&t->d32, sizeof(float) * t->off[5]) != hipSuccess) {
+        delete t;
+        return fail(QED_ERR_NOMEM, "qed_tables_load: device allocation failed");
+    }
+    HIP_TRY(hipMemcpy(t->d64, h64.data(), sizeof(double) * t->off[5], hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(t->d32, h32.data(), sizeof(float) * t->off[5], hipMemcpyHostToDevice));
+    qed::TablesDev &d = t->dev;
+    d.ln_hrad = t->d64 + t->off[0]; d.ln_g = t->d64 + t->off[1]; d.emit_q = t->d64 + t->off[2];
+    d.pair_lnh = t->d64 + t->off[3]; d.pair_q = t->d64 + t->off[4];
+    d.ln_hrad_f = t->d32 + t->off[0]; d.ln_g_f = t->d32 + t->off[1]; d.emit_q_f = t->d32 + t->off[2];
+    d.pair_lnh_f = t->d32 + t->off[3]; d.pair_q_f = t->d32 + t->off[4];
+    d.e_n_chi = emit->n_chi; d.e_n_q = emit->n_q; d.p_n_chi = pair->n_chi; d.p_n_q = pair->n_q;
+    d.e_lnchi0 = std::log(emit->chi_min);
+    d.e_inv_dlnchi = (emit->n_chi - 1) / (std::log(emit->chi_max) - std::log(emit->chi_min));
+    d.e_logit_max = emit->logit_max;
+    d.e_inv_dt = (emit->n_q - 1) / (2.0 * emit->logit_max);
+    d.p_chi_min = pair->chi_min;
+    d.p_lnchi0 = std::log(pair->chi_min);
+    d.p_inv_dlnchi = (pair->n_chi - 1) / (std::log(pair->chi_max) - std::log(pair->chi_min));
+    d.p_logit_max = pair->logit_max;
+    d.p_inv_dt = (pair->n_q - 1) / (2.0 * pair->logit_max);
+    *out = t;
+    return QED_OK;
+}
+
+qed_status qed_tables_build(const qed_table_spec *emit, const qed_table_spec *pair, qed_tables **out) {
+    if (!out) return fail(QED_ERR_ARG, "qed_tables_build: null out");
+    *out = nullptr;
+    if (!spec_ok(emit) || !spec_ok(pair)) return fail(QED_ERR_ARG, "qed_tables_build: invalid table spec");
+    std::vector<double> a(emit->n_chi), b(emit->n_chi), c((size_t)emit->n_chi * emit->n_q),
+        d(pair->n_chi), e((size_t)pair->n_chi * pair->n_q);
+    qed_status st = qed_tables_compute_host(emit, pair, a.data(), b.data(), c.data(), d.data(), e.data());
+    if (st != QED_OK) return st;
+    return qed_tables_load(emit, pair, a.data(), b.data(), c.data(), d.data(), e.data(), out);
+}
+
+qed_status qed_tables_export(const qed_tables *t, int32_t which, double *host, size_t n) {
+    if (!t || !host || which < 0 || which > 4) return fail(QED_ERR_ARG, "qed_tables_export: bad arguments");
+    const size_t len = t->off[which + 1] - t->off[which];
+    if (n != len) return fail(QED_ERR_ARG, "qed_tables_export: table %d has %zu entries, not %zu", which, len, n);
+    HIP_TRY(hipMemcpy(host, t->d64 + t->off[which], sizeof(double) * len, hipMemcpyDeviceToHost));
+    return QED_OK;
+}
+
+void qed_tables_free(qed_tables *t) {
+    if (!t) return;
+    (void)hipFree(t->d64);
+    (void)hipFree(t->d32);
+    delete t;
+}
+
+// --------------------------------------------------------------- workspace --
+qed_status qed_workspace_create(int64_t max_particles, qed_workspace **out) {
+    if (!out) return fail(QED_ERR_ARG, "qed_workspace_create: null out");
+    *out = nullptr;
+    if (max_particles < 1 || max_particles > (int64_t)1 << 40)
+        return fail(QED_ERR_ARG, "qed_workspace_create: max_particles out of range");
+    qed_workspace *w = new qed_workspace();
+    HIP_TRY(hipGetDevice(&w->device));
+    HIP_TRY(hipDeviceGetAttribute(&w->n_cu, hipDeviceAttributeMultiprocessorCount, w->device));
+    // smallest tile is 64 threads x 1 particle
+    w->max_tiles = (max_particles + 63) / 64 + 1;
+    if (w->max_tiles > 0xffffffffll) { delete w; return fail(QED_ERR_ARG, "qed_workspace_create: too many tiles"); }
+    if (hipMalloc(&w->d_ticket, 64) != hipSuccess || hipMalloc(&w->d_lb, sizeof(uint64_t) * 4 * w->max_tiles) != hipSuccess ||
+        hipMalloc(&w->d_status, 64) != hipSuccess) {
+        delete w;
+        return fail(QED_ERR_NOMEM, "qed_workspace_create: device allocation failed");
+    }
+    // epoch 1 in the ticket's high word: zeroed look-back words (epoch 0) never match
+    const uint64_t ticket0[8] = {1ull << 32, 0, 0, 0, 0, 0, 0, 0};
+    std::vector<uint64_t> zeros(4 * w->max_tiles, 0ull);
+    HIP_TRY(hipMemcpy(w->d_ticket, ticket0, 64, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(w->d_lb, zeros.data(), sizeof(uint64_t) * 4 * w->max_tiles, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(w->d_status, zeros.data(), 64, hipMemcpyHostToDevice));
+    w->dev.ticket = w->d_ticket;
+    w->dev.lb.agg0 = w->d_lb;
+    w->dev.lb.agg1 = w->d_lb + w->max_tiles;
+    w->dev.lb.inc0 = w->d_lb + 2 * w->max_tiles;
+    w->dev.lb.inc1 = w->d_lb + 3 * w->max_tiles;
+    w->dev.status = w->d_status;
+    *out = w;
+    return QED_OK;
+}
+
+void qed_workspace_free(qed_workspace *w) {
+    if (!w) return;
+    (void)hipFree(w->d_ticket);
+    (void)hipFree(w->d_lb);
+    (void)hipFree(w->d_status);
+    delete w;
+}
+
+qed_status qed_sync_status(qed_workspace *w, qed_status_report *out, int32_t clear, void *stream) {
+    if (!w || !out) return fail(QED_ERR_ARG, "qed_sync_status: null argument");
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    unsigned long long h[8];
+    HIP_TRY(hipMemcpy(h, w->d_status, 64, hipMemcpyDeviceToHost));
+    out->flags = (int64_t)h[0];
+    for (int k = 0; k < 4; ++k) out->needed[k] = (int64_t)h[1 + k];
+    out->chi_above_table = (int64_t)h[5];
+    if (clear) {
+        const unsigned long long z[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        HIP_TRY(hipMemcpy(w->d_status, z, 64, hipMemcpyHostToDevice));
+    }
+    if (h[0] & 1ull) return fail(QED_ERR_CAPACITY, "an append did not fit its buffer (needed %lld/%lld/%lld/%lld)",
+                                 (long long)h[1], (long long)h[2], (long long)h[3], (long long)h[4]);
+    if (h[0] & 2ull) return fail(QED_ERR_RANGE, "non-finite particle state met on the device");
+    return QED_OK;
+}
+
+qed_status qed_tally_reduce(const qed_tally *t, double energy[QED_N_ENERGY], int64_t count[QED_N_COUNT],
+                            void *stream) {
+    if (!t || !t->energy || !t->count || t->n_slots < 1 || !energy || !count)
+        return fail(QED_ERR_ARG, "qed_tally_reduce: bad arguments");
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    std::vector<double> e((size_t)t->n_slots * QED_N_ENERGY);
+    HIP_TRY(hipMemcpy(e.data(), t->energy, sizeof(double) * e.size(), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(count, t->count, sizeof(int64_t) * QED_N_COUNT, hipMemcpyDeviceToHost));
+    for (int k = 0; k < QED_N_ENERGY; ++k) {
+        double s = 0.0;
+        for (int64_t j = 0; j < t->n_slots; ++j) s += e[(size_t)j * QED_N_ENERGY + k];
+        energy[k] = s;
+    }
+    return QED_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ checks --
+namespace {
+
+qed_status species_dev(const qed_species *s, bool need_chi, const char *what, qed::SpeciesDev &d) {
+    std::memset(&d, 0, sizeof d);
+    if (!s) return QED_OK;
+    if (s->prec != QED_F64 && s->prec != QED_F32) return fail(QED_ERR_ARG, "%s: prec must be QED_F64 or QED_F32", what);
+    if (!s->x || !s->y || !s->z || !s->ux || !s->uy || !s->uz || !s->tau || !s->w || !s->uid || !s->n_event || !s->d_count)
+        return fail(QED_ERR_ARG, "%s: null array", what);
+    if (need_chi && !s->chi) return fail(QED_ERR_ARG, "%s: photons need the chi array", what);
+    if (s->capacity < 0 || s->capacity > 0xffffffffll * 64) return fail(QED_ERR_ARG, "%s: bad capacity", what);
+    d.x = s->x; d.y = s->y; d.z = s->z; d.ux = s->ux; d.uy = s->uy; d.uz = s->uz;
+    d.tau = s->tau; d.w = s->w; d.chi = s->chi; d.uid = s->uid; d.n_ev = s->n_event;
+    d.count = s->d_count; d.cap = s->capacity; d.present = 1;
+    return QED_OK;
+}
+
+qed_status field_dev(const qed_field *f, int prec, qed::FieldDev &d, int &fk) {
+    std::memset(&d, 0, sizeof d);
+    if (!f) return fail(QED_ERR_ARG, "field: null");
+    d.kind = f->kind;
+    for (int c = 0; c < 3; ++c) { d.E[c] = f->E[c]; d.B[c] = f->B[c]; }
+    if (f->kind == QED_FIELD_UNIFORM) {
+        fk = qed::FIELD_UNIFORM;
+    } else if (f->kind == QED_FIELD_PLANE_WAVE) {
+        if (!(f->n_periods > 0.0) || !std::isfinite(f->a0)) return fail(QED_ERR_ARG, "field: plane wave needs n_periods > 0");
+        d.a0 = f->a0;
+        d.Phi = 2.0 * qed::kPi * f->n_periods;
+        fk = qed::FIELD_PLANE;
+    } else if (f->kind == QED_FIELD_YEE) {
+        if (!f->grid || f->nx < 1 || f->ny < 1 || f->nz < 1 || !(f->dx > 0) || !(f->dy > 0) || !(f->dz > 0))
+            return fail(QED_ERR_ARG, "field: Yee grid needs a grid pointer, sizes and spacings");
+        d.grid = f->grid; d.nx = f->nx; d.ny = f->ny; d.nz = f->nz;
+        d.inv_dx = 1.0 / f->dx; d.inv_dy = 1.0 / f->dy; d.inv_dz = 1.0 / f->dz;
+        d.x0 = f->x0; d.y0 = f->y0; d.z0 = f->z0;
+        fk = qed::FIELD_YEE;
+    } else {
+        return fail(QED_ERR_ARG, "field: unknown kind %d", f->kind);
+    }
+    (void)prec;
+    return QED_OK;
+}
+
+qed_status step_dev(const qed_step *s, qed::StepDev &d) {
+    if (!s) return fail(QED_ERR_ARG, "step: null");
+    if (!(s->dt > 0.0) || !std::isfinite(s->t)) return fail(QED_ERR_ARG, "step: dt must be > 0 and t finite");
+    if (s->rad_model < QED_RAD_NONE || s->rad_model > QED_RAD_HYBRID) return fail(QED_ERR_ARG, "step: bad rad_model");
+    if (s->max_events < 1 || s->max_events > qed::kMaxEvents) return fail(QED_ERR_ARG, "step: max_events must be 1..4");
+    d.t = s->t; d.dt = s->dt; d.d_step = s->d_step; d.seed = s->seed;
+    d.rad = s->rad_model; d.kmax = s->max_events; d.chi_switch = s->chi_switch;
+    d.gmin = s->gamma_photon_min; d.chi_push_min = s->chi_photon_push_min; d.no_recoil = s->no_recoil;
+    return QED_OK;
+}
+
+qed_status tally_dev(const qed_tally *t, qed::TallyDev &d) {
+    if (!t || !t->energy || !t->count || t->n_slots < 1) return fail(QED_ERR_ARG, "tally: needs energy, count and n_slots >= 1");
+    d.energy = t->energy; d.count = t->count; d.n_slots = t->n_slots;
+    return QED_OK;
+}
+
+qed_status consts_dev(const qed_units *u, double q, qed::ConstsDev &c) {
+    if (!u || !(u->Es_hat > 0) || !(u->A_hat > 0) || !(u->tau0_hat >= 0)) return fail(QED_ERR_ARG, "units: invalid");
+    c.q = q; c.es_inv = 1.0 / u->Es_hat; c.A = u->A_hat; c.tau0 = u->tau0_hat;
+    return QED_OK;
+}
+
+qed_status shape(const qed_workspace *w, const qed_schedule *s, int64_t capacity, dim3 &grid, dim3 &block) {
+    int b = 256, ipt = 1, bpc = 8;
+    if (s) {
+        if (s->block) b = s->block;
+        if (s->items_per_thread) ipt = s->items_per_thread;
+        if (s->blocks_per_cu) bpc = s->blocks_per_cu;
+    }
+    if (b < 64 || b > 256 || b % 64) return fail(QED_ERR_ARG, "schedule: block must be 64, 128, 192 or 256");
+    if (ipt != 1) return fail(QED_ERR_ARG, "schedule: items_per_thread must be 1");
+    if (bpc < 1 || bpc > 64) return fail(QED_ERR_ARG, "schedule: blocks_per_cu must be 1..64");
+    const int64_t tiles = (capacity + b - 1) / b;
+    if (tiles + 1 > w->max_tiles) return fail(QED_ERR_ARG, "workspace too small for %lld particles", (long long)capacity);
+    int64_t g = (int64_t)w->n_cu * bpc;
+    g = std::max<int64_t>(1, std::min<int64_t>(g, tiles));
+    grid = dim3((unsigned)g);
+    block = dim3((unsigned)b);
+    return QED_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qed_status qed_init_optical_depth(qed_species *s, uint64_t seed, void *stream) {
+    qed::SpeciesDev d;
+    if (!s) return fail(QED_ERR_ARG, "qed_init_optical_depth: null species");
+    qed_status st = species_dev(s, false, "qed_init_optical_depth", d);
+    if (st) return st;
+    int nb = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (s->capacity + 255) / 256));
+    HIP_TRY(qed::launch_init_tau(s->uid, s->tau, s->d_count, seed, nb, (hipStream_t)stream));
+    return QED_OK;
+}
+
+qed_status qed_yee_fill_separable(float *grid, int64_t nx, int64_t ny, int64_t nz, double a0,
+                                  const double *tperp, const double *tpar, void *stream) {
+    if (!grid || !tperp || !tpar || nx < 1 || ny < 1 || nz < 1) return fail(QED_ERR_ARG, "qed_yee_fill_separable: bad arguments");
+    const int64_t total = 6 * nx * ny * nz;
+    int nb = (int)std::min<int64_t>(65536, (total + 255) / 256);
+    HIP_TRY(qed::launch_yee_fill(grid, nx, ny, nz, a0, tperp, tpar, nb, (hipStream_t)stream));
+    return QED_OK;
+}
+
+qed_status qed_step_advance(int64_t *d_step, void *stream) {
+    if (!d_step) return fail(QED_ERR_ARG, "qed_step_advance: null counter");
+    HIP_TRY(qed::launch_step_advance(d_step, (hipStream_t)stream));
+    return QED_OK;
+}
+
+static qed_status push_common(const qed_tables *tab, qed_workspace *ws, const qed_units *u, double charge,
+                              qed_species *lep, qed::FieldDev &fd, int fk, qed_species *pp, qed_species *pr,
+                              qed_tally *tally, const qed_step *st, uint64_t *uid_next, const qed_schedule *sched,
+                              void *stream) {
+    if (!tab || !ws || !lep || !uid_next) return fail(QED_ERR_ARG, "qed_push_emit: null argument");
+    if (charge != -1.0 && charge != 1.0) return fail(QED_ERR_ARG, "qed_push_emit: charge must be -1 or +1");
+    qed::PushArgs a;
+    std::memset(&a, 0, sizeof a);
+    qed_status s;
+    if ((s = species_dev(lep, false, "qed_push_emit(leptons)", a.lep))) return s;
+    if ((s = species_dev(pp, true, "qed_push_emit(pushed photons)", a.pp))) return s;
+    if ((s = species_dev(pr, true, "qed_push_emit(recorded photons)", a.pr))) return s;
+    if ((pp && pp->prec != lep->prec) || (pr && pr->prec != lep->prec))
+        return fail(QED_ERR_ARG, "qed_push_emit: photons and leptons must share a precision");
+    if ((s = step_dev(st, a.st))) return s;
+    if ((s = tally_dev(tally, a.tal))) return s;
+    if ((s = consts_dev(u, charge, a.c))) return s;
+    a.tab = tab->dev;
+    a.f = fd;
+    a.ws = ws->dev;
+    a.uid_next = uid_next;
+    dim3 grid, block;
+    if ((s = shape(ws, sched, lep->capacity, grid, block))) return s;
+    HIP_TRY(qed::launch_push_emit(a, lep->prec, fk, grid, block, (hipStream_t)stream));
+    return QED_OK;
+}
+
+qed_status qed_push_emit(const qed_tables *tab, qed_workspace *ws, const qed_units *u, double charge,
+                         qed_species *lep, const qed_field *f, qed_species *ph_push, qed_species *ph_rec,
+                         qed_tally *tally, const qed_step *st, uint64_t *d_uid_next, const qed_schedule *sched,
+                         void *stream) {
+    if (!lep) return fail(QED_ERR_ARG, "qed_push_emit: null leptons");
+    qed::FieldDev fd;
+    int fk = 0;
+    qed_status s = field_dev(f, lep->prec, fd, fk);
+    if (s) return s;
+    return push_common(tab, ws, u, charge, lep, fd, fk, ph_push, ph_rec, tally, st, d_uid_next, sched, stream);
+}
+
+qed_status qed_push_emit_batched(const qed_tables *tab, qed_workspace *ws, const qed_units *u, double charge,
+                                 qed_species *lep, const qed_bunches *b, qed_species *ph_push, qed_species *ph_rec,
+                                 qed_tally *tally, const qed_step *st, uint64_t *d_uid_next,
+                                 const qed_schedule *sched, void *stream) {
+    if (!b || b->n_bunches < 1 || !b->offsets || !b->a0 || !b->n_periods)
+        return fail(QED_ERR_ARG, "qed_push_emit_batched: bad bunch table");
+    qed::FieldDev fd;
+    std::memset(&fd, 0, sizeof fd);
+    fd.kind = -1;
+    fd.n_bunches = b->n_bunches;
+    fd.offsets = b->offsets;
+    fd.a0s = b->a0;
+    fd.nper = b->n_periods;
+    return push_common(tab, ws, u, charge, lep, fd, qed::FIELD_BUNCHED, ph_push, ph_rec, tally, st, d_uid_next,
+                       sched, stream);
+}
+
+qed_status qed_pair_create(const qed_tables *tab, qed_workspace *ws, const qed_units *u, qed_species *ph,
+                           const qed_field *f, qed_species *elec, qed_species *posi, qed_tally *tally,
+                           const qed_step *st, uint64_t *d_uid_next, const qed_schedule *sched, void *stream) {
+    if (!tab || !ws || !ph || !elec || !posi || !d_uid_next) return fail(QED_ERR_ARG, "qed_pair_create: null argument");
+    qed::PairArgs a;
+    std::memset(&a, 0, sizeof a);
+    qed_status s;
+    if ((s = species_dev(ph, true, "qed_pair_create(photons)", a.ph))) return s;
+    if ((s = species_dev(elec, false, "qed_pair_create(electrons)", a.el))) return s;
+    if ((s = species_dev(posi, false, "qed_pair_create(positrons)", a.po))) return s;
+    if (elec->prec != ph->prec || posi->prec != ph->prec) return fail(QED_ERR_ARG, "qed_pair_create: mixed precisions");
+    int fk = 0;
+    if ((s = field_dev(f, ph->prec, a.f, fk))) return s;
+    if ((s = step_dev(st, a.st))) return s;
+    if ((s = tally_dev(tally, a.tal))) return s;
+    if ((s = consts_dev(u, 0.0, a.c))) return s;
+    a.tab = tab->dev;
+    a.ws = ws->dev;
+    a.uid_next = d_uid_next;
+    dim3 grid, block;
+    if ((s = shape(ws, sched, ph->capacity, grid, block))) return s;
+    HIP_TRY(qed::launch_pair_create(a, ph->prec, fk, grid, block, (hipStream_t)stream));
+    return QED_OK;
+}
+
+qed_status qed_compact(qed_workspace *ws, qed_species *ph, const qed_schedule *sched, void *stream) {
+    if (!ws || !ph) return fail(QED_ERR_ARG, "qed_compact: null argument");
+    qed::CompactArgs a;
+    std::memset(&a, 0, sizeof a);
+    qed_status s;
+    if ((s = species_dev(ph, false, "qed_compact", a.s))) return s;
+    a.ws = ws->dev;
+    dim3 grid, block;
+    if ((s = shape(ws, sched, ph->capacity, grid, block))) return s;
+    HIP_TRY(qed::launch_compact(a, ph->prec, grid, block, (hipStream_t)stream));
+    return QED_OK;
+}
+
+// ---------------------------------------------------------------- autotune --
+qed_status qed_autotune_batched(const qed_tables *tab, qed_workspace *ws, const qed_units *u, double charge,
+                                qed_species *lep, const qed_bunches *b, qed_species *ph_rec, const qed_step *st,
+                                const qed_schedule *cand, int32_t n_cand, int32_t trial_steps,
+                                const char *cache_path, qed_schedule *best, double *best_ms, void *stream) {
+    if (!tab || !ws || !u || !lep || !b || !st || !cand || n_cand < 1 || trial_steps < 1 || !best)
+        return fail(QED_ERR_ARG, "qed_autotune_batched: bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipStreamSynchronize(s));
+    int64_t n = 0;
+    HIP_TRY(hipMemcpy(&n, lep->d_count, sizeof n, hipMemcpyDeviceToHost));
+    char key[256];
+    snprintf(key, sizeof key, "n=%lld bunches=%d prec=%d rad=%d", (long long)n, b->n_bunches, lep->prec, st->rad_model);
+    if (cache_path) {
+        if (FILE *fp = std::fopen(cache_path, "r")) {
+            char line[512];
+            while (std::fgets(line, sizeof line, fp)) {
+                qed_schedule c{};
+                double ms = 0;
+                char k2[256];
+                if (std::sscanf(line, "%255[^|]| %d %d %d %lf", k2, &c.block, &c.items_per_thread, &c.blocks_per_cu, &ms) == 5 &&
+                    std::strncmp(k2, key, std::strlen(key)) == 0) {
+                    std::fclose(fp);
+                    *best = c;
+                    if (best_ms) *best_ms = ms;
+                    return QED_OK;
+                }
+            }
+            std::fclose(fp);
+        }
+    }
+    // scratch copy of the mutable lepton state, restored after each trial
+    const size_t es = lep->prec == QED_F64 ? 8 : 4;
+    void *saved = nullptr;
+    const size_t bytes = (size_t)n * (6 * es + 8 + 4);
+    if (n > 0 && hipMalloc(&saved, bytes) != hipSuccess) return fail(QED_ERR_NOMEM, "qed_autotune_batched: no scratch");
+    auto copy_state = [&](bool save) -> hipError_t {
+        char *p = (char *)saved;
+        void *arr[6] = {lep->x, lep->y, lep->z, lep->ux, lep->uy, lep->uz};
+        for (int k = 0; k < 6; ++k) {
+            hipError_t e = save ? hipMemcpyAsync(p, arr[k], n * es, hipMemcpyDeviceToDevice, s)
+                                : hipMemcpyAsync(arr[k], p, n * es, hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return e;
+            p += n * es;
+        }
+        hipError_t e = save ? hipMemcpyAsync(p, lep->tau, n * 8, hipMemcpyDeviceToDevice, s)
+                            : hipMemcpyAsync(lep->tau, p, n * 8, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+        p += n * 8;
+        return save ? hipMemcpyAsync(p, lep->n_event, n * 4, hipMemcpyDeviceToDevice, s)
+                    : hipMemcpyAsync(lep->n_event, p, n * 4, hipMemcpyDeviceToDevice, s);
+    };
+    // scratch tally, step counter and id counter
+    double *t_energy = nullptr;
+    int64_t *t_count = nullptr;
+    uint64_t *t_uid = nullptr;
+    int64_t rec_count0 = 0;
+    if (ph_rec) HIP_TRY(hipMemcpy(&rec_count0, ph_rec->d_count, sizeof rec_count0, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMalloc(&t_energy, sizeof(double) * QED_N_ENERGY));
+    HIP_TRY(hipMalloc(&t_count, sizeof(int64_t) * QED_N_COUNT));
+    HIP_TRY(hipMalloc(&t_uid, sizeof(uint64_t)));
+    qed_tally tal{t_energy, t_count, 1};
+    if (n > 0) HIP_TRY(copy_state(true));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    qed_status rc = QED_OK;
+    double best_t = 1e300;
+    for (int c = 0; c < n_cand && rc == QED_OK; ++c) {
+        const uint64_t big = 1ull << 62;
+        HIP_TRY(hipMemcpy(t_uid, &big, sizeof big, hipMemcpyHostToDevice));
+        qed_step stc = *st;
+        stc.d_step = nullptr;
+        // one untimed warm-up step, then the timed trial
+        for (int k = 0; k <= trial_steps && rc == QED_OK; ++k) {
+            if (k == 1) HIP_TRY(hipEventRecord(e0, s));
+            stc.t = st->t + k * st->dt;
+            rc = qed_push_emit_batched(tab, ws, u, charge, lep, b, nullptr, ph_rec, &tal, &stc, t_uid, &cand[c], stream);
+        }
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (rc == QED_OK && ms < best_t) { best_t = ms; *best = cand[c]; }
+        if (rc != QED_OK) rc = QED_OK;          // an invalid candidate is skipped
+        if (n > 0) HIP_TRY(copy_state(false));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (ph_rec) HIP_TRY(hipMemcpy(ph_rec->d_count, &rec_count0, sizeof rec_count0, hipMemcpyHostToDevice));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(t_energy);
+    (void)hipFree(t_count);
+    (void)hipFree(t_uid);
+    if (saved) (void)hipFree(saved);
+    if (best_t >= 1e300) return fail(QED_ERR_ARG, "qed_autotune_batched: no valid candidate");
+    if (best_ms) *best_ms = best_t / trial_steps;
+    if (cache_path) {
+        if (FILE *fp = std::fopen(cache_path, "a")) {
+            std::fprintf(fp, "%s| %d %d %d %.6f\n", key, best->block, best->items_per_thread, best->blocks_per_cu,
+                         best_t / trial_steps);
+            std::fclose(fp);
+        }
+    }
+    return QED_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,771 @@
+// qed_kernels.hip -- gfx950 kernels of the per-particle radiation and QED step
+// (Lobet et al., arXiv:1311.1107, Secs. 2-3).
+//
+// All particle kernels are persistent: a fixed grid of workgroups takes tiles
+// of consecutive particles from a ticket counter, so tiles are processed in
+// index order and the decoupled look-back sees its predecessors running.
+// Particles are structure-of-arrays; each tile reads and writes its particles
+// once with coalesced accesses; new particles are appended at offsets given by
+// a wave-ballot/shuffle scan within the tile plus the look-back prefix across
+// tiles, which reproduces the serial order of the parents.
+#include "qed_kernels.h"
+
+namespace qed {
+
+// ------------------------------------------------------------------------
+// fields
+// ------------------------------------------------------------------------
+__constant__ double kYeeStag[6][3] = {
+    {0.5, 0.0, 0.0}, {0.0, 0.5, 0.0}, {0.0, 0.0, 0.5},
+    {0.0, 0.5, 0.5}, {0.5, 0.0, 0.5}, {0.5, 0.5, 0.0},
+};
+
+// Plane wave from a_y = a0 sin^2(pi phi/Phi) sin(phi), phi = t - x:
+// E_y = B_z = -(da_y/dphi).
+template <typename R>
+__device__ __forceinline__ R plane_wave_da(double t, R x, double a0, double Phi);
+
+template <>
+__device__ __forceinline__ double plane_wave_da<double>(double t, double x, double a0, double Phi) {
+    const double phi = t - x;
+    if (!(phi > 0.0 && phi < Phi)) return 0.0;
+    const double arg = kPi * phi / Phi;
+    double se, ce, sp, cp;
+    sincos(arg, &se, &ce);
+    sincos(phi, &sp, &cp);
+    return a0 * ((kPi / Phi) * (2.0 * se * ce) * sp + se * se * cp);
+}
+
+template <>
+__device__ __forceinline__ float plane_wave_da<float>(double t, float x, double a0, double Phi) {
+    // phase formed and reduced in FP64, trigonometry in FP32
+    const double phi = t - (double)x;
+    if (!(phi > 0.0 && phi < Phi)) return 0.0f;
+    const float arg = (float)(kPi * phi / Phi);
+    const double red = phi - (2.0 * kPi) * rint(phi * (0.5 / kPi));
+    float se, ce, sp, cp;
+    sincosf(arg, &se, &ce);
+    sincosf((float)red, &sp, &cp);
+    return (float)a0 * ((float)(kPi / Phi) * (2.0f * se * ce) * sp + se * se * cp);
+}
+
+// Quadratic (TSC) weights about the nearest node.
+template <typename R>
+__device__ __forceinline__ int64_t tsc(R g, R w[3]) {
+    // far outside the grid (or NaN): a node index that every bounds test rejects
+    if (!(g > R(-1.0e6) && g < R(1.0e6))) g = R(-1.0e6);
+    const R f = floor(g + R(0.5));
+    const R d = g - f;
+    w[0] = R(0.5) * (R(0.5) - d) * (R(0.5) - d);
+    w[1] = R(0.75) - d * d;
+    w[2] = R(0.5) * (R(0.5) + d) * (R(0.5) + d);
+    return (int64_t)f;
+}
+
+template <typename R>
+__device__ __forceinline__ void yee_gather(const FieldDev &f, R x, R y, R z, R E[3], R B[3]) {
+    const int64_t nx = f.nx, ny = f.ny, nz = f.nz, plane = ny * nz, ncell = nx * plane;
+    const R gx = (x - (R)f.x0) * (R)f.inv_dx, gy = (y - (R)f.y0) * (R)f.inv_dy, gz = (z - (R)f.z0) * (R)f.inv_dz;
+    R out[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        R wx[3], wy[3], wz[3];
+        const int64_t i0 = tsc<R>(gx - (R)kYeeStag[c][0], wx) - 1;
+        const int64_t j0 = tsc<R>(gy - (R)kYeeStag[c][1], wy) - 1;
+        const int64_t k0 = tsc<R>(gz - (R)kYeeStag[c][2], wz) - 1;
+        const float *g = f.grid + c * ncell;
+        R acc = R(0);
+        if (i0 >= 0 && i0 + 2 < nx && j0 >= 0 && j0 + 2 < ny && k0 >= 0 && k0 + 2 < nz) {
+            const float *p = g + (i0 * ny + j0) * nz + k0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    const float *r = p + (a * ny + b) * nz;
+                    const R wab = wx[a] * wy[b];
+                    acc += wab * (wz[0] * (R)r[0] + wz[1] * (R)r[1] + wz[2] * (R)r[2]);
+                }
+        } else {
+            for (int a = 0; a < 3; ++a) {
+                const int64_t i = i0 + a;
+                if (i < 0 || i >= nx) continue;
+                for (int b = 0; b < 3; ++b) {
+                    const int64_t j = j0 + b;
+                    if (j < 0 || j >= ny) continue;
+                    for (int cc = 0; cc < 3; ++cc) {
+                        const int64_t k = k0 + cc;
+                        if (k < 0 || k >= nz) continue;
+                        acc += (wx[a] * wy[b]) * wz[cc] * (R)g[(i * ny + j) * nz + k];
+                    }
+                }
+            }
+        }
+        out[c] = acc;
+    }
+    E[0] = out[0]; E[1] = out[1]; E[2] = out[2];
+    B[0] = out[3]; B[1] = out[4]; B[2] = out[5];
+}
+
+template <typename R, int FK>
+__device__ __forceinline__ void field_at(const FieldDev &f, double t, R x, R y, R z,
+                                         double a0, double Phi, R E[3], R B[3]) {
+    if (FK == FIELD_UNIFORM) {
+        E[0] = (R)f.E[0]; E[1] = (R)f.E[1]; E[2] = (R)f.E[2];
+        B[0] = (R)f.B[0]; B[1] = (R)f.B[1]; B[2] = (R)f.B[2];
+    } else if (FK == FIELD_PLANE || FK == FIELD_BUNCHED) {
+        const R da = plane_wave_da<R>(t, x, a0, Phi);
+        E[0] = R(0); E[1] = -da; E[2] = R(0);
+        B[0] = R(0); B[1] = R(0); B[2] = -da;
+    } else {
+        yee_gather<R>(f, x, y, z, E, B);
+    }
+}
+
+// ------------------------------------------------------------------------
+// helpers for the per-tile epilogue
+// ------------------------------------------------------------------------
+__device__ __forceinline__ void status_flag(unsigned long long *st, unsigned long long bit) {
+    atomicOr(st + 0, bit);
+}
+__device__ __forceinline__ void status_need(unsigned long long *st, int which, int64_t v) {
+    atomicMax(st + 1 + which, (unsigned long long)v);
+}
+
+// Reduce the per-thread energies of a tile and add them to the tile's slot.
+template <int NE>
+__device__ __forceinline__ void tile_energy(const TallyDev &tal, int64_t tile, bool atomic_slots,
+                                            double (&e)[NE], double *s_red) {
+    const int lane = lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+        double v = e[k];
+        if (__ballot(v != 0.0)) v = wave_sum_f64(v); else v = 0.0;
+        if (lane == 0) s_red[k * kMaxWaves + wid] = v;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < NE) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += s_red[threadIdx.x * kMaxWaves + w];
+        if (s != 0.0) {
+            double *slot = tal.energy + (tile % tal.n_slots) * kNEnergy + threadIdx.x;
+            if (atomic_slots) atomicAdd(slot, s); else *slot += s;
+        }
+    }
+}
+
+// Add the block's integer counts into the tally (commutative, so exact).
+__device__ __forceinline__ void block_counts(const TallyDev &tal, int (&c)[N_COUNT_USED], int64_t *s_cnt) {
+    if (threadIdx.x < N_COUNT_USED) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < N_COUNT_USED; ++k) {
+        uint32_t v = (uint32_t)c[k];
+        if (__ballot(v != 0u)) {
+            v = wave_sum_u32(v);
+            if (lane_id() == 0 && v) atomicAdd((unsigned long long *)&s_cnt[k], (unsigned long long)v);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < N_COUNT_USED && s_cnt[threadIdx.x])
+        atomicAdd((unsigned long long *)(tal.count + threadIdx.x), (unsigned long long)s_cnt[threadIdx.x]);
+}
+
+// ------------------------------------------------------------------------
+// Lepton step: Boris push, chi_e, Sokolov or optical-depth Monte Carlo.
+// ------------------------------------------------------------------------
+// Emissions of one particle in one step, kept in registers: slots are written
+// through compile-time indices so that no scratch memory is used.
+template <typename R>
+struct Emitted {
+    R gg[kMaxEvents];      // gamma_gamma
+    R chig[kMaxEvents];    // chi_gamma at creation
+    uint8_t dst[kMaxEvents];   // 0 pushed, 1 recorded, 2 tallied, 3 below threshold
+    int n;
+    __device__ __forceinline__ void put(int k, R g, R c, uint8_t d) {
+#pragma unroll
+        for (int j = 0; j < kMaxEvents; ++j)
+            if (j == k) { gg[j] = g; chig[j] = c; dst[j] = d; }
+        n = k + 1;
+    }
+};
+
+template <typename R, int FK>
+__global__ void __launch_bounds__(256)
+k_push_emit(PushArgs a) {
+    __shared__ R s_lh[kMaxChiNodes];
+    __shared__ R s_lg[kMaxChiNodes];
+    __shared__ uint64_t s_ticket;
+    __shared__ uint32_t s_wave[2 * kMaxWaves];
+    __shared__ uint32_t s_pref[2];
+    __shared__ int64_t s_b0;
+    __shared__ double s_red[kNEnergy * kMaxWaves];
+    __shared__ int64_t s_cnt[N_COUNT_USED];
+
+    const int tid = threadIdx.x;
+    const TablesDev &tb = a.tab;
+    for (int i = tid; i < tb.e_n_chi; i += blockDim.x) {
+        s_lh[i] = (R)tb.ln_hrad[i];
+        s_lg[i] = (R)tb.ln_g[i];
+    }
+    const int64_t n = *a.lep.count;
+    const int64_t base0 = a.pp.present ? *a.pp.count : 0;
+    const int64_t base1 = a.pr.present ? *a.pr.count : 0;
+    const uint64_t uid0 = *a.uid_next;
+    const double t = a.st.d_step ? a.st.t + (double)(*a.st.d_step) * a.st.dt : a.st.t;
+    const double dt = a.st.dt;
+    const R dtr = (R)dt;
+    const int64_t tile_sz = blockDim.x;
+    const int64_t n_tiles = (n + tile_sz - 1) / tile_sz;
+    const bool atomic_slots = n_tiles > a.tal.n_slots;
+    const R q = (R)a.c.q, hq = R(0.5) * q * dtr;
+    const R es_inv = (R)a.c.es_inv, Ah = (R)a.c.A, tau0 = (R)a.c.tau0;
+    const R lnchi0 = (R)tb.e_lnchi0, inv_d = (R)tb.e_inv_dlnchi;
+    const R* qtab = emit_q_ptr<R>(tb);
+    R *X = (R *)a.lep.x, *Y = (R *)a.lep.y, *Z = (R *)a.lep.z;
+    R *UX = (R *)a.lep.ux, *UY = (R *)a.lep.uy, *UZ = (R *)a.lep.uz;
+    const R *Wt = (const R *)a.lep.w;
+    int cnt[N_COUNT_USED];
+#pragma unroll
+    for (int k = 0; k < N_COUNT_USED; ++k) cnt[k] = 0;
+    __syncthreads();
+
+    for (;;) {
+        if (tid == 0) {
+            s_ticket = atomicAdd((unsigned long long *)a.ws.ticket, 1ull);
+            if (FK == FIELD_BUNCHED) {
+                // bunch of the tile's first particle
+                const int64_t first = (int64_t)(s_ticket & 0xffffffffull) * tile_sz;
+                int lo = 0, hi = a.f.n_bunches;     // offsets[lo] <= first < offsets[hi]
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (a.f.offsets[mid] <= first) lo = mid; else hi = mid;
+                }
+                s_b0 = lo;
+            }
+        }
+        __syncthreads();
+        const uint64_t tk = s_ticket;
+        const uint32_t epoch = (uint32_t)(tk >> 32);
+        const int64_t tile = (int64_t)(tk & 0xffffffffull);
+        if (tile >= n_tiles) {
+            if (tid == 0 && tile == n_tiles + (int64_t)gridDim.x - 1) {
+                if (n_tiles > 0) {
+                    uint32_t t0, t1;
+                    lb_wait_inclusive(a.ws.lb, n_tiles - 1, epoch, t0, t1);
+                    if (a.pp.present) {
+                        int64_t want = base0 + (int64_t)t0;
+                        if (want > a.pp.cap) { status_flag(a.ws.status, 1ull); status_need(a.ws.status, 0, want); want = a.pp.cap; }
+                        *a.pp.count = want;
+                    }
+                    if (a.pr.present) {
+                        int64_t want = base1 + (int64_t)t1;
+                        if (want > a.pr.cap) { status_flag(a.ws.status, 1ull); status_need(a.ws.status, 1, want); want = a.pr.cap; }
+                        *a.pr.count = want;
+                    }
+                    *a.uid_next = uid0 + (uint64_t)t0 + (uint64_t)t1;
+                }
+                atomicAdd((unsigned long long *)a.ws.ticket,
+                          (1ull << 32) - (unsigned long long)(n_tiles + (int64_t)gridDim.x));
+            }
+            break;
+        }
+
+        const int64_t i = tile * tile_sz + tid;
+        const bool live = i < n;
+        double en[kNEnergy];
+#pragma unroll
+        for (int k = 0; k < kNEnergy; ++k) en[k] = 0.0;
+        Emitted<R> em;
+        em.n = 0;
+        R x = R(0), y = R(0), z = R(0), ux = R(0), uy = R(0), uz = R(0);
+        R nx_ = R(0), ny_ = R(0), nz_ = R(0);       // updated position
+        R uhx = R(0), uhy = R(0), uhz = R(0);       // photon direction
+        double tau = 0.0;
+        uint32_t nev = 0;
+        uint64_t uid = 0;
+        R wgt = R(0);
+        bool mc_taken = false;
+        if (live) {
+            x = X[i]; y = Y[i]; z = Z[i];
+            ux = UX[i]; uy = UY[i]; uz = UZ[i];
+            double a0 = a.f.a0, Phi = a.f.Phi;
+            if (FK == FIELD_BUNCHED) {
+                int64_t b = s_b0;
+                while (b + 1 < a.f.n_bunches && i >= a.f.offsets[b + 1]) ++b;
+                a0 = a.f.a0s[b];
+                Phi = 2.0 * kPi * a.f.nper[b];
+            }
+            R E[3], B[3];
+            field_at<R, FK>(a.f, t, x, y, z, a0, Phi, E, B);
+            const R g_old = Math<R>::sqrt_(R(1) + (ux * ux + uy * uy + uz * uz));
+
+            // Boris: half electric kick, magnetic rotation, half kick
+            const R umx = ux + hq * E[0], umy = uy + hq * E[1], umz = uz + hq * E[2];
+            const R gm = Math<R>::sqrt_(R(1) + (umx * umx + umy * umy + umz * umz));
+            const R tx = hq * B[0] / gm, ty = hq * B[1] / gm, tz = hq * B[2] / gm;
+            const R t2 = tx * tx + ty * ty + tz * tz;
+            const R sx = R(2) * tx / (R(1) + t2), sy = R(2) * ty / (R(1) + t2), sz = R(2) * tz / (R(1) + t2);
+            const R px = umx + (umy * tz - umz * ty);
+            const R py = umy + (umz * tx - umx * tz);
+            const R pz = umz + (umx * ty - umy * tx);
+            const R qx = umx + (py * sz - pz * sy);
+            const R qy = umy + (pz * sx - px * sz);
+            const R qz = umz + (px * sy - py * sx);
+            const R uLx = qx + hq * E[0], uLy = qy + hq * E[1], uLz = qz + hq * E[2];
+            const R gL = Math<R>::sqrt_(R(1) + (uLx * uLx + uLy * uLy + uLz * uLz));
+            wgt = Wt[i];
+            en[E_WORK] = (double)wgt * (double)(gL - g_old);
+
+            const R chi = chi_of<R>(es_inv, gL, uLx, uLy, uLz, E, B);
+            R unx = uLx, uny = uLy, unz = uLz;
+            R dvx = R(0), dvy = R(0), dvz = R(0);
+            int rad = a.st.rad;
+            if (!isfinite((double)chi) || !isfinite((double)gL)) { cnt[C_NAN]++; rad = RAD_NONE; status_flag(a.ws.status, 2ull); }
+
+            if (rad == RAD_SOKOLOV || (rad == RAD_HYBRID && (double)chi < a.st.chi_switch)) {
+                // Sokolov scheme (Eq. 4) with P_rad of Eq. 5
+                cnt[C_SOKOLOV]++;
+                const R vx = uLx / gL, vy = uLy / gL, vz = uLz / gL;
+                const R fx = q * (E[0] + (vy * B[2] - vz * B[1]));
+                const R fy = q * (E[1] + (vz * B[0] - vx * B[2]));
+                const R fz = q * (E[2] + (vx * B[1] - vy * B[0]));
+                const R vf = vx * fx + vy * fy + vz * fz;
+                const R den = R(1) + tau0 * vf;
+                dvx = tau0 * (fx - vx * vf) / den;
+                dvy = tau0 * (fy - vy * vf) / den;
+                dvz = tau0 * (fz - vz * vf) / den;
+                R g = R(1);
+                if (chi > R(0)) {
+                    bool above = false;
+                    g = Math<R>::exp_(lerp_rate<R>(s_lg, tb.e_n_chi, lnchi0, inv_d, Math<R>::log_(chi), above));
+                }
+                const R P = (R(2) / R(3)) * Ah * chi * chi * g;
+                const R bx = dvy * B[2] - dvz * B[1], by = dvz * B[0] - dvx * B[2], bz = dvx * B[1] - dvy * B[0];
+                unx = uLx + dtr * (q * bx - P * uLx / gL);
+                uny = uLy + dtr * (q * by - P * uLy / gL);
+                unz = uLz + dtr * (q * bz - P * uLz / gL);
+                en[E_RAD] = (double)wgt * (double)P * dt;
+            } else if (rad == RAD_MC || rad == RAD_HYBRID) {
+                // optical-depth Monte Carlo, Eqs. 6-8
+                cnt[C_MC]++;
+                mc_taken = true;
+                R p = Math<R>::sqrt_(uLx * uLx + uLy * uLy + uLz * uLz);
+                if (p > R(0)) { uhx = uLx / p; uhy = uLy / p; uhz = uLz / p; }
+                R gam = gL, ce = chi;
+                R W = R(0);
+                if (p > R(0) && ce > R(0)) {
+                    bool above = false;
+                    W = Ah * Math<R>::exp_(lerp_rate<R>(s_lh, tb.e_n_chi, lnchi0, inv_d, Math<R>::log_(ce), above)) / gam;
+                    if (above) cnt[C_RANGE]++;
+                }
+                tau = a.lep.tau[i];
+                double t_left = dt;
+                int k = 0;
+                for (;;) {
+                    const double Wd = (double)W;
+                    if (!(W > R(0)) || tau > Wd * t_left) { tau -= Wd * t_left; break; }
+                    if (k == a.st.kmax) { tau -= Wd * t_left; cnt[C_CAP]++; break; }
+                    t_left -= (tau > 0.0 ? tau : 0.0) / Wd;
+                    if (k == 0) { nev = a.lep.n_ev[i]; uid = a.lep.uid[i]; }
+                    const U64x4 o = philox4x64_10(uid, (uint64_t)nev, (uint64_t)RNG_EMIT, 0ull, a.st.seed, 0ull);
+                    const double r1 = u01(o.a), r2 = u01(o.b);
+                    R xi = Math<R>::exp_(quantile<R>(qtab, tb.e_n_chi, tb.e_n_q, lnchi0, inv_d,
+                                                     tb.e_logit_max, tb.e_inv_dt, Math<R>::log_(ce), r1));
+                    if (xi > R(1)) xi = R(1);
+                    const R gg = xi * gam;
+                    cnt[C_EMIT]++;
+                    uint8_t d;
+                    R chig_k = R(0);
+                    const double eg = (double)wgt * (double)gg;
+                    if ((double)gg > a.st.gmin) {
+                        chig_k = xi * ce;
+                        if (a.pp.present && (double)chig_k > a.st.chi_push_min) { d = 0; cnt[C_PUSH]++; en[E_PUSH] += eg; }
+                        else if (a.pr.present) { d = 1; cnt[C_REC]++; en[E_REC] += eg; }
+                        else { d = 2; cnt[C_DROP]++; en[E_DROP] += eg; }
+                    } else {
+                        d = 3; cnt[C_SUB]++; en[E_SUB] += eg;
+                    }
+                    em.put(k, gg, chig_k, d);
+                    if (!a.st.no_recoil) {
+                        // Eq. 8: |p_f| = |p| - eps_gamma/c, clamped at zero
+                        p = p - gg;
+                        if (p < R(0)) p = R(0);
+                        gam = Math<R>::sqrt_(R(1) + p * p);
+                        ce = chi_of<R>(es_inv, gam, p * uhx, p * uhy, p * uhz, E, B);
+                        W = R(0);
+                        if (p > R(0) && ce > R(0)) {
+                            bool above = false;
+                            W = Ah * Math<R>::exp_(lerp_rate<R>(s_lh, tb.e_n_chi, lnchi0, inv_d, Math<R>::log_(ce), above)) / gam;
+                            if (above) cnt[C_RANGE]++;
+                        }
+                    }
+                    tau = -log(r2);
+                    ++nev;
+                    ++k;
+                }
+                if (em.n > 0) { unx = p * uhx; uny = p * uhy; unz = p * uhz; }
+            }
+            const R gn = Math<R>::sqrt_(R(1) + (unx * unx + uny * uny + unz * unz));
+            nx_ = x + dtr * (unx / gn + dvx);
+            ny_ = y + dtr * (uny / gn + dvy);
+            nz_ = z + dtr * (unz / gn + dvz);
+            ux = unx; uy = uny; uz = unz;
+        }
+
+        // --- stable append of the stored photons --------------------------
+        uint32_t c0 = 0, c1 = 0;
+#pragma unroll
+        for (int k = 0; k < kMaxEvents; ++k)
+            if (k < em.n) { c0 += em.dst[k] == 0; c1 += em.dst[k] == 1; }
+        uint32_t e0, e1, tot0, tot1;
+        block_scan2(c0, c1, e0, e1, tot0, tot1, s_wave);
+        if (tid < kWave) {
+            uint32_t p0, p1;
+            lookback2(a.ws.lb, tile, epoch, tot0, tot1, p0, p1);
+            if (tid == 0) { s_pref[0] = p0; s_pref[1] = p1; }
+        }
+        __syncthreads();
+
+        if (live) {
+            X[i] = nx_; Y[i] = ny_; Z[i] = nz_;
+            UX[i] = ux; UY[i] = uy; UZ[i] = uz;
+            if (mc_taken) a.lep.tau[i] = tau;
+            if (em.n > 0) a.lep.n_ev[i] = nev;
+            uint32_t g0 = s_pref[0] + e0, g1 = s_pref[1] + e1;
+#pragma unroll
+            for (int k = 0; k < kMaxEvents; ++k) {
+                if (k >= em.n) break;
+                const uint8_t d = em.dst[k];
+                if (d > 1) continue;
+                const uint64_t nid = uid0 + (uint64_t)g0 + (uint64_t)g1;
+                const SpeciesDev &S = d == 0 ? a.pp : a.pr;
+                const int64_t j = (d == 0 ? base0 + (int64_t)g0 : base1 + (int64_t)g1);
+                if (d == 0) ++g0; else ++g1;
+                if (j >= S.cap) { cnt[C_LOST]++; continue; }
+                const R gg = em.gg[k];
+                ((R *)S.x)[j] = x + dtr * uhx;
+                ((R *)S.y)[j] = y + dtr * uhy;
+                ((R *)S.z)[j] = z + dtr * uhz;
+                ((R *)S.ux)[j] = gg * uhx;
+                ((R *)S.uy)[j] = gg * uhy;
+                ((R *)S.uz)[j] = gg * uhz;
+                ((R *)S.w)[j] = wgt;
+                if (S.chi) ((R *)S.chi)[j] = em.chig[k];
+                S.uid[j] = nid;
+                S.n_ev[j] = 0u;
+                S.tau[j] = initial_tau(a.st.seed, nid);
+            }
+        }
+        tile_energy<kNEnergy>(a.tal, tile, atomic_slots, en, s_red);
+        __syncthreads();
+    }
+    block_counts(a.tal, cnt, s_cnt);
+}
+
+// ------------------------------------------------------------------------
+// Photon step: Breit-Wheeler pair creation (Sec. 3, Eq. 3) and straight-line
+// push.  Decayed photons are marked with tau = +inf (removed by k_compact).
+// ------------------------------------------------------------------------
+template <typename R, int FK>
+__global__ void __launch_bounds__(256)
+k_pair_create(PairArgs a) {
+    __shared__ R s_lp[kMaxChiNodes];
+    __shared__ uint64_t s_ticket;
+    __shared__ uint32_t s_wave[2 * kMaxWaves];
+    __shared__ uint32_t s_pref;
+    __shared__ double s_red[kNEnergy * kMaxWaves];
+    __shared__ int64_t s_cnt[N_COUNT_USED];
+
+    const int tid = threadIdx.x;
+    const TablesDev &tb = a.tab;
+    for (int i = tid; i < tb.p_n_chi; i += blockDim.x) s_lp[i] = (R)tb.pair_lnh[i];
+    const int64_t n = *a.ph.count;
+    const int64_t base_e = *a.el.count, base_p = *a.po.count;
+    const uint64_t uid0 = *a.uid_next;
+    const double t = a.st.d_step ? a.st.t + (double)(*a.st.d_step) * a.st.dt : a.st.t;
+    const double dt = a.st.dt;
+    const R dtr = (R)dt;
+    const int64_t tile_sz = blockDim.x;
+    const int64_t n_tiles = (n + tile_sz - 1) / tile_sz;
+    const bool atomic_slots = n_tiles > a.tal.n_slots;
+    const R es_inv = (R)a.c.es_inv, Ah = (R)a.c.A;
+    const R lnchi0 = (R)tb.p_lnchi0, inv_d = (R)tb.p_inv_dlnchi, chi_min = (R)tb.p_chi_min;
+    const R *qtab = pair_q_ptr<R>(tb);
+    R *X = (R *)a.ph.x, *Y = (R *)a.ph.y, *Z = (R *)a.ph.z;
+    const R *KX = (const R *)a.ph.ux, *KY = (const R *)a.ph.uy, *KZ = (const R *)a.ph.uz;
+    int cnt[N_COUNT_USED];
+#pragma unroll
+    for (int k = 0; k < N_COUNT_USED; ++k) cnt[k] = 0;
+    __syncthreads();
+
+    for (;;) {
+        if (tid == 0) s_ticket = atomicAdd((unsigned long long *)a.ws.ticket, 1ull);
+        __syncthreads();
+        const uint64_t tk = s_ticket;
+        const uint32_t epoch = (uint32_t)(tk >> 32);
+        const int64_t tile = (int64_t)(tk & 0xffffffffull);
+        if (tile >= n_tiles) {
+            if (tid == 0 && tile == n_tiles + (int64_t)gridDim.x - 1) {
+                if (n_tiles > 0) {
+                    uint32_t t0, t1;
+                    lb_wait_inclusive(a.ws.lb, n_tiles - 1, epoch, t0, t1);
+                    int64_t we = base_e + (int64_t)t0, wp = base_p + (int64_t)t0;
+                    if (we > a.el.cap) { status_flag(a.ws.status, 1ull); status_need(a.ws.status, 2, we); we = a.el.cap; }
+                    if (wp > a.po.cap) { status_flag(a.ws.status, 1ull); status_need(a.ws.status, 3, wp); wp = a.po.cap; }
+                    *a.el.count = we;
+                    *a.po.count = wp;
+                    *a.uid_next = uid0 + 2ull * (uint64_t)t0;
+                }
+                atomicAdd((unsigned long long *)a.ws.ticket,
+                          (1ull << 32) - (unsigned long long)(n_tiles + (int64_t)gridDim.x));
+            }
+            break;
+        }
+        const int64_t i = tile * tile_sz + tid;
+        double en[kNEnergy];
+#pragma unroll
+        for (int k = 0; k < kNEnergy; ++k) en[k] = 0.0;
+        bool event = false;
+        R x = R(0), y = R(0), z = R(0), khx = R(0), khy = R(0), khz = R(0);
+        R gmn = R(1), gpl = R(1), chim = R(0), chip = R(0), wgt = R(0);
+        double tau = 0.0;
+        if (i < n) {
+            tau = a.ph.tau[i];
+            if (tau != HUGE_VAL) {
+                x = X[i]; y = Y[i]; z = Z[i];
+                const R kx = KX[i], ky = KY[i], kz = KZ[i];
+                R E[3], B[3];
+                field_at<R, FK>(a.f, t, x, y, z, a.f.a0, a.f.Phi, E, B);
+                const R kk = Math<R>::sqrt_(kx * kx + ky * ky + kz * kz);
+                const R chig = chi_of<R>(es_inv, kk, kx, ky, kz, E, B);
+                cnt[C_PHSTEP]++;
+                R Wp = R(0);
+                if (kk > R(2) && chig >= chi_min) {
+                    bool above = false;
+                    const R l = lerp_rate<R>(s_lp, tb.p_n_chi, lnchi0, inv_d, Math<R>::log_(chig), above);
+                    Wp = Ah * Math<R>::exp_(l - R(8) / (R(3) * chig)) / kk;
+                    if (above) cnt[C_RANGE]++;
+                }
+                tau -= (double)Wp * dt;
+                khx = kx / kk; khy = ky / kk; khz = kz / kk;
+                if (Wp > R(0) && tau <= 0.0) {
+                    event = true;
+                    const U64x4 o = philox4x64_10(a.ph.uid[i], (uint64_t)a.ph.n_ev[i], (uint64_t)RNG_PAIR, 0ull,
+                                                  a.st.seed, 0ull);
+                    const R s = quantile<R>(qtab, tb.p_n_chi, tb.p_n_q, lnchi0, inv_d, tb.p_logit_max,
+                                            tb.p_inv_dt, Math<R>::log_(chig), u01(o.a));
+                    const R eta = R(1) / (R(1) + Math<R>::exp_(-s));
+                    chim = eta * chig;
+                    chip = chig - chim;
+                    gmn = R(1) + (kk - R(2)) * (chim / chig);
+                    gpl = R(1) + (kk - R(2)) * (chip / chig);
+                    wgt = ((const R *)a.ph.w)[i];
+                    cnt[C_PAIR]++;
+                    en[E_PAIR] = (double)wgt * (double)kk;
+                }
+            }
+        }
+        uint32_t e, tot;
+        block_scan_flag(event, e, tot, s_wave);
+        if (tid < kWave) {
+            uint32_t p0, p1;
+            lookback2(a.ws.lb, tile, epoch, tot, 0u, p0, p1);
+            if (tid == 0) s_pref = p0;
+        }
+        __syncthreads();
+        if (i < n && tau != HUGE_VAL) {
+            if (!event) {
+                X[i] = x + dtr * khx;
+                Y[i] = y + dtr * khy;
+                Z[i] = z + dtr * khz;
+                a.ph.tau[i] = tau;
+            } else {
+                a.ph.tau[i] = HUGE_VAL;
+                const uint32_t g = s_pref + e;
+                const uint64_t nid = uid0 + 2ull * (uint64_t)g;
+#pragma unroll
+                for (int side = 0; side < 2; ++side) {
+                    const SpeciesDev &D = side == 0 ? a.el : a.po;
+                    const int64_t j = (side == 0 ? base_e : base_p) + (int64_t)g;
+                    if (j >= D.cap) { cnt[C_LOST]++; continue; }
+                    const R gmag = side == 0 ? gmn : gpl;
+                    const R pm = Math<R>::sqrt_(gmag * gmag - R(1));
+                    const R ux = pm * khx, uy = pm * khy, uz = pm * khz;
+                    const uint64_t id = nid + (uint64_t)side;
+                    ((R *)D.x)[j] = x + dtr * (ux / gmag);
+                    ((R *)D.y)[j] = y + dtr * (uy / gmag);
+                    ((R *)D.z)[j] = z + dtr * (uz / gmag);
+                    ((R *)D.ux)[j] = ux;
+                    ((R *)D.uy)[j] = uy;
+                    ((R *)D.uz)[j] = uz;
+                    ((R *)D.w)[j] = wgt;
+                    if (D.chi) ((R *)D.chi)[j] = side == 0 ? chim : chip;
+                    D.uid[j] = id;
+                    D.n_ev[j] = 0u;
+                    D.tau[j] = initial_tau(a.st.seed, id);
+                }
+            }
+        }
+        tile_energy<kNEnergy>(a.tal, tile, atomic_slots, en, s_red);
+        __syncthreads();
+    }
+    block_counts(a.tal, cnt, s_cnt);
+}
+
+// ------------------------------------------------------------------------
+// Stable in-place compaction of the photons that are still alive.  Every
+// thread holds its whole particle in registers before the tile publishes its
+// count, so a later tile writing over this tile's slots cannot clobber data
+// that has not been read yet.
+// ------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_compact(CompactArgs a) {
+    __shared__ uint64_t s_ticket;
+    __shared__ uint32_t s_wave[2 * kMaxWaves];
+    __shared__ uint32_t s_pref;
+    const int tid = threadIdx.x;
+    const int64_t n = *a.s.count;
+    const int64_t tile_sz = blockDim.x;
+    const int64_t n_tiles = (n + tile_sz - 1) / tile_sz;
+    R *X = (R *)a.s.x, *Y = (R *)a.s.y, *Z = (R *)a.s.z;
+    R *UX = (R *)a.s.ux, *UY = (R *)a.s.uy, *UZ = (R *)a.s.uz, *Wt = (R *)a.s.w, *CH = (R *)a.s.chi;
+    __syncthreads();
+    for (;;) {
+        if (tid == 0) s_ticket = atomicAdd((unsigned long long *)a.ws.ticket, 1ull);
+        __syncthreads();
+        const uint64_t tk = s_ticket;
+        const uint32_t epoch = (uint32_t)(tk >> 32);
+        const int64_t tile = (int64_t)(tk & 0xffffffffull);
+        if (tile >= n_tiles) {
+            if (tid == 0 && tile == n_tiles + (int64_t)gridDim.x - 1) {
+                if (n_tiles > 0) {
+                    uint32_t t0, t1;
+                    lb_wait_inclusive(a.ws.lb, n_tiles - 1, epoch, t0, t1);
+                    *a.s.count = (int64_t)t0;
+                }
+                atomicAdd((unsigned long long *)a.ws.ticket,
+                          (1ull << 32) - (unsigned long long)(n_tiles + (int64_t)gridDim.x));
+            }
+            break;
+        }
+        const int64_t i = tile * tile_sz + tid;
+        bool alive = false;
+        R x = R(0), y = R(0), z = R(0), ux = R(0), uy = R(0), uz = R(0), w = R(0), ch = R(0);
+        double tau = 0.0;
+        uint64_t uid = 0;
+        uint32_t nev = 0;
+        if (i < n) {
+            tau = a.s.tau[i];
+            alive = tau != HUGE_VAL;
+            if (alive) {
+                x = X[i]; y = Y[i]; z = Z[i]; ux = UX[i]; uy = UY[i]; uz = UZ[i]; w = Wt[i];
+                if (CH) ch = CH[i];
+                uid = a.s.uid[i];
+                nev = a.s.n_ev[i];
+            }
+        }
+        // all loads of this tile complete before its count becomes visible
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        uint32_t e, tot;
+        block_scan_flag(alive, e, tot, s_wave);
+        if (tid < kWave) {
+            uint32_t p0, p1;
+            lookback2(a.ws.lb, tile, epoch, tot, 0u, p0, p1);
+            if (tid == 0) s_pref = p0;
+        }
+        __syncthreads();
+        if (alive) {
+            const int64_t j = (int64_t)(s_pref + e);
+            if (j != i) {
+                X[j] = x; Y[j] = y; Z[j] = z; UX[j] = ux; UY[j] = uy; UZ[j] = uz; Wt[j] = w;
+                if (CH) CH[j] = ch;
+                a.s.uid[j] = uid;
+                a.s.n_ev[j] = nev;
+                a.s.tau[j] = tau;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------
+// small kernels
+// ------------------------------------------------------------------------
+__global__ void k_init_tau(const uint64_t *uid, double *tau, const int64_t *count, uint64_t seed) {
+    const int64_t n = *count;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        tau[i] = initial_tau(seed, uid[i]);
+}
+
+__global__ void k_yee_fill(float *grid, int64_t nx, int64_t ny, int64_t nz, double a0,
+                           const double *tperp, const double *tpar) {
+    const int64_t plane = ny * nz, ncell = nx * plane, total = 6 * ncell;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = idx / ncell, r = idx - c * ncell;
+        const int64_t i = r / plane, jk = r - i * plane;
+        grid[idx] = (float)((a0 * tperp[c * plane + jk]) * tpar[c * nx + i]);
+    }
+}
+
+__global__ void k_step_advance(int64_t *d_step) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *d_step += 1;
+}
+
+// ------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------
+template <typename R>
+hipError_t launch_push(const PushArgs &a, int fk, dim3 grid, dim3 block, hipStream_t s) {
+    switch (fk) {
+    case FIELD_UNIFORM: hipLaunchKernelGGL((k_push_emit<R, FIELD_UNIFORM>), grid, block, 0, s, a); break;
+    case FIELD_PLANE: hipLaunchKernelGGL((k_push_emit<R, FIELD_PLANE>), grid, block, 0, s, a); break;
+    case FIELD_YEE: hipLaunchKernelGGL((k_push_emit<R, FIELD_YEE>), grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_push_emit<R, FIELD_BUNCHED>), grid, block, 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_push_emit(const PushArgs &a, int prec, int fk, dim3 grid, dim3 block, hipStream_t s) {
+    return prec == 0 ? launch_push<double>(a, fk, grid, block, s) : launch_push<float>(a, fk, grid, block, s);
+}
+
+template <typename R>
+hipError_t launch_pair(const PairArgs &a, int fk, dim3 grid, dim3 block, hipStream_t s) {
+    switch (fk) {
+    case FIELD_UNIFORM: hipLaunchKernelGGL((k_pair_create<R, FIELD_UNIFORM>), grid, block, 0, s, a); break;
+    case FIELD_PLANE: hipLaunchKernelGGL((k_pair_create<R, FIELD_PLANE>), grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_pair_create<R, FIELD_YEE>), grid, block, 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_create(const PairArgs &a, int prec, int fk, dim3 grid, dim3 block, hipStream_t s) {
+    return prec == 0 ? launch_pair<double>(a, fk, grid, block, s) : launch_pair<float>(a, fk, grid, block, s);
+}
+
+hipError_t launch_compact(const CompactArgs &a, int prec, dim3 grid, dim3 block, hipStream_t s) {
+    if (prec == 0) hipLaunchKernelGGL((k_compact<double>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_compact<float>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_tau(const uint64_t *uid, double *tau, const int64_t *count, uint64_t seed,
+                           int n_blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_tau, dim3(n_blocks), dim3(256), 0, s, uid, tau, count, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_yee_fill(float *grid, int64_t nx, int64_t ny, int64_t nz, double a0,
+                           const double *tperp, const double *tpar, int n_blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_yee_fill, dim3(n_blocks), dim3(256), 0, s, grid, nx, ny, nz, a0, tperp, tpar);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_advance(int64_t *d_step, hipStream_t s) {
+    hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(64), 0, s, d_step);
+    return hipGetLastError();
+}
+
+}  // namespace qed

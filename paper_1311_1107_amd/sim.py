@@ -1,0 +1,129 @@
+"""A run of the QED step on one GPU: electrons, positrons and photons in a
+laser field, advanced step by step through libqed.
+
+Order within step n (time t = n dt):
+  1. (Yee field) sample the pulse onto the grid for step n
+  2. electrons: push + emission            (qed_push_emit, charge -1)
+  3. positrons: push + emission            (qed_push_emit, charge +1)
+  4. photons alive at the start of the step: pair creation and push
+     (qed_pair_create); photons emitted in 2-3 are stored at level n+1 and
+     are first advanced at step n+1, as are the pairs created in 4
+  5. every `compact_every` steps, decayed photons are removed (qed_compact)
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+
+import numpy as np
+import torch
+
+from . import binding as B
+from . import device as D
+from .workloads import LAMBDA_M, PlaneWave, Workload, YeePulse
+
+EMIT_SPEC = dict(chi_min=1e-3, chi_max=1e2, n_chi=128, n_q=128, logit_max=18.0)
+PAIR_SPEC = dict(chi_min=1e-2, chi_max=1e2, n_chi=128, n_q=128, logit_max=18.0)
+
+
+class Run:
+    def __init__(self, wl: Workload, prec: int = B.QED_F64, tables: D.Tables | None = None,
+                 photon_capacity: int | None = None, record_capacity: int | None = None,
+                 pair_capacity: int | None = None, rad_model: int = B.QED_RAD_HYBRID,
+                 chi_switch: float = 1e-3, gamma_photon_min: float = 2.0, max_events: int = 4,
+                 sched: B.qed_schedule | None = None, compact_every: int = 16,
+                 deterministic_tally: bool = True, device: str = "cuda"):
+        self.wl = wl
+        self.prec = prec
+        self.units = B.qed_units_init(LAMBDA_M)
+        self.tables = tables or D.Tables(EMIT_SPEC, PAIR_SPEC)
+        n0 = len(wl.electrons["x"])
+        self.n0 = n0
+        push = wl.push_photons
+        self.push = push
+        cap_ph = photon_capacity if photon_capacity is not None else (4 * n0 if push else 0)
+        cap_rec = record_capacity if record_capacity is not None else (4 * n0 if wl.record_photons else 0)
+        cap_pair = pair_capacity if pair_capacity is not None else (n0 if push else 0)
+        self.el = D.Species(n0 + cap_pair, prec, chi=True, device=device)
+        self.po = D.Species(cap_pair, prec, chi=True, device=device)
+        self.ph = D.Species(cap_ph, prec, chi=True, device=device) if push else None
+        self.rec = D.Species(cap_rec, prec, chi=True, device=device) if wl.record_photons else None
+        caps = [n0 + cap_pair, cap_pair, cap_ph, cap_rec, 1]
+        self.ws = D.Workspace(max(caps))
+        slots = (max(caps) + 63) // 64 + 1 if deterministic_tally else 4096
+        self.tally = D.Tally(slots, device=device)
+        self.uid_next = torch.tensor([n0], dtype=torch.int64, device=device)
+        self.ph_snap = torch.zeros(1, dtype=torch.int64, device=device)
+        self.sched = sched
+        self.compact_every = compact_every
+        self.step_kw = dict(rad_model=rad_model, chi_switch=chi_switch, gamma_photon_min=gamma_photon_min,
+                            chi_photon_push_min=wl.chi_photon_push_min, max_events=max_events)
+        self.el.upload(wl.electrons)
+        B.qed_init_optical_depth(self.el.struct(), wl.seed)
+        # field
+        f = wl.field
+        if isinstance(f, PlaneWave):
+            self.field = D.plane_wave(f.a0, f.n_periods)
+            self.grid = None
+        elif isinstance(f, YeePulse):
+            nx, ny, nz = f.shape
+            self.grid = torch.zeros(6 * nx * ny * nz, dtype=torch.float32, device=device)
+            self.tperp = torch.from_numpy(np.ascontiguousarray(f.tperp)).to(device)
+            self.tpar = torch.from_numpy(np.ascontiguousarray(f.tpar)).to(device)
+            self.field = D.yee(self.grid, f.shape, f.spacing, f.origin)
+        else:
+            raise TypeError("unknown field description")
+        # photon view whose count is the snapshot taken at the start of a step
+        if self.ph is not None:
+            s = self.ph.struct()
+            self.ph_step = B.qed_species()
+            C.memmove(C.addressof(self.ph_step), C.addressof(s), C.sizeof(s))
+            self.ph_step.d_count = self.ph_snap.data_ptr()
+
+    # ------------------------------------------------------------------
+    def fill_field(self, n: int):
+        if self.grid is not None:
+            f = self.wl.field
+            nx, ny, nz = f.shape
+            tp = self.tpar[n].reshape(-1)
+            B.qed_yee_fill_separable(self.grid.data_ptr(), nx, ny, nz, f.a0, self.tperp.data_ptr(), tp.data_ptr())
+
+    def step(self, n: int):
+        st = D.step(n * self.wl.dt, self.wl.dt, self.wl.seed, **self.step_kw)
+        self.fill_field(n)
+        if self.ph is not None:
+            self.ph_snap.copy_(self.ph.count)
+        pp = self.ph.struct() if self.ph is not None else None
+        pr = self.rec.struct() if self.rec is not None else None
+        uid = self.uid_next.data_ptr()
+        B.qed_push_emit(self.tables.h, self.ws.h, self.units, -1.0, self.el.struct(), self.field, pp, pr,
+                        self.tally.s, st, uid, self.sched)
+        B.qed_push_emit(self.tables.h, self.ws.h, self.units, +1.0, self.po.struct(), self.field, pp, pr,
+                        self.tally.s, st, uid, self.sched)
+        if self.ph is not None:
+            B.qed_pair_create(self.tables.h, self.ws.h, self.units, self.ph_step, self.field, self.el.struct(),
+                              self.po.struct(), self.tally.s, st, uid, self.sched)
+            if self.compact_every and (n + 1) % self.compact_every == 0:
+                self.compact()
+
+    def compact(self):
+        if self.ph is not None:
+            B.qed_compact(self.ws.h, self.ph.struct(), self.sched)
+
+    def run(self, steps: int, start: int = 0):
+        for n in range(start, start + steps):
+            self.step(n)
+
+    def counts(self) -> dict:
+        return {"electrons": self.el.n(), "positrons": self.po.n(),
+                "photons": self.ph.n() if self.ph is not None else 0,
+                "recorded": self.rec.n() if self.rec is not None else 0}
+
+    def result(self) -> dict:
+        self.compact()
+        torch.cuda.synchronize()
+        out = {"electrons": self.el.download(), "positrons": self.po.download(),
+               "photons": self.ph.download() if self.ph is not None else None,
+               "recorded": self.rec.download() if self.rec is not None else None,
+               "tally": self.tally.reduce(), "uid_next": int(self.uid_next.item())}
+        return out

@@ -77,10 +77,13 @@ def beam_in_box(n: int, gamma0: float, spread: float, rng: np.random.Generator,
 
 
 def plane_wave_beam(n=100_000, a0=100.0, gamma0=2000.0, spread=0.01, steps=1000, seed=1,
-                    name="plane-wave beam") -> Workload:
-    """1e5 electrons, gamma0 2000 (1 % spread) against an a0 = 100 plane wave, 1000 steps."""
+                    box_lambda=20.0, push_photons=False, name="plane-wave beam") -> Workload:
+    """Electrons uniform in a box of box_lambda wavelengths, gamma0 (1 % spread) along -x,
+    against a 10-period plane wave.  Defaults: 1e5 electrons, gamma0 2000, a0 = 100,
+    20-lambda box, 1000 steps, photons recorded."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    return Workload(name, beam_in_box(n, gamma0, spread, rng), PlaneWave(a0), steps, seed=seed)
+    return Workload(name, beam_in_box(n, gamma0, spread, rng, box=box_lambda * LAM), PlaneWave(a0), steps,
+                    seed=seed, push_photons=push_photons)
 
 
 def cascade_beam(n=50_000_000, a0=1000.0, gamma0=1.0e4, steps=500, seed=5) -> Workload:
@@ -135,17 +138,22 @@ def yee_pulse(steps: int, shape=(256, 128, 128), cells_per_lambda=8, a0=200.0, w
     return YeePulse(shape, (d, d, d), origin, a0, tperp, tpar)
 
 
-def yee_beam(n=10_000_000, steps=2000, seed=2, shape=(256, 128, 128), a0=200.0) -> Workload:
-    """1e7 electrons, ln gamma0 ~ N(ln 2000, 0.3^2), uniform in the cylinder r <= 2 lambda,
-    x in [20, 28) lambda, moving along -x; sorted by grid cell (as a PIC code keeps them)."""
+def yee_beam(n=10_000_000, steps=2000, seed=2, shape=(256, 128, 128), a0=200.0, gamma_median=2000.0,
+             gamma_sigma=0.3, x_range_lambda=(20.0, 28.0), r_max_lambda=2.0, x_center0=0.0,
+             fwhm_fs=30.0, w0_lambda=3.0, chi_photon_push_min=1e-3) -> Workload:
+    """Electrons with ln gamma0 ~ N(ln gamma_median, gamma_sigma^2), uniform in the cylinder
+    r <= r_max around the axis and x in x_range (in wavelengths), moving along -x, sorted by
+    grid cell (as a PIC code keeps them), against the focused pulse of yee_pulse().
+    Defaults: 1e7 electrons, median 2000, sigma 0.3, a0 = 200, w0 = 3 lambda, 30 fs,
+    Yee grid 256 x 128 x 128 at lambda/8, 2000 steps."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    pulse = yee_pulse(steps, shape=shape, a0=a0)
+    pulse = yee_pulse(steps, shape=shape, a0=a0, w0_lambda=w0_lambda, fwhm_fs=fwhm_fs, x_center0=x_center0)
     d = pulse.spacing[0]
-    x = rng.uniform(20.0 * LAM, 28.0 * LAM, n)
-    r = 2.0 * LAM * np.sqrt(rng.uniform(0.0, 1.0, n))
+    x = rng.uniform(x_range_lambda[0] * LAM, x_range_lambda[1] * LAM, n)
+    r = r_max_lambda * LAM * np.sqrt(rng.uniform(0.0, 1.0, n))
     th = rng.uniform(0.0, TWO_PI, n)
     y, z = r * np.cos(th), r * np.sin(th)
-    g = np.exp(math.log(2000.0) + 0.3 * rng.standard_normal(n))
+    g = np.exp(math.log(gamma_median) + gamma_sigma * rng.standard_normal(n))
     ux = -np.sqrt(g * g - 1.0)
     ci = np.floor((x - pulse.origin[0]) / d).astype(np.int64)
     cj = np.floor((y - pulse.origin[1]) / d).astype(np.int64)
@@ -154,7 +162,7 @@ def yee_beam(n=10_000_000, steps=2000, seed=2, shape=(256, 128, 128), a0=200.0) 
     zero = np.zeros(n)
     e = _electrons(x[order], y[order], z[order], ux[order], zero, zero.copy())
     return Workload("Yee-grid focused pulse", e, pulse, steps, seed=seed, push_photons=True,
-                    chi_photon_push_min=1e-3, record_photons=True)
+                    chi_photon_push_min=chi_photon_push_min, record_photons=True)
 
 
 def subset(wl: Workload, idx) -> Workload:

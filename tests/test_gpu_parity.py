@@ -1,0 +1,309 @@
+"""GPU parity: the HIP path through the C interface against the oracle.
+
+FP64 form: bit-exact event and particle counts, particle ids and event
+counters; momenta and positions within 1e-12 of max(|value|, 1); FP64 tallies
+within 1e-12 relative.  The step kernels are first run on the oracle's own
+tables (loaded through qed_tables_load) so that the comparison isolates the
+step; the library-built tables are compared with the oracle's separately and
+then used end to end.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O                      # noqa: E402
+from paper_1311_1107_amd import binding as B        # noqa: E402
+from paper_1311_1107_amd import device as D         # noqa: E402
+from paper_1311_1107_amd import sim as S            # noqa: E402
+from paper_1311_1107_amd import workloads as W      # noqa: E402
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from runners import assert_species_match, oracle_run  # noqa: E402
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible: the gpu tests need an MI355X")
+
+
+@pytest.fixture(scope="module")
+def gpu_oracle_tables(oracle_tables):
+    _need_gpu()
+    return D.Tables(O.EMIT_SPEC, O.PAIR_SPEC, arrays=oracle_tables)
+
+
+def _pw_small(seed=11, n=3000, steps=700):
+    # 3000 electrons: 11 full tiles of 256 and a ragged tail of 184
+    return W.plane_wave_beam(n=n, box_lambda=2.0, steps=steps, seed=seed)
+
+
+def _yee_small(seed=12, n=2000, steps=260):
+    return W.yee_beam(n=n, steps=steps, seed=seed, shape=(64, 32, 32), a0=800.0, gamma_median=4000.0,
+                      x_range_lambda=(3.0, 5.0), r_max_lambda=1.0, x_center0=12.0)
+
+
+def _tally_match(got: dict, want: dict, rtol=1e-12):
+    for k, v in want.items():
+        if k.startswith("N_"):
+            assert got[k] == v, f"{k}: {got[k]} != {v}"
+        else:
+            assert got[k] == pytest.approx(v, rel=rtol, abs=1e-300), k
+
+
+# ---------------------------------------------------------------- tables ----
+def test_tables_build_on_device_match_oracle(oracle_tables):
+    _need_gpu()
+    t = D.Tables(O.EMIT_SPEC, O.PAIR_SPEC)
+    got = t.export()
+    for k in ("ln_hrad", "ln_g", "emit_q", "pair_lnh", "pair_q"):
+        assert np.max(np.abs(got[k] - oracle_tables[k])) < 1e-12, k
+
+
+def test_tables_load_roundtrip(oracle_tables, gpu_oracle_tables):
+    got = gpu_oracle_tables.export()
+    for k in ("ln_hrad", "ln_g", "emit_q", "pair_lnh", "pair_q"):
+        assert np.array_equal(got[k], oracle_tables[k]), k
+
+
+def test_initial_optical_depth_matches_oracle():
+    _need_gpu()
+    n = 5000
+    sp = D.Species(n)
+    uid = (np.arange(n, dtype=np.uint64) * np.uint64(7919)) + np.uint64(12345)
+    sp.upload({"x": np.zeros(n), "uid": uid})
+    B.qed_init_optical_depth(sp.struct(), 77)
+    got = sp.download()["tau"]
+    o = O.species_from({"x": np.zeros(n), "uid": uid})
+    O.init_tau(o, 77)
+    assert np.allclose(got, o["tau"][:n], rtol=4e-16, atol=0)
+
+
+# ---------------------------------------------------- plane wave, FP64 ----
+def _compare_run(got, want, rtol=1e-12, tally_rtol=1e-12):
+    for sp in ("electrons", "positrons", "photons", "recorded"):
+        if want.get(sp) is None:
+            continue
+        assert_species_match(got[sp], want[sp], rtol=rtol, what=sp)
+        if "chi" in want[sp] and len(want[sp]["x"]) and sp in ("photons", "recorded"):
+            c = np.abs(got[sp]["chi"] - want[sp]["chi"]) / np.maximum(np.abs(want[sp]["chi"]), 1e-300)
+            assert c.max() <= rtol * 10, sp
+    assert got["uid_next"] == want["uid_next"]
+    _tally_match(got["tally"], want["tally"], tally_rtol)
+
+
+def test_plane_wave_fp64_parity(gpu_oracle_tables, bound_tables):
+    wl = _pw_small()
+    print(f"case: plane wave n=3000 steps=700 seed=11", flush=True)
+    want = oracle_run(wl, bound_tables, wl.steps, record_capacity=16 * 3000)
+    run = S.Run(wl, tables=gpu_oracle_tables, record_capacity=16 * 3000)
+    run.run(wl.steps)
+    got = run.result()
+    assert want["tally"]["N_emit"] > 20000 and want["tally"]["N_sokolov"] > 0
+    _compare_run(got, want)
+    run.ws.status()
+
+
+def test_plane_wave_fp64_with_library_tables(bound_tables):
+    _need_gpu()
+    wl = _pw_small(seed=13, n=1500, steps=600)
+    want = oracle_run(wl, bound_tables, wl.steps, record_capacity=16 * 1500)
+    run = S.Run(wl, record_capacity=16 * 1500)          # tables from qed_tables_build
+    run.run(wl.steps)
+    got = run.result()
+    # independent quadratures agree to ~1e-14, so the runs agree far below 1e-9
+    _compare_run(got, want, rtol=1e-9, tally_rtol=1e-9)
+
+
+def test_schedule_invariance_and_repeatability(gpu_oracle_tables):
+    wl = _pw_small(seed=21, n=2000, steps=400)
+    outs = []
+    for sched in (D.schedule(256, 1, 8), D.schedule(64, 1, 2), D.schedule(128, 1, 31), D.schedule(256, 1, 8)):
+        run = S.Run(wl, tables=gpu_oracle_tables, record_capacity=16 * 2000, sched=sched)
+        run.run(wl.steps)
+        outs.append(run.result())
+    for o in outs[1:]:
+        for sp in ("electrons", "recorded"):
+            for k, v in outs[0][sp].items():
+                assert np.array_equal(v, o[sp][k]), (sp, k)
+        for k, v in outs[0]["tally"].items():
+            if k.startswith("N_"):
+                assert v == o["tally"][k]
+    # same schedule twice: tallies bit-identical too
+    assert outs[0]["tally"] == outs[3]["tally"]
+
+
+def test_capacity_overflow_is_reported(gpu_oracle_tables, bound_tables):
+    wl = _pw_small(seed=31, n=1000, steps=400)
+    cap = 777
+    want = oracle_run(wl, bound_tables, wl.steps, record_capacity=cap)
+    run = S.Run(wl, tables=gpu_oracle_tables, record_capacity=cap)
+    run.run(wl.steps)
+    rc, rep = run.ws.status(raise_on_error=False)
+    assert rc == B.QED_ERR_CAPACITY and rep.flags & 1
+    got = run.result()
+    # the first `cap` photons in serial order are kept, exactly as the oracle keeps them
+    assert_species_match(got["recorded"], want["recorded"], what="recorded")
+    assert got["tally"]["N_rec"] == want["tally"]["N_rec"] > cap
+    # the largest count asked for in one launch is at least the capacity overflowed
+    assert rep.needed[1] > cap
+
+
+def test_empty_and_single_particle(gpu_oracle_tables, bound_tables):
+    _need_gpu()
+    wl = _pw_small(seed=41, n=1, steps=300)
+    want = oracle_run(wl, bound_tables, wl.steps, record_capacity=64)
+    run = S.Run(wl, tables=gpu_oracle_tables, record_capacity=64)
+    run.run(wl.steps)
+    _compare_run(run.result(), want)
+    # no particles at all: every kernel drains its grid and changes nothing
+    wl0 = _pw_small(seed=42, n=1, steps=3)
+    run0 = S.Run(wl0, tables=gpu_oracle_tables, record_capacity=8)
+    run0.el.count.zero_()
+    run0.run(3)
+    r = run0.result()
+    assert r["tally"]["N_mc"] == 0 and r["uid_next"] == 1
+
+
+def test_non_finite_state_is_flagged(gpu_oracle_tables):
+    wl = _pw_small(seed=43, n=300, steps=2)
+    wl.electrons["ux"][5] = np.nan
+    run = S.Run(wl, tables=gpu_oracle_tables, record_capacity=4096)
+    run.run(2)
+    rc, rep = run.ws.status(raise_on_error=False)
+    assert rc == B.QED_ERR_RANGE and rep.flags & 2
+    assert run.result()["tally"]["N_nan"] >= 1
+
+
+# ----------------------------------------------- Yee grid, pairs, FP64 ----
+def test_yee_pairs_fp64_parity(gpu_oracle_tables, bound_tables):
+    wl = _yee_small()
+    print("case: Yee 64x32x32 n=2000 steps=260 seed=12", flush=True)
+    caps = dict(photon_capacity=64 * 2000, record_capacity=8 * 2000, pair_capacity=4 * 2000)
+    want = oracle_run(wl, bound_tables, wl.steps, **caps)
+    assert want["tally"]["N_pair"] > 1000 and want["tally"]["N_cap"] > 0
+    run = S.Run(wl, tables=gpu_oracle_tables, compact_every=7, **caps)
+    run.run(wl.steps)
+    got = run.result()
+    _compare_run(got, want)
+    run.ws.status()
+
+
+# --------------------------------------------------------- batched form ----
+def _bunch_setup(seed=4, n_bunches=6):
+    e, off, a0s, g0s = W.bunches(n_bunches=n_bunches, seed=seed, lo=2.0, hi=3.3)
+    return e, off, a0s
+
+
+def _run_bunches_gpu(tabs, e, off, a0s, steps, batched, prec=B.QED_F64, sched=None, seed=4):
+    n = len(e["x"])
+    units = B.qed_units_init(W.LAMBDA_M)
+    el = D.Species(n, prec)
+    el.upload(e)
+    B.qed_init_optical_depth(el.struct(), seed)
+    rec = D.Species(16 * n, prec)
+    ws = D.Workspace(16 * n)
+    tal = D.Tally((16 * n) // 64 + 2)
+    uid = torch.tensor([n], dtype=torch.int64, device="cuda")
+    nb = len(a0s)
+    d_off = torch.from_numpy(off).cuda()
+    d_a0 = torch.from_numpy(np.ascontiguousarray(a0s)).cuda()
+    d_np = torch.full((nb,), 10.0, dtype=torch.float64, device="cuda")
+    counts = torch.from_numpy(np.diff(off)).cuda()
+    bun = B.qed_bunches(nb, 0, d_off.data_ptr(), d_a0.data_ptr(), d_np.data_ptr())
+    for k in range(steps):
+        st = D.step(k * W.DT, W.DT, seed)
+        if batched:
+            B.qed_push_emit_batched(tabs.h, ws.h, units, -1.0, el.struct(), bun, None, rec.struct(), tal.s, st,
+                                    uid.data_ptr(), sched)
+        else:
+            for b in range(nb):
+                v = el.view(int(off[b]), counts[b:b + 1].data_ptr(), int(off[b + 1] - off[b]))
+                B.qed_push_emit(tabs.h, ws.h, units, -1.0, v, D.plane_wave(float(a0s[b])), None, rec.struct(),
+                                tal.s, st, uid.data_ptr(), sched)
+    torch.cuda.synchronize()
+    return el.download(), rec.download(), tal.reduce(), int(uid.item())
+
+
+def test_batched_matches_per_bunch_and_oracle(gpu_oracle_tables, bound_tables):
+    e, off, a0s = _bunch_setup()
+    steps = 300
+    gb = _run_bunches_gpu(gpu_oracle_tables, e, off, a0s, steps, batched=True)
+    gp = _run_bunches_gpu(gpu_oracle_tables, e, off, a0s, steps, batched=False)
+    for k in gb[0]:
+        assert np.array_equal(gb[0][k], gp[0][k]), k
+    for k in gb[1]:
+        assert np.array_equal(gb[1][k], gp[1][k]), k
+    assert gb[3] == gp[3]
+    # oracle: bunches one after another, each in its own plane wave, one shared photon buffer
+    n = len(e["x"])
+    el = O.species_from(e)
+    O.init_tau(el, 4)
+    rec = O.new_species(16 * n)
+    un = [n]
+    tally = O.Tally()
+    for k in range(steps):
+        st = O.make_step(k * W.DT, W.DT, 4)
+        for b in range(len(a0s)):
+            sub = {kk: el[kk][off[b]:off[b + 1]] for kk in O.FLOAT_KEYS + ("uid", "n_ev")}
+            sub["n"] = int(off[b + 1] - off[b])
+            f = O.make_field(O.FIELD_PLANE_WAVE, a0=float(a0s[b]), n_periods=10.0)
+            O.push_emit(bound_tables, W.LAMBDA_M, -1.0, sub, f, None, rec, st, un, tally)
+    assert_species_match(gb[0], O.view(el), what="electrons")
+    assert_species_match(gb[1], O.view(rec), what="recorded")
+    assert gb[3] == un[0]
+    td = tally.as_dict()
+    assert gb[2]["N_emit"] == td["N_emit"] and gb[2]["N_rec"] == td["N_rec"]
+
+
+# ------------------------------------------------------------ FP32 form ----
+def test_fp32_one_step_within_1e5(gpu_oracle_tables, bound_tables):
+    """One step from identical state (FP64 state rounded to FP32): momenta within 1e-5."""
+    wl = _pw_small(seed=51, n=3000, steps=400)
+    # FP64 oracle to the middle of the pulse, then one more step on both sides
+    mid = oracle_run(wl, bound_tables, 399, record_capacity=16 * 3000)
+    state = {k: v.copy() for k, v in mid["electrons"].items()}
+    wl2 = W.Workload(wl.name, state, wl.field, 1, wl.dt, wl.seed)
+    o = O.species_from(state)
+    o["tau"][:len(state["x"])] = state["tau"]
+    o["n_ev"][:len(state["x"])] = state["n_ev"]
+    st = O.make_step(399 * wl.dt, wl.dt, wl.seed)
+    rec = O.new_species(8 * 3000)
+    O.push_emit(bound_tables, W.LAMBDA_M, -1.0, o, O.make_field(O.FIELD_PLANE_WAVE, a0=100.0), None, rec, st,
+                [10**9], O.Tally())
+    want = O.view(o)
+    run = S.Run(wl2, prec=B.QED_F32, tables=gpu_oracle_tables, record_capacity=8 * 3000)
+    run.el.a["tau"][:3000] = torch.from_numpy(state["tau"]).cuda()
+    run.el.a["n_ev"][:3000] = torch.from_numpy(state["n_ev"].view(np.int32)).cuda()
+    run.step(399)
+    got = run.result()["electrons"]
+    same_events = got["n_ev"] == want["n_ev"]
+    assert same_events.mean() > 0.999
+    u_g = np.stack([got["ux"], got["uy"], got["uz"]], 1).astype(np.float64)[same_events]
+    u_w = np.stack([want["ux"], want["uy"], want["uz"]], 1)[same_events]
+    rel = np.linalg.norm(u_g - u_w, axis=1) / np.maximum(np.linalg.norm(u_w, axis=1), 1.0)
+    print(f"FP32 one-step momentum rel err: max {rel.max():.2e} median {np.median(rel):.2e}", flush=True)
+    assert rel.max() <= 1e-5
+
+
+def test_fp32_spectra_ks(gpu_oracle_tables, bound_tables):
+    from scipy.stats import ks_2samp
+    wl = _pw_small(seed=61, n=3000, steps=700)
+    want = oracle_run(wl, bound_tables, wl.steps, record_capacity=16 * 3000)
+    g_w = np.linalg.norm(np.stack([want["recorded"][k] for k in ("ux", "uy", "uz")], 1), axis=1)
+    for seed in (61, 61 + 1000):
+        wl_s = _pw_small(seed=61, n=3000, steps=700)
+        wl_s.seed = seed
+        run = S.Run(wl_s, prec=B.QED_F32, tables=gpu_oracle_tables, record_capacity=16 * 3000)
+        run.run(wl.steps)
+        r = run.result()["recorded"]
+        g_g = np.linalg.norm(np.stack([r[k] for k in ("ux", "uy", "uz")], 1).astype(np.float64), axis=1)
+        p = ks_2samp(g_g, g_w).pvalue
+        print(f"FP32 photon spectrum KS seed {seed}: p = {p:.3g} ({len(g_g)} vs {len(g_w)})", flush=True)
+        assert p > 0.01
