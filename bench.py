@@ -1,0 +1,233 @@
+"""Throughput of the QED particle step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload yee|plane|batched|cascade]
+
+Default workload: 1e7 electrons (ln gamma0 ~ N(ln 2000, 0.3^2)) colliding with
+a focused a0 = 200 pulse (w0 = 3 lambda, 30 fs) sampled on a 256 x 128 x 128
+FP32 Yee grid, FP64 step, photon emission, photons with chi_gamma > 1e-3 pushed
+and tested for Breit-Wheeler pairs, 2000 steps (the whole collision).
+
+The timed region is K steps from the initial state with every input resident
+in HBM: field sampling onto the grid, electron and positron push/emission,
+photon push/pair creation and periodic compaction.  W warm-up steps run first
+and the state is then reset to the initial one.  The metric counts particles
+advanced per second (leptons plus pushed photons).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=None)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--workload", default="yee", choices=["yee", "plane", "batched", "cascade"])
+    p.add_argument("--electrons", type=int, default=None, help="override the electron count")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-sample", type=int, default=1000, help="electrons in the oracle sample")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="run a 1 GiB device copy first (reference for the traffic counters)")
+    p.add_argument("--compact-every", type=int, default=16)
+    return p.parse_args()
+
+
+def cpu_baseline(wl, n_sample: int, steps: int):
+    """The oracle, single-threaded, on a fixed uid subset of the same workload."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_1311_1107_amd import workloads as W
+
+    n = len(wl.electrons["x"])
+    idx = np.linspace(0, n - 1, min(n_sample, n)).astype(np.int64)
+    sub = W.subset(wl, idx)
+    bt = O.BoundTables(O.compute_tables())
+    m = len(idx)
+    el = O.species_from(sub.electrons, capacity=m * 2)
+    O.init_tau(el, wl.seed)
+    po = O.new_species(m)
+    ph = O.new_species(80 * m) if wl.push_photons else None
+    rec = O.new_species(20 * m) if wl.record_photons else None
+    un = [n]
+    tally = O.Tally()
+    f = wl.field
+    t0 = time.perf_counter()
+    for k in range(steps):
+        if isinstance(f, W.YeePulse):
+            field = O.make_field(O.FIELD_YEE_SEPARABLE, a0=f.a0, shape=f.shape, spacing=f.spacing,
+                                 origin=f.origin, tperp=f.tperp, tpar=f.tpar[k])
+        else:
+            field = O.make_field(O.FIELD_PLANE_WAVE, a0=f.a0, n_periods=f.n_periods)
+        st = O.make_step(k * wl.dt, wl.dt, wl.seed, chi_photon_push_min=wl.chi_photon_push_min)
+        n_ph0 = ph["n"] if ph is not None else 0
+        O.push_emit(bt, W.LAMBDA_M, -1.0, el, field, ph, rec, st, un, tally)
+        O.push_emit(bt, W.LAMBDA_M, +1.0, po, field, ph, rec, st, un, tally)
+        if ph is not None:
+            O.pair_create(bt, W.LAMBDA_M, ph, field, el, po, st, un, tally, n_limit=n_ph0)
+    dt = time.perf_counter() - t0
+    c = tally.as_dict()
+    ps = c["N_mc"] + c["N_sokolov"] + c["N_nan"] + c["N_phstep"]
+    return {"value": ps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{m} electrons (uid subset) of the same workload, {steps} steps, "
+                      f"{ps} particle-steps in {dt:.1f} s, single thread"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1311_1107_amd import binding as B
+    from paper_1311_1107_amd import device as D
+    from paper_1311_1107_amd import sim as S
+    from paper_1311_1107_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    torch.cuda.set_device(0)
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")     # 1 GiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    if args.workload == "yee":
+        wl = W.yee_beam(n=args.electrons or 10_000_000)
+        caps = dict(photon_capacity=42 * len(wl.electrons["x"]), record_capacity=6 * len(wl.electrons["x"]),
+                    pair_capacity=len(wl.electrons["x"]) // 4)
+        prec = B.QED_F64
+        desc = ("1e7 e- (ln gamma0 ~ N(ln 2000, 0.3^2), r <= 2 lambda, x in [20,28) lambda) vs focused pulse "
+                "a0=200 w0=3 lambda 30 fs on a 256x128x128 FP32 Yee grid, TSC gather, FP64, photons with "
+                "chi_gamma>1e-3 pushed + Breit-Wheeler pairs")
+    else:
+        raise SystemExit(f"workload {args.workload}: not wired into bench.py yet")
+    K = args.steps if args.steps is not None else wl.steps
+    K = min(K, wl.steps)
+    n0 = len(wl.electrons["x"])
+
+    run = S.Run(wl, prec=prec, compact_every=args.compact_every, **caps)
+    init = {k: v.clone() for k, v in run.el.a.items()}
+
+    def reset():
+        for k, v in init.items():
+            run.el.a[k].copy_(v)
+        run.el.count.fill_(n0)
+        for sp in (run.po, run.ph, run.rec):
+            if sp is not None:
+                sp.count.zero_()
+        run.uid_next.fill_(n0)
+        run.tally.zero()
+
+    for k in range(args.warmup):
+        run.step(k)
+    torch.cuda.synchronize()
+    reset()
+    torch.cuda.synchronize()
+
+    # per-kernel event timing on the stream the kernels run on
+    stream = torch.cuda.current_stream()
+    kinds = ("fill", "push_e", "push_p", "pair", "compact")
+    evs = {k: [] for k in kinds}
+
+    def timed(kind, fn):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        evs[kind].append((a, b))
+
+    units, tabs = run.units, run.tables
+    pp = run.ph.struct() if run.ph is not None else None
+    pr = run.rec.struct() if run.rec is not None else None
+    uid = run.uid_next.data_ptr()
+
+    def step(n):
+        st = D.step(n * wl.dt, wl.dt, wl.seed, **run.step_kw)
+        if run.grid is not None:
+            timed("fill", lambda: run.fill_field(n))
+        if run.ph is not None:
+            run.ph_snap.copy_(run.ph.count)
+        timed("push_e", lambda: B.qed_push_emit(tabs.h, run.ws.h, units, -1.0, run.el.struct(), run.field, pp, pr,
+                                                run.tally.s, st, uid, run.sched))
+        timed("push_p", lambda: B.qed_push_emit(tabs.h, run.ws.h, units, +1.0, run.po.struct(), run.field, pp, pr,
+                                                run.tally.s, st, uid, run.sched))
+        if run.ph is not None:
+            timed("pair", lambda: B.qed_pair_create(tabs.h, run.ws.h, units, run.ph_step, run.field,
+                                                    run.el.struct(), run.po.struct(), run.tally.s, st, uid,
+                                                    run.sched))
+            if args.compact_every and (n + 1) % args.compact_every == 0:
+                timed("compact", run.compact)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for n in range(K):
+        step(n)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    rc, rep = run.ws.status(raise_on_error=False)
+    tal = run.tally.reduce()
+    counts = run.counts()
+    kernel_ms = {k: sum(a.elapsed_time(b) for a, b in v) for k, v in evs.items() if v}
+    n_launch = {k: len(v) for k, v in evs.items() if v}
+
+    lepton_steps = tal["N_mc"] + tal["N_sokolov"] + tal["N_nan"]
+    photon_steps = tal["N_phstep"]
+    psteps = lepton_steps + photon_steps
+    # algorithmic bytes (FP64): lepton x,u read+write 96 B, tau read+write 16 B, weight 8 B;
+    # per emission uid/n_event 16 B; per stored photon 84 B written.
+    # photon step: x,k,tau read 56 B, x,tau written 32 B; per pair 20 B read + 2 x 84 B written.
+    es = 8 if prec == B.QED_F64 else 4
+    lep_bytes = lepton_steps * (12 * es + 16 + es) + tal["N_emit"] * 16 + (tal["N_push"] + tal["N_rec"]) * (10 * es + 12)
+    ph_bytes = photon_steps * (7 * es + 8 + 3 * es + 8) + tal["N_pair"] * (20 + 2 * (10 * es + 12))
+    push_ms = kernel_ms.get("push_e", 0) + kernel_ms.get("push_p", 0)
+    pair_ms = kernel_ms.get("pair", 0)
+    if pair_ms >= push_ms:
+        dom, dom_bytes, dom_ms, dom_n = "qed_pair_create (photon step)", ph_bytes, pair_ms, n_launch.get("pair", 1)
+    else:
+        dom, dom_bytes, dom_ms = "qed_push_emit (lepton step)", lep_bytes, push_ms
+        dom_n = n_launch.get("push_e", 1)
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
+
+    out = {
+        "metric": "QED particle-steps/s",
+        "value": psteps / wall,
+        "unit": "particle-steps/s",
+        "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / K,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == B.QED_F64 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "electrons": n0, "grid": list(wl.field.shape) if hasattr(wl.field, "shape") else None,
+                   "steps_timed": K, "dt": wl.dt, "compact_every": args.compact_every},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": dom_bytes / max(dom_n, 1), "avg_launch_ms": dom_ms / max(dom_n, 1)},
+        "detail": {"lepton_steps": lepton_steps, "photon_steps": photon_steps, "kernel_ms": kernel_ms,
+                   "launches": n_launch, "final_counts": counts, "emissions": tal["N_emit"], "pairs": tal["N_pair"],
+                   "status": int(rc), "lepton_bytes": lep_bytes, "photon_bytes": ph_bytes},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample, K)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

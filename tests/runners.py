@@ -46,20 +46,23 @@ def oracle_run(wl, tabs: O.BoundTables, steps: int, photon_capacity=None, record
 
 
 def assert_species_match(got: dict, want: dict, rtol=1e-12, what="", exact_keys=("uid", "n_ev")):
-    """Element-wise comparison: integers bit-exact; momenta and positions to rtol
-    relative to max(|value|, 1)."""
+    """Element-wise comparison: integers bit-exact; each momentum and position
+    vector within rtol of max(norm, 1); weights exact."""
     n = len(want["x"])
     assert len(got["x"]) == n, f"{what}: count {len(got['x'])} != {n}"
     for k in exact_keys:
         if k in want:
             bad = np.nonzero(got[k] != want[k])[0]
             assert bad.size == 0, f"{what}: {k} differs at {bad[:5]} ({got[k][bad[:5]]} vs {want[k][bad[:5]]})"
-    for k in ("x", "y", "z", "ux", "uy", "uz", "w"):
-        g, w_ = np.asarray(got[k], np.float64), np.asarray(want[k], np.float64)
-        scale = np.maximum(np.abs(w_), 1.0)
-        err = np.abs(g - w_) / scale
+    # vectors (position, momentum) relative to their norm, floored at 1
+    for keys in (("x", "y", "z"), ("ux", "uy", "uz")):
+        g = np.stack([np.asarray(got[k], np.float64) for k in keys], 1)
+        w_ = np.stack([np.asarray(want[k], np.float64) for k in keys], 1)
+        err = np.linalg.norm(g - w_, axis=1) / np.maximum(np.linalg.norm(w_, axis=1), 1.0)
         i = int(np.argmax(err)) if n else 0
-        assert n == 0 or err[i] <= rtol, f"{what}: {k} rel err {err[i]:.3e} at {i}: {g[i]!r} vs {w_[i]!r}"
+        assert n == 0 or err[i] <= rtol, f"{what}: {keys} rel err {err[i]:.3e} at {i}: {g[i]!r} vs {w_[i]!r}"
+    g, w_ = np.asarray(got["w"], np.float64), np.asarray(want["w"], np.float64)
+    assert np.array_equal(g, w_), f"{what}: weights differ"
     if "tau" in want:
         g, w_ = got["tau"], want["tau"]
         err = np.abs(g - w_) / np.maximum(np.abs(w_), 1.0)
