@@ -219,13 +219,17 @@ qed_status qed_tally_reduce(const qed_tally *t, double energy[QED_N_ENERGY] /* [
                             int64_t count[QED_N_COUNT] /* [host] */, void *stream);
 
 /* ------------------------------------------------------------------------ *
- * Workspace: tile-status words of the decoupled look-back used for stable
- * appends, launch tickets and the sticky device status.  One workspace per
- * stream; calls sharing a workspace must not overlap in time.
+ * Workspace: per-tile append counts and their prefixes, emission records
+ * handed from the physics pass to the append pass, look-back words and
+ * tickets of the scan and compaction kernels, and the sticky device status.
+ * max_particles bounds the capacity of any species passed with it;
+ * max_leptons bounds the capacity of the lepton species given to
+ * qed_push_emit (emission records take about 124 bytes per lepton).  One
+ * workspace per stream; calls sharing a workspace must not overlap in time.
  * ------------------------------------------------------------------------ */
 typedef struct qed_workspace qed_workspace;
 
-qed_status qed_workspace_create(int64_t max_particles, qed_workspace **out);
+qed_status qed_workspace_create(int64_t max_particles, int64_t max_leptons, qed_workspace **out);
 void qed_workspace_free(qed_workspace *ws);
 
 typedef struct {

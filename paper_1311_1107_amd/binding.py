@@ -99,7 +99,7 @@ _SIGS = {
     "qed_init_optical_depth": ([_P(qed_species), C.c_uint64, _vp], C.c_int32),
     "qed_yee_fill_separable": ([_vp, C.c_int64, C.c_int64, C.c_int64, C.c_double, _vp, _vp, _vp], C.c_int32),
     "qed_tally_reduce": ([_P(qed_tally), _dp, _P(C.c_int64), _vp], C.c_int32),
-    "qed_workspace_create": ([C.c_int64, _P(_vp)], C.c_int32),
+    "qed_workspace_create": ([C.c_int64, C.c_int64, _P(_vp)], C.c_int32),
     "qed_workspace_free": ([_vp], None),
     "qed_sync_status": ([_vp, _P(qed_status_report), C.c_int32, _vp], C.c_int32),
     "qed_push_emit": ([_vp, _vp, _P(qed_units), C.c_double, _P(qed_species), _P(qed_field),
@@ -201,9 +201,9 @@ def qed_tables_free(handle):
     lib().qed_tables_free(handle)
 
 
-def qed_workspace_create(max_particles: int) -> C.c_void_p:
+def qed_workspace_create(max_particles: int, max_leptons: int) -> C.c_void_p:
     h = C.c_void_p()
-    _check(lib().qed_workspace_create(int(max_particles), C.byref(h)))
+    _check(lib().qed_workspace_create(int(max_particles), int(max_leptons), C.byref(h)))
     return h
 
 

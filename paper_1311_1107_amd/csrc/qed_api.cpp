@@ -60,9 +60,14 @@ struct qed_workspace {
     int device;
     int n_cu;
     int64_t max_tiles;
+    int64_t max_leptons;
     uint64_t *d_ticket;
     uint64_t *d_lb;
     unsigned long long *d_status;
+    uint32_t *d_tiles;        // tile counts and prefixes, 4 * max_tiles
+    qed::LaunchInfo *d_info;
+    void *d_rec;              // emission records
+    uint32_t *d_meta, *d_nrec;
     qed::WsDev dev;
 };
 
@@ -179,20 +184,26 @@ void qed_tables_free(qed_tables *t) {
 }
 
 // --------------------------------------------------------------- workspace --
-qed_status qed_workspace_create(int64_t max_particles, qed_workspace **out) {
+qed_status qed_workspace_create(int64_t max_particles, int64_t max_leptons, qed_workspace **out) {
     if (!out) return fail(QED_ERR_ARG, "qed_workspace_create: null out");
     *out = nullptr;
-    if (max_particles < 1 || max_particles > (int64_t)1 << 40)
-        return fail(QED_ERR_ARG, "qed_workspace_create: max_particles out of range");
+    if (max_particles < 1 || max_particles > (int64_t)1 << 40 || max_leptons < 0 || max_leptons > max_particles)
+        return fail(QED_ERR_ARG, "qed_workspace_create: need 1 <= max_particles <= 2^40, 0 <= max_leptons <= max_particles");
     qed_workspace *w = new qed_workspace();
     HIP_TRY(hipGetDevice(&w->device));
     HIP_TRY(hipDeviceGetAttribute(&w->n_cu, hipDeviceAttributeMultiprocessorCount, w->device));
     // smallest tile is 64 threads x 1 particle
     w->max_tiles = (max_particles + 63) / 64 + 1;
+    w->max_leptons = max_leptons;
     if (w->max_tiles > 0xffffffffll) { delete w; return fail(QED_ERR_ARG, "qed_workspace_create: too many tiles"); }
+    const int64_t slots = ((max_leptons + 255) / 256 + 1) * 256;
     if (hipMalloc(&w->d_ticket, 64) != hipSuccess || hipMalloc(&w->d_lb, sizeof(uint64_t) * 4 * w->max_tiles) != hipSuccess ||
-        hipMalloc(&w->d_status, 64) != hipSuccess) {
-        delete w;
+        hipMalloc(&w->d_status, 64) != hipSuccess || hipMalloc(&w->d_tiles, sizeof(uint32_t) * 4 * w->max_tiles) != hipSuccess ||
+        hipMalloc(&w->d_info, sizeof(qed::LaunchInfo)) != hipSuccess ||
+        hipMalloc(&w->d_rec, sizeof(double) * qed::kRecReals * slots) != hipSuccess ||
+        hipMalloc(&w->d_meta, sizeof(uint32_t) * slots) != hipSuccess ||
+        hipMalloc(&w->d_nrec, sizeof(uint32_t) * w->max_tiles) != hipSuccess) {
+        qed_workspace_free(w);
         return fail(QED_ERR_NOMEM, "qed_workspace_create: device allocation failed");
     }
     // epoch 1 in the ticket's high word: zeroed look-back words (epoch 0) never match
@@ -201,12 +212,23 @@ qed_status qed_workspace_create(int64_t max_particles, qed_workspace **out) {
     HIP_TRY(hipMemcpy(w->d_ticket, ticket0, 64, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(w->d_lb, zeros.data(), sizeof(uint64_t) * 4 * w->max_tiles, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(w->d_status, zeros.data(), 64, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(w->d_nrec, zeros.data(), sizeof(uint32_t) * w->max_tiles, hipMemcpyHostToDevice));
     w->dev.ticket = w->d_ticket;
     w->dev.lb.agg0 = w->d_lb;
     w->dev.lb.agg1 = w->d_lb + w->max_tiles;
     w->dev.lb.inc0 = w->d_lb + 2 * w->max_tiles;
     w->dev.lb.inc1 = w->d_lb + 3 * w->max_tiles;
     w->dev.status = w->d_status;
+    w->dev.tile_cnt0 = w->d_tiles;
+    w->dev.tile_cnt1 = w->d_tiles + w->max_tiles;
+    w->dev.tile_pre0 = w->d_tiles + 2 * w->max_tiles;
+    w->dev.tile_pre1 = w->d_tiles + 3 * w->max_tiles;
+    w->dev.info = w->d_info;
+    w->dev.stage.rec = w->d_rec;
+    w->dev.stage.meta = w->d_meta;
+    w->dev.stage.n_rec = w->d_nrec;
+    w->dev.stage.slots = slots;
+    w->dev.max_tiles = w->max_tiles;
     *out = w;
     return QED_OK;
 }
@@ -216,6 +238,11 @@ void qed_workspace_free(qed_workspace *w) {
     (void)hipFree(w->d_ticket);
     (void)hipFree(w->d_lb);
     (void)hipFree(w->d_status);
+    (void)hipFree(w->d_tiles);
+    (void)hipFree(w->d_info);
+    (void)hipFree(w->d_rec);
+    (void)hipFree(w->d_meta);
+    (void)hipFree(w->d_nrec);
     delete w;
 }
 
@@ -321,6 +348,8 @@ qed_status consts_dev(const qed_units *u, double q, qed::ConstsDev &c) {
     return QED_OK;
 }
 
+// Launch shape of the physics passes: a persistent grid whose size is a
+// multiple of 8 (one share per XCD).
 qed_status shape(const qed_workspace *w, const qed_schedule *s, int64_t capacity, dim3 &grid, dim3 &block) {
     int b = 256, ipt = 1, bpc = 8;
     if (s) {
@@ -334,10 +363,18 @@ qed_status shape(const qed_workspace *w, const qed_schedule *s, int64_t capacity
     const int64_t tiles = (capacity + b - 1) / b;
     if (tiles + 1 > w->max_tiles) return fail(QED_ERR_ARG, "workspace too small for %lld particles", (long long)capacity);
     int64_t g = (int64_t)w->n_cu * bpc;
-    g = std::max<int64_t>(1, std::min<int64_t>(g, tiles));
+    g = std::min<int64_t>(g, ((tiles + 7) / 8) * 8);
+    g = std::max<int64_t>(8, (g / 8) * 8);
     grid = dim3((unsigned)g);
     block = dim3((unsigned)b);
     return QED_OK;
+}
+
+// Grid of the scan pass: one block per 4096 tile counts, at most one per CU.
+dim3 scan_grid(const qed_workspace *w, int64_t capacity, int64_t tile_sz) {
+    const int64_t tiles = (capacity + tile_sz - 1) / tile_sz;
+    const int64_t blocks = (tiles + 4095) / 4096;
+    return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks, w->n_cu)));
 }
 
 }  // namespace
@@ -390,9 +427,26 @@ static qed_status push_common(const qed_tables *tab, qed_workspace *ws, const qe
     a.f = fd;
     a.ws = ws->dev;
     a.uid_next = uid_next;
+    if (lep->capacity > ws->max_leptons)
+        return fail(QED_ERR_ARG, "qed_push_emit: %lld leptons exceed the workspace's max_leptons %lld",
+                    (long long)lep->capacity, (long long)ws->max_leptons);
     dim3 grid, block;
     if ((s = shape(ws, sched, lep->capacity, grid, block))) return s;
-    HIP_TRY(qed::launch_push_emit(a, lep->prec, fk, grid, block, (hipStream_t)stream));
+    a.tile_sz = block.x;
+    hipStream_t st_ = (hipStream_t)stream;
+    // physics pass, scan of the per-tile photon counts, photon appends
+    HIP_TRY(qed::launch_push_emit(a, lep->prec, fk, grid, block, st_));
+    qed::ScanArgs sc;
+    std::memset(&sc, 0, sizeof sc);
+    sc.src_count = lep->d_count;
+    sc.tile_sz = block.x;
+    sc.d0 = a.pp;
+    sc.d1 = a.pr;
+    sc.uid_next = uid_next;
+    sc.mode = 0;
+    sc.ws = ws->dev;
+    HIP_TRY(qed::launch_scan_tiles(sc, scan_grid(ws, lep->capacity, block.x), st_));
+    HIP_TRY(qed::launch_push_append(a, lep->prec, grid, dim3(256), st_));
     return QED_OK;
 }
 
@@ -446,7 +500,21 @@ qed_status qed_pair_create(const qed_tables *tab, qed_workspace *ws, const qed_u
     a.uid_next = d_uid_next;
     dim3 grid, block;
     if ((s = shape(ws, sched, ph->capacity, grid, block))) return s;
-    HIP_TRY(qed::launch_pair_create(a, ph->prec, fk, grid, block, (hipStream_t)stream));
+    a.tile_sz = block.x;
+    hipStream_t st_ = (hipStream_t)stream;
+    // physics pass, scan of the per-tile pair counts, pair appends
+    HIP_TRY(qed::launch_pair_create(a, ph->prec, fk, grid, block, st_));
+    qed::ScanArgs sc;
+    std::memset(&sc, 0, sizeof sc);
+    sc.src_count = ph->d_count;
+    sc.tile_sz = block.x;
+    sc.d0 = a.el;
+    sc.d1 = a.po;
+    sc.uid_next = d_uid_next;
+    sc.mode = 1;
+    sc.ws = ws->dev;
+    HIP_TRY(qed::launch_scan_tiles(sc, scan_grid(ws, ph->capacity, block.x), st_));
+    HIP_TRY(qed::launch_pair_append(a, ph->prec, fk, grid, dim3(256), st_));
     return QED_OK;
 }
 

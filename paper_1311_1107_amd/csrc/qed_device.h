@@ -285,6 +285,28 @@ __device__ __forceinline__ void block_scan2(uint32_t c0, uint32_t c1, uint32_t &
     tot0 = t0; tot1 = t1;
 }
 
+// Exclusive rank of a 0/1 flag and the block totals of the flag and of two
+// counts (block <= 256 threads); s_wave holds 3*kMaxWaves words.
+__device__ __forceinline__ void block_rank3(bool f, uint32_t c0, uint32_t c1, uint32_t &rank,
+                                            uint32_t &tf, uint32_t &t0, uint32_t &t1, uint32_t *s_wave) {
+    uint32_t wf;
+    const uint32_t x = ballot_excl(f, wf);
+    const uint32_t w0 = wave_sum_u32(c0), w1 = wave_sum_u32(c1);
+    const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (lane_id() == 0) { s_wave[wid] = wf; s_wave[kMaxWaves + wid] = w0; s_wave[2 * kMaxWaves + wid] = w1; }
+    __syncthreads();
+    uint32_t o = 0, a = 0, b = 0, c = 0;
+    for (int k = 0; k < nw; ++k) {
+        const uint32_t v = s_wave[k];
+        if (k < wid) o += v;
+        a += v;
+        b += s_wave[kMaxWaves + k];
+        c += s_wave[2 * kMaxWaves + k];
+    }
+    rank = o + x;
+    tf = a; t0 = b; t1 = c;
+}
+
 // Same for 0/1 flags, using the wave ballot.
 __device__ __forceinline__ void block_scan_flag(bool f, uint32_t &e, uint32_t &tot, uint32_t *s_wave) {
     uint32_t w;

@@ -48,10 +48,34 @@ struct ConstsDev {
     double q, es_inv, A, tau0;
 };
 
+// Emission records written by the physics pass for the append pass: one per
+// particle that stored photons in the step, at slot tile * tile_size + rank.
+// Reals (SoA, stride `slots`): 0-2 position x^n, 3-5 direction u_hat, 6 weight,
+// 7-10 gamma_gamma of each event, 11-14 chi_gamma of each event.
+constexpr int kRecReals = 15;
+struct StageDev {
+    void *rec;                       // kRecReals * slots reals (double or float)
+    uint32_t *meta;                  // per record: events (bits 0-2), destination of event k (2 bits at 3+2k)
+    uint32_t *n_rec;                 // per tile
+    int64_t slots;
+};
+
+// Written by the scan pass for the append pass of the same launch.
+struct LaunchInfo {
+    int64_t base0, base1;            // counts of the two destination buffers before the launch
+    uint64_t uid0;                   // first id handed out by the launch
+    int64_t pad;
+};
+
 struct WsDev {
     uint64_t *ticket;
     LookBack lb;
     unsigned long long *status;      // [0] flags, [1..4] needed counts, [5] spare
+    uint32_t *tile_cnt0, *tile_cnt1; // per physics tile: appends to buffers 0 and 1
+    uint32_t *tile_pre0, *tile_pre1; // their exclusive prefixes over tiles
+    LaunchInfo *info;
+    StageDev stage;
+    int64_t max_tiles;
 };
 
 struct TallyDev {
@@ -62,6 +86,7 @@ struct TallyDev {
 
 struct PushArgs {
     TablesDev tab;
+    int64_t tile_sz;                 // tile of the physics pass (its block size)
     SpeciesDev lep, pp, pr;
     FieldDev f;
     StepDev st;
@@ -73,6 +98,7 @@ struct PushArgs {
 
 struct PairArgs {
     TablesDev tab;
+    int64_t tile_sz;
     SpeciesDev ph, el, po;
     FieldDev f;
     StepDev st;
@@ -87,8 +113,24 @@ struct CompactArgs {
     WsDev ws;
 };
 
+// Scan pass: prefixes of the per-tile append counts of the physics pass that
+// ran over the `src` species with tiles of tile_sz; mode 0 appends photons
+// (buffer 0 pushed, buffer 1 recorded, one id each), mode 1 appends pairs
+// (one electron in buffer 0 and one positron in buffer 1 per event, two ids).
+struct ScanArgs {
+    const int64_t *src_count;
+    int64_t tile_sz;
+    SpeciesDev d0, d1;
+    uint64_t *uid_next;
+    int mode;
+    WsDev ws;
+};
+
 hipError_t launch_push_emit(const PushArgs &a, int prec, int fk, dim3 grid, dim3 block, hipStream_t s);
 hipError_t launch_pair_create(const PairArgs &a, int prec, int fk, dim3 grid, dim3 block, hipStream_t s);
+hipError_t launch_scan_tiles(const ScanArgs &a, dim3 grid, hipStream_t s);
+hipError_t launch_push_append(const PushArgs &a, int prec, dim3 grid, dim3 block, hipStream_t s);
+hipError_t launch_pair_append(const PairArgs &a, int prec, int fk, dim3 grid, dim3 block, hipStream_t s);
 hipError_t launch_compact(const CompactArgs &a, int prec, dim3 grid, dim3 block, hipStream_t s);
 hipError_t launch_init_tau(const uint64_t *uid, double *tau, const int64_t *count, uint64_t seed,
                            int n_blocks, hipStream_t s);

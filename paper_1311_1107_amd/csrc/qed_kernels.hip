@@ -171,6 +171,21 @@ __device__ __forceinline__ void block_counts(const TallyDev &tal, int (&c)[N_COU
 }
 
 // ------------------------------------------------------------------------
+// Physics passes walk the tiles of a launch with a persistent grid.  The tile
+// range is cut into eight contiguous pieces, one per XCD (the dispatcher deals
+// block ids to the eight XCDs in turn), so that each XCD's L2 serves a compact
+// run of particles.  Tiles are independent here: appends are placed later by
+// the scan and append passes, so no tile waits for another.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ int64_t xcd_tile(int64_t it, int64_t n_tiles) {
+    const int64_t g8 = gridDim.x >> 3;             // the grid is a multiple of 8
+    const int64_t x = blockIdx.x & 7, l = blockIdx.x >> 3;
+    const int64_t lo = n_tiles * x / 8, hi = n_tiles * (x + 1) / 8;
+    const int64_t t = lo + l + it * g8;
+    return t < hi ? t : -1;
+}
+
+// ------------------------------------------------------------------------
 // Lepton step: Boris push, chi_e, Sokolov or optical-depth Monte Carlo.
 // ------------------------------------------------------------------------
 // Emissions of one particle in one step, kept in registers: slots are written
@@ -189,14 +204,14 @@ struct Emitted {
     }
 };
 
+// Physics pass of the lepton step.  Writes each particle's new state, and for
+// particles that store photons an emission record for the append pass.
 template <typename R, int FK>
 __global__ void __launch_bounds__(256)
 k_push_emit(PushArgs a) {
     __shared__ R s_lh[kMaxChiNodes];
     __shared__ R s_lg[kMaxChiNodes];
-    __shared__ uint64_t s_ticket;
-    __shared__ uint32_t s_wave[2 * kMaxWaves];
-    __shared__ uint32_t s_pref[2];
+    __shared__ uint32_t s_wave[3 * kMaxWaves];
     __shared__ int64_t s_b0;
     __shared__ double s_red[kNEnergy * kMaxWaves];
     __shared__ int64_t s_cnt[N_COUNT_USED];
@@ -208,9 +223,6 @@ k_push_emit(PushArgs a) {
         s_lg[i] = (R)tb.ln_g[i];
     }
     const int64_t n = *a.lep.count;
-    const int64_t base0 = a.pp.present ? *a.pp.count : 0;
-    const int64_t base1 = a.pr.present ? *a.pr.count : 0;
-    const uint64_t uid0 = *a.uid_next;
     const double t = a.st.d_step ? a.st.t + (double)(*a.st.d_step) * a.st.dt : a.st.t;
     const double dt = a.st.dt;
     const R dtr = (R)dt;
@@ -224,17 +236,19 @@ k_push_emit(PushArgs a) {
     R *X = (R *)a.lep.x, *Y = (R *)a.lep.y, *Z = (R *)a.lep.z;
     R *UX = (R *)a.lep.ux, *UY = (R *)a.lep.uy, *UZ = (R *)a.lep.uz;
     const R *Wt = (const R *)a.lep.w;
+    R *rec = (R *)a.ws.stage.rec;
+    const int64_t slots = a.ws.stage.slots;
     int cnt[N_COUNT_USED];
 #pragma unroll
     for (int k = 0; k < N_COUNT_USED; ++k) cnt[k] = 0;
     __syncthreads();
 
-    for (;;) {
-        if (tid == 0) {
-            s_ticket = atomicAdd((unsigned long long *)a.ws.ticket, 1ull);
-            if (FK == FIELD_BUNCHED) {
-                // bunch of the tile's first particle
-                const int64_t first = (int64_t)(s_ticket & 0xffffffffull) * tile_sz;
+    for (int64_t it = 0;; ++it) {
+        const int64_t tile = xcd_tile(it, n_tiles);
+        if (tile < 0) break;
+        if (FK == FIELD_BUNCHED) {
+            if (tid == 0) {
+                const int64_t first = tile * tile_sz;
                 int lo = 0, hi = a.f.n_bunches;     // offsets[lo] <= first < offsets[hi]
                 while (hi - lo > 1) {
                     const int mid = (lo + hi) >> 1;
@@ -242,34 +256,8 @@ k_push_emit(PushArgs a) {
                 }
                 s_b0 = lo;
             }
+            __syncthreads();
         }
-        __syncthreads();
-        const uint64_t tk = s_ticket;
-        const uint32_t epoch = (uint32_t)(tk >> 32);
-        const int64_t tile = (int64_t)(tk & 0xffffffffull);
-        if (tile >= n_tiles) {
-            if (tid == 0 && tile == n_tiles + (int64_t)gridDim.x - 1) {
-                if (n_tiles > 0) {
-                    uint32_t t0, t1;
-                    lb_wait_inclusive(a.ws.lb, n_tiles - 1, epoch, t0, t1);
-                    if (a.pp.present) {
-                        int64_t want = base0 + (int64_t)t0;
-                        if (want > a.pp.cap) { status_flag(a.ws.status, 1ull); status_need(a.ws.status, 0, want); want = a.pp.cap; }
-                        *a.pp.count = want;
-                    }
-                    if (a.pr.present) {
-                        int64_t want = base1 + (int64_t)t1;
-                        if (want > a.pr.cap) { status_flag(a.ws.status, 1ull); status_need(a.ws.status, 1, want); want = a.pr.cap; }
-                        *a.pr.count = want;
-                    }
-                    *a.uid_next = uid0 + (uint64_t)t0 + (uint64_t)t1;
-                }
-                atomicAdd((unsigned long long *)a.ws.ticket,
-                          (1ull << 32) - (unsigned long long)(n_tiles + (int64_t)gridDim.x));
-            }
-            break;
-        }
-
         const int64_t i = tile * tile_sz + tid;
         const bool live = i < n;
         double en[kNEnergy];
@@ -277,17 +265,12 @@ k_push_emit(PushArgs a) {
         for (int k = 0; k < kNEnergy; ++k) en[k] = 0.0;
         Emitted<R> em;
         em.n = 0;
-        R x = R(0), y = R(0), z = R(0), ux = R(0), uy = R(0), uz = R(0);
-        R nx_ = R(0), ny_ = R(0), nz_ = R(0);       // updated position
+        R x = R(0), y = R(0), z = R(0);
         R uhx = R(0), uhy = R(0), uhz = R(0);       // photon direction
-        double tau = 0.0;
-        uint32_t nev = 0;
-        uint64_t uid = 0;
         R wgt = R(0);
-        bool mc_taken = false;
         if (live) {
             x = X[i]; y = Y[i]; z = Z[i];
-            ux = UX[i]; uy = UY[i]; uz = UZ[i];
+            const R ux = UX[i], uy = UY[i], uz = UZ[i];
             double a0 = a.f.a0, Phi = a.f.Phi;
             if (FK == FIELD_BUNCHED) {
                 int64_t b = s_b0;
@@ -348,7 +331,6 @@ k_push_emit(PushArgs a) {
             } else if (rad == RAD_MC || rad == RAD_HYBRID) {
                 // optical-depth Monte Carlo, Eqs. 6-8
                 cnt[C_MC]++;
-                mc_taken = true;
                 R p = Math<R>::sqrt_(uLx * uLx + uLy * uLy + uLz * uLz);
                 if (p > R(0)) { uhx = uLx / p; uhy = uLy / p; uhz = uLz / p; }
                 R gam = gL, ce = chi;
@@ -358,8 +340,10 @@ k_push_emit(PushArgs a) {
                     W = Ah * Math<R>::exp_(lerp_rate<R>(s_lh, tb.e_n_chi, lnchi0, inv_d, Math<R>::log_(ce), above)) / gam;
                     if (above) cnt[C_RANGE]++;
                 }
-                tau = a.lep.tau[i];
+                double tau = a.lep.tau[i];
                 double t_left = dt;
+                uint32_t nev = 0;
+                uint64_t uid = 0;
                 int k = 0;
                 for (;;) {
                     const double Wd = (double)W;
@@ -403,58 +387,42 @@ k_push_emit(PushArgs a) {
                     ++nev;
                     ++k;
                 }
-                if (em.n > 0) { unx = p * uhx; uny = p * uhy; unz = p * uhz; }
+                if (em.n > 0) { unx = p * uhx; uny = p * uhy; unz = p * uhz; a.lep.n_ev[i] = nev; }
+                a.lep.tau[i] = tau;
             }
             const R gn = Math<R>::sqrt_(R(1) + (unx * unx + uny * uny + unz * unz));
-            nx_ = x + dtr * (unx / gn + dvx);
-            ny_ = y + dtr * (uny / gn + dvy);
-            nz_ = z + dtr * (unz / gn + dvz);
-            ux = unx; uy = uny; uz = unz;
+            X[i] = x + dtr * (unx / gn + dvx);
+            Y[i] = y + dtr * (uny / gn + dvy);
+            Z[i] = z + dtr * (unz / gn + dvz);
+            UX[i] = unx; UY[i] = uny; UZ[i] = unz;
         }
 
-        // --- stable append of the stored photons --------------------------
-        uint32_t c0 = 0, c1 = 0;
+        // --- emission record and the tile's append counts -----------------
+        uint32_t c0 = 0, c1 = 0, meta = (uint32_t)em.n;
 #pragma unroll
         for (int k = 0; k < kMaxEvents; ++k)
-            if (k < em.n) { c0 += em.dst[k] == 0; c1 += em.dst[k] == 1; }
-        uint32_t e0, e1, tot0, tot1;
-        block_scan2(c0, c1, e0, e1, tot0, tot1, s_wave);
-        if (tid < kWave) {
-            uint32_t p0, p1;
-            lookback2(a.ws.lb, tile, epoch, tot0, tot1, p0, p1);
-            if (tid == 0) { s_pref[0] = p0; s_pref[1] = p1; }
-        }
-        __syncthreads();
-
-        if (live) {
-            X[i] = nx_; Y[i] = ny_; Z[i] = nz_;
-            UX[i] = ux; UY[i] = uy; UZ[i] = uz;
-            if (mc_taken) a.lep.tau[i] = tau;
-            if (em.n > 0) a.lep.n_ev[i] = nev;
-            uint32_t g0 = s_pref[0] + e0, g1 = s_pref[1] + e1;
-#pragma unroll
-            for (int k = 0; k < kMaxEvents; ++k) {
-                if (k >= em.n) break;
-                const uint8_t d = em.dst[k];
-                if (d > 1) continue;
-                const uint64_t nid = uid0 + (uint64_t)g0 + (uint64_t)g1;
-                const SpeciesDev &S = d == 0 ? a.pp : a.pr;
-                const int64_t j = (d == 0 ? base0 + (int64_t)g0 : base1 + (int64_t)g1);
-                if (d == 0) ++g0; else ++g1;
-                if (j >= S.cap) { cnt[C_LOST]++; continue; }
-                const R gg = em.gg[k];
-                ((R *)S.x)[j] = x + dtr * uhx;
-                ((R *)S.y)[j] = y + dtr * uhy;
-                ((R *)S.z)[j] = z + dtr * uhz;
-                ((R *)S.ux)[j] = gg * uhx;
-                ((R *)S.uy)[j] = gg * uhy;
-                ((R *)S.uz)[j] = gg * uhz;
-                ((R *)S.w)[j] = wgt;
-                if (S.chi) ((R *)S.chi)[j] = em.chig[k];
-                S.uid[j] = nid;
-                S.n_ev[j] = 0u;
-                S.tau[j] = initial_tau(a.st.seed, nid);
+            if (k < em.n) {
+                c0 += em.dst[k] == 0;
+                c1 += em.dst[k] == 1;
+                meta |= (uint32_t)em.dst[k] << (3 + 2 * k);
             }
+        const bool has = (c0 + c1) > 0;
+        uint32_t rank, n_rec, tot0, tot1;
+        block_rank3(has, c0, c1, rank, n_rec, tot0, tot1, s_wave);
+        if (has) {
+            const int64_t sl = tile * tile_sz + rank;
+            rec[0 * slots + sl] = x; rec[1 * slots + sl] = y; rec[2 * slots + sl] = z;
+            rec[3 * slots + sl] = uhx; rec[4 * slots + sl] = uhy; rec[5 * slots + sl] = uhz;
+            rec[6 * slots + sl] = wgt;
+#pragma unroll
+            for (int k = 0; k < kMaxEvents; ++k)
+                if (k < em.n) { rec[(7 + k) * slots + sl] = em.gg[k]; rec[(11 + k) * slots + sl] = em.chig[k]; }
+            a.ws.stage.meta[sl] = meta;
+        }
+        if (tid == 0) {
+            a.ws.tile_cnt0[tile] = tot0;
+            a.ws.tile_cnt1[tile] = tot1;
+            a.ws.stage.n_rec[tile] = n_rec;
         }
         tile_energy<kNEnergy>(a.tal, tile, atomic_slots, en, s_red);
         __syncthreads();
@@ -463,16 +431,198 @@ k_push_emit(PushArgs a) {
 }
 
 // ------------------------------------------------------------------------
+// Scan pass: exclusive prefixes of the physics pass's per-tile append counts
+// (decoupled look-back over blocks of kScanItems x 256 counts, taken in ticket
+// order).  The launch's final requester records the destination buffers'
+// counts and the first id for the append pass, then advances them.
+// ------------------------------------------------------------------------
+constexpr int kScanItems = 16;
+
+__global__ void __launch_bounds__(256)
+k_scan_tiles(ScanArgs a) {
+    __shared__ uint64_t s_ticket;
+    __shared__ uint32_t s_wave[2 * kMaxWaves];
+    __shared__ uint32_t s_pref[2];
+    const int tid = threadIdx.x;
+    const int64_t n = *a.src_count;
+    const int64_t n_tiles = (n + a.tile_sz - 1) / a.tile_sz;
+    const int64_t per = (int64_t)blockDim.x * kScanItems;
+    const int64_t n_st = (n_tiles + per - 1) / per;
+    const int64_t base0 = a.d0.present ? *a.d0.count : 0;
+    const int64_t base1 = a.d1.present ? *a.d1.count : 0;
+    const uint64_t uid0 = *a.uid_next;
+    __syncthreads();
+    for (;;) {
+        if (tid == 0) s_ticket = atomicAdd((unsigned long long *)a.ws.ticket, 1ull);
+        __syncthreads();
+        const uint64_t tk = s_ticket;
+        const uint32_t epoch = (uint32_t)(tk >> 32);
+        const int64_t st = (int64_t)(tk & 0xffffffffull);
+        if (st >= n_st) {
+            if (tid == 0 && st == n_st + (int64_t)gridDim.x - 1) {
+                uint32_t t0 = 0, t1 = 0;
+                if (n_st > 0) lb_wait_inclusive(a.ws.lb, n_st - 1, epoch, t0, t1);
+                a.ws.info->base0 = base0;
+                a.ws.info->base1 = base1;
+                a.ws.info->uid0 = uid0;
+                if (a.mode == 0) {
+                    if (a.d0.present) {
+                        int64_t want = base0 + (int64_t)t0;
+                        if (want > a.d0.cap) { status_flag(a.ws.status, 1ull); status_need(a.ws.status, 0, want); want = a.d0.cap; }
+                        *a.d0.count = want;
+                    }
+                    if (a.d1.present) {
+                        int64_t want = base1 + (int64_t)t1;
+                        if (want > a.d1.cap) { status_flag(a.ws.status, 1ull); status_need(a.ws.status, 1, want); want = a.d1.cap; }
+                        *a.d1.count = want;
+                    }
+                    *a.uid_next = uid0 + (uint64_t)t0 + (uint64_t)t1;
+                } else {
+                    int64_t we = base0 + (int64_t)t0, wp = base1 + (int64_t)t0;
+                    if (we > a.d0.cap) { status_flag(a.ws.status, 1ull); status_need(a.ws.status, 2, we); we = a.d0.cap; }
+                    if (wp > a.d1.cap) { status_flag(a.ws.status, 1ull); status_need(a.ws.status, 3, wp); wp = a.d1.cap; }
+                    *a.d0.count = we;
+                    *a.d1.count = wp;
+                    *a.uid_next = uid0 + 2ull * (uint64_t)t0;
+                }
+                atomicAdd((unsigned long long *)a.ws.ticket,
+                          (1ull << 32) - (unsigned long long)(n_st + (int64_t)gridDim.x));
+            }
+            break;
+        }
+        const int64_t b = st * per + (int64_t)tid * kScanItems;
+        uint32_t v0[kScanItems], v1[kScanItems];
+        uint32_t s0 = 0, s1 = 0;
+#pragma unroll
+        for (int j = 0; j < kScanItems; ++j) {
+            const int64_t idx = b + j;
+            v0[j] = idx < n_tiles ? a.ws.tile_cnt0[idx] : 0u;
+            v1[j] = idx < n_tiles ? a.ws.tile_cnt1[idx] : 0u;
+            s0 += v0[j];
+            s1 += v1[j];
+        }
+        uint32_t e0, e1, tot0, tot1;
+        block_scan2(s0, s1, e0, e1, tot0, tot1, s_wave);
+        if (tid < kWave) {
+            uint32_t p0, p1;
+            lookback2(a.ws.lb, st, epoch, tot0, tot1, p0, p1);
+            if (tid == 0) { s_pref[0] = p0; s_pref[1] = p1; }
+        }
+        __syncthreads();
+        uint32_t r0 = s_pref[0] + e0, r1 = s_pref[1] + e1;
+#pragma unroll
+        for (int j = 0; j < kScanItems; ++j) {
+            const int64_t idx = b + j;
+            if (idx < n_tiles) { a.ws.tile_pre0[idx] = r0; a.ws.tile_pre1[idx] = r1; }
+            r0 += v0[j];
+            r1 += v1[j];
+        }
+        __syncthreads();
+    }
+}
+
+// Lists, in LDS, the tiles of chunk c (blockDim tiles) whose count is non-zero;
+// returns how many.
+__device__ __forceinline__ uint32_t list_tiles(const uint32_t *cnt, int64_t c, int64_t n_tiles,
+                                               uint32_t *s_list, uint32_t *s_wave) {
+    const int64_t t = c * blockDim.x + threadIdx.x;
+    const bool nz = t < n_tiles && cnt[t] != 0u;
+    uint32_t pos, m;
+    block_scan_flag(nz, pos, m, s_wave);
+    if (nz) s_list[pos] = threadIdx.x;
+    __syncthreads();
+    return m;
+}
+
+// Append pass of the lepton step: photons from the emission records, at the
+// offsets of the scan pass, with ids in the parents' serial order.
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_push_append(PushArgs a) {
+    __shared__ uint32_t s_wave[3 * kMaxWaves];
+    __shared__ uint32_t s_list[256];
+    __shared__ int64_t s_cnt[N_COUNT_USED];
+    const int tid = threadIdx.x;
+    const int64_t n = *a.lep.count;
+    const int64_t tile_sz = a.tile_sz;
+    const int64_t n_tiles = (n + tile_sz - 1) / tile_sz;
+    const int64_t n_chunks = (n_tiles + blockDim.x - 1) / blockDim.x;
+    const LaunchInfo info = *a.ws.info;
+    const R dtr = (R)a.st.dt;
+    const R *rec = (const R *)a.ws.stage.rec;
+    const int64_t slots = a.ws.stage.slots;
+    int cnt[N_COUNT_USED];
+#pragma unroll
+    for (int k = 0; k < N_COUNT_USED; ++k) cnt[k] = 0;
+    for (int64_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+        const uint32_t m = list_tiles(a.ws.stage.n_rec, c, n_tiles, s_list, s_wave);
+        for (uint32_t qi = 0; qi < m; ++qi) {
+            const int64_t tile = c * blockDim.x + s_list[qi];
+            const uint32_t nrec = a.ws.stage.n_rec[tile];
+            const bool have = tid < (int)nrec;
+            const int64_t sl = tile * tile_sz + tid;
+            uint32_t meta = 0, c0 = 0, c1 = 0;
+            if (have) {
+                meta = a.ws.stage.meta[sl];
+                const uint32_t ne = meta & 7u;
+#pragma unroll
+                for (int k = 0; k < kMaxEvents; ++k)
+                    if ((uint32_t)k < ne) {
+                        const uint32_t d = (meta >> (3 + 2 * k)) & 3u;
+                        c0 += d == 0u;
+                        c1 += d == 1u;
+                    }
+            }
+            uint32_t e0, e1, t0, t1;
+            block_scan2(c0, c1, e0, e1, t0, t1, s_wave);
+            if (have) {
+                uint32_t g0 = a.ws.tile_pre0[tile] + e0, g1 = a.ws.tile_pre1[tile] + e1;
+                const R x0 = rec[0 * slots + sl], y0 = rec[1 * slots + sl], z0 = rec[2 * slots + sl];
+                const R hx = rec[3 * slots + sl], hy = rec[4 * slots + sl], hz = rec[5 * slots + sl];
+                const R wgt = rec[6 * slots + sl];
+                const uint32_t ne = meta & 7u;
+#pragma unroll
+                for (int k = 0; k < kMaxEvents; ++k) {
+                    if ((uint32_t)k >= ne) break;
+                    const uint32_t d = (meta >> (3 + 2 * k)) & 3u;
+                    if (d > 1u) continue;
+                    const uint64_t nid = info.uid0 + (uint64_t)g0 + (uint64_t)g1;
+                    const SpeciesDev &S = d == 0u ? a.pp : a.pr;
+                    const int64_t j = d == 0u ? info.base0 + (int64_t)g0 : info.base1 + (int64_t)g1;
+                    if (d == 0u) ++g0; else ++g1;
+                    if (j >= S.cap) { cnt[C_LOST]++; continue; }
+                    const R gg = rec[(7 + k) * slots + sl];
+                    ((R *)S.x)[j] = x0 + dtr * hx;
+                    ((R *)S.y)[j] = y0 + dtr * hy;
+                    ((R *)S.z)[j] = z0 + dtr * hz;
+                    ((R *)S.ux)[j] = gg * hx;
+                    ((R *)S.uy)[j] = gg * hy;
+                    ((R *)S.uz)[j] = gg * hz;
+                    ((R *)S.w)[j] = wgt;
+                    if (S.chi) ((R *)S.chi)[j] = rec[(11 + k) * slots + sl];
+                    S.uid[j] = nid;
+                    S.n_ev[j] = 0u;
+                    S.tau[j] = initial_tau(a.st.seed, nid);
+                }
+            }
+            __syncthreads();
+        }
+    }
+    block_counts(a.tal, cnt, s_cnt);
+}
+
+// ------------------------------------------------------------------------
 // Photon step: Breit-Wheeler pair creation (Sec. 3, Eq. 3) and straight-line
-// push.  Decayed photons are marked with tau = +inf (removed by k_compact).
+// push.  The physics pass marks a photon that decays with tau = -inf and
+// leaves its position and momentum as they were; the append pass recomputes
+// the decay of marked photons, writes the pair and sets tau = +inf (removed
+// later by k_compact).
 // ------------------------------------------------------------------------
 template <typename R, int FK>
 __global__ void __launch_bounds__(256)
 k_pair_create(PairArgs a) {
     __shared__ R s_lp[kMaxChiNodes];
-    __shared__ uint64_t s_ticket;
-    __shared__ uint32_t s_wave[2 * kMaxWaves];
-    __shared__ uint32_t s_pref;
+    __shared__ uint32_t s_wave[3 * kMaxWaves];
     __shared__ double s_red[kNEnergy * kMaxWaves];
     __shared__ int64_t s_cnt[N_COUNT_USED];
 
@@ -480,8 +630,6 @@ k_pair_create(PairArgs a) {
     const TablesDev &tb = a.tab;
     for (int i = tid; i < tb.p_n_chi; i += blockDim.x) s_lp[i] = (R)tb.pair_lnh[i];
     const int64_t n = *a.ph.count;
-    const int64_t base_e = *a.el.count, base_p = *a.po.count;
-    const uint64_t uid0 = *a.uid_next;
     const double t = a.st.d_step ? a.st.t + (double)(*a.st.d_step) * a.st.dt : a.st.t;
     const double dt = a.st.dt;
     const R dtr = (R)dt;
@@ -490,7 +638,6 @@ k_pair_create(PairArgs a) {
     const bool atomic_slots = n_tiles > a.tal.n_slots;
     const R es_inv = (R)a.c.es_inv, Ah = (R)a.c.A;
     const R lnchi0 = (R)tb.p_lnchi0, inv_d = (R)tb.p_inv_dlnchi, chi_min = (R)tb.p_chi_min;
-    const R *qtab = pair_q_ptr<R>(tb);
     R *X = (R *)a.ph.x, *Y = (R *)a.ph.y, *Z = (R *)a.ph.z;
     const R *KX = (const R *)a.ph.ux, *KY = (const R *)a.ph.uy, *KZ = (const R *)a.ph.uz;
     int cnt[N_COUNT_USED];
@@ -498,41 +645,18 @@ k_pair_create(PairArgs a) {
     for (int k = 0; k < N_COUNT_USED; ++k) cnt[k] = 0;
     __syncthreads();
 
-    for (;;) {
-        if (tid == 0) s_ticket = atomicAdd((unsigned long long *)a.ws.ticket, 1ull);
-        __syncthreads();
-        const uint64_t tk = s_ticket;
-        const uint32_t epoch = (uint32_t)(tk >> 32);
-        const int64_t tile = (int64_t)(tk & 0xffffffffull);
-        if (tile >= n_tiles) {
-            if (tid == 0 && tile == n_tiles + (int64_t)gridDim.x - 1) {
-                if (n_tiles > 0) {
-                    uint32_t t0, t1;
-                    lb_wait_inclusive(a.ws.lb, n_tiles - 1, epoch, t0, t1);
-                    int64_t we = base_e + (int64_t)t0, wp = base_p + (int64_t)t0;
-                    if (we > a.el.cap) { status_flag(a.ws.status, 1ull); status_need(a.ws.status, 2, we); we = a.el.cap; }
-                    if (wp > a.po.cap) { status_flag(a.ws.status, 1ull); status_need(a.ws.status, 3, wp); wp = a.po.cap; }
-                    *a.el.count = we;
-                    *a.po.count = wp;
-                    *a.uid_next = uid0 + 2ull * (uint64_t)t0;
-                }
-                atomicAdd((unsigned long long *)a.ws.ticket,
-                          (1ull << 32) - (unsigned long long)(n_tiles + (int64_t)gridDim.x));
-            }
-            break;
-        }
+    for (int64_t it = 0;; ++it) {
+        const int64_t tile = xcd_tile(it, n_tiles);
+        if (tile < 0) break;
         const int64_t i = tile * tile_sz + tid;
         double en[kNEnergy];
 #pragma unroll
         for (int k = 0; k < kNEnergy; ++k) en[k] = 0.0;
         bool event = false;
-        R x = R(0), y = R(0), z = R(0), khx = R(0), khy = R(0), khz = R(0);
-        R gmn = R(1), gpl = R(1), chim = R(0), chip = R(0), wgt = R(0);
-        double tau = 0.0;
         if (i < n) {
-            tau = a.ph.tau[i];
+            double tau = a.ph.tau[i];
             if (tau != HUGE_VAL) {
-                x = X[i]; y = Y[i]; z = Z[i];
+                const R x = X[i], y = Y[i], z = Z[i];
                 const R kx = KX[i], ky = KY[i], kz = KZ[i];
                 R E[3], B[3];
                 field_at<R, FK>(a.f, t, x, y, z, a.f.a0, a.f.Phi, E, B);
@@ -547,46 +671,85 @@ k_pair_create(PairArgs a) {
                     if (above) cnt[C_RANGE]++;
                 }
                 tau -= (double)Wp * dt;
-                khx = kx / kk; khy = ky / kk; khz = kz / kk;
                 if (Wp > R(0) && tau <= 0.0) {
                     event = true;
-                    const U64x4 o = philox4x64_10(a.ph.uid[i], (uint64_t)a.ph.n_ev[i], (uint64_t)RNG_PAIR, 0ull,
-                                                  a.st.seed, 0ull);
-                    const R s = quantile<R>(qtab, tb.p_n_chi, tb.p_n_q, lnchi0, inv_d, tb.p_logit_max,
-                                            tb.p_inv_dt, Math<R>::log_(chig), u01(o.a));
-                    const R eta = R(1) / (R(1) + Math<R>::exp_(-s));
-                    chim = eta * chig;
-                    chip = chig - chim;
-                    gmn = R(1) + (kk - R(2)) * (chim / chig);
-                    gpl = R(1) + (kk - R(2)) * (chip / chig);
-                    wgt = ((const R *)a.ph.w)[i];
                     cnt[C_PAIR]++;
-                    en[E_PAIR] = (double)wgt * (double)kk;
+                    en[E_PAIR] = (double)((const R *)a.ph.w)[i] * (double)kk;
+                    a.ph.tau[i] = -HUGE_VAL;
+                } else {
+                    X[i] = x + dtr * (kx / kk);
+                    Y[i] = y + dtr * (ky / kk);
+                    Z[i] = z + dtr * (kz / kk);
+                    a.ph.tau[i] = tau;
                 }
             }
         }
-        uint32_t e, tot;
-        block_scan_flag(event, e, tot, s_wave);
-        if (tid < kWave) {
-            uint32_t p0, p1;
-            lookback2(a.ws.lb, tile, epoch, tot, 0u, p0, p1);
-            if (tid == 0) s_pref = p0;
+        uint32_t rank, tot, d0, d1;
+        block_rank3(event, 0u, 0u, rank, tot, d0, d1, s_wave);
+        if (tid == 0) {
+            a.ws.tile_cnt0[tile] = tot;
+            a.ws.tile_cnt1[tile] = 0u;
         }
+        tile_energy<kNEnergy>(a.tal, tile, atomic_slots, en, s_red);
         __syncthreads();
-        if (i < n && tau != HUGE_VAL) {
-            if (!event) {
-                X[i] = x + dtr * khx;
-                Y[i] = y + dtr * khy;
-                Z[i] = z + dtr * khz;
-                a.ph.tau[i] = tau;
-            } else {
-                a.ph.tau[i] = HUGE_VAL;
-                const uint32_t g = s_pref + e;
-                const uint64_t nid = uid0 + 2ull * (uint64_t)g;
+    }
+    block_counts(a.tal, cnt, s_cnt);
+}
+
+// Append pass of the photon step: e- and e+ of each marked photon.
+template <typename R, int FK>
+__global__ void __launch_bounds__(256)
+k_pair_append(PairArgs a) {
+    __shared__ uint32_t s_wave[3 * kMaxWaves];
+    __shared__ uint32_t s_list[256];
+    __shared__ int64_t s_cnt[N_COUNT_USED];
+    const int tid = threadIdx.x;
+    const TablesDev &tb = a.tab;
+    const int64_t n = *a.ph.count;
+    const int64_t tile_sz = a.tile_sz;
+    const int64_t n_tiles = (n + tile_sz - 1) / tile_sz;
+    const int64_t n_chunks = (n_tiles + blockDim.x - 1) / blockDim.x;
+    const LaunchInfo info = *a.ws.info;
+    const double t = a.st.d_step ? a.st.t + (double)(*a.st.d_step) * a.st.dt : a.st.t;
+    const R dtr = (R)a.st.dt;
+    const R es_inv = (R)a.c.es_inv;
+    const R lnchi0 = (R)tb.p_lnchi0, inv_d = (R)tb.p_inv_dlnchi;
+    const R *qtab = pair_q_ptr<R>(tb);
+    int cnt[N_COUNT_USED];
+#pragma unroll
+    for (int k = 0; k < N_COUNT_USED; ++k) cnt[k] = 0;
+    for (int64_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+        const uint32_t m = list_tiles(a.ws.tile_cnt0, c, n_tiles, s_list, s_wave);
+        for (uint32_t qi = 0; qi < m; ++qi) {
+            const int64_t tile = c * blockDim.x + s_list[qi];
+            const int64_t i = tile * tile_sz + tid;
+            const bool ev = tid < tile_sz && i < n && a.ph.tau[i] == -HUGE_VAL;
+            uint32_t e, tot;
+            block_scan_flag(ev, e, tot, s_wave);
+            if (ev) {
+                const R x = ((const R *)a.ph.x)[i], y = ((const R *)a.ph.y)[i], z = ((const R *)a.ph.z)[i];
+                const R kx = ((const R *)a.ph.ux)[i], ky = ((const R *)a.ph.uy)[i], kz = ((const R *)a.ph.uz)[i];
+                const R wgt = ((const R *)a.ph.w)[i];
+                R E[3], B[3];
+                field_at<R, FK>(a.f, t, x, y, z, a.f.a0, a.f.Phi, E, B);
+                const R kk = Math<R>::sqrt_(kx * kx + ky * ky + kz * kz);
+                const R chig = chi_of<R>(es_inv, kk, kx, ky, kz, E, B);
+                const R khx = kx / kk, khy = ky / kk, khz = kz / kk;
+                const U64x4 o = philox4x64_10(a.ph.uid[i], (uint64_t)a.ph.n_ev[i], (uint64_t)RNG_PAIR, 0ull,
+                                              a.st.seed, 0ull);
+                const R s = quantile<R>(qtab, tb.p_n_chi, tb.p_n_q, lnchi0, inv_d, tb.p_logit_max,
+                                        tb.p_inv_dt, Math<R>::log_(chig), u01(o.a));
+                const R eta = R(1) / (R(1) + Math<R>::exp_(-s));
+                const R chim = eta * chig;
+                const R chip = chig - chim;
+                const R gmn = R(1) + (kk - R(2)) * (chim / chig);
+                const R gpl = R(1) + (kk - R(2)) * (chip / chig);
+                const uint32_t g = a.ws.tile_pre0[tile] + e;
+                const uint64_t nid = info.uid0 + 2ull * (uint64_t)g;
 #pragma unroll
                 for (int side = 0; side < 2; ++side) {
                     const SpeciesDev &D = side == 0 ? a.el : a.po;
-                    const int64_t j = (side == 0 ? base_e : base_p) + (int64_t)g;
+                    const int64_t j = (side == 0 ? info.base0 : info.base1) + (int64_t)g;
                     if (j >= D.cap) { cnt[C_LOST]++; continue; }
                     const R gmag = side == 0 ? gmn : gpl;
                     const R pm = Math<R>::sqrt_(gmag * gmag - R(1));
@@ -604,10 +767,10 @@ k_pair_create(PairArgs a) {
                     D.n_ev[j] = 0u;
                     D.tau[j] = initial_tau(a.st.seed, id);
                 }
+                a.ph.tau[i] = HUGE_VAL;
             }
+            __syncthreads();
         }
-        tile_energy<kNEnergy>(a.tal, tile, atomic_slots, en, s_red);
-        __syncthreads();
     }
     block_counts(a.tal, cnt, s_cnt);
 }
@@ -731,6 +894,17 @@ hipError_t launch_push_emit(const PushArgs &a, int prec, int fk, dim3 grid, dim3
     return prec == 0 ? launch_push<double>(a, fk, grid, block, s) : launch_push<float>(a, fk, grid, block, s);
 }
 
+hipError_t launch_scan_tiles(const ScanArgs &a, dim3 grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_scan_tiles, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_push_append(const PushArgs &a, int prec, dim3 grid, dim3 block, hipStream_t s) {
+    if (prec == 0) hipLaunchKernelGGL((k_push_append<double>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_push_append<float>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_pair(const PairArgs &a, int fk, dim3 grid, dim3 block, hipStream_t s) {
     switch (fk) {
@@ -743,6 +917,20 @@ hipError_t launch_pair(const PairArgs &a, int fk, dim3 grid, dim3 block, hipStre
 
 hipError_t launch_pair_create(const PairArgs &a, int prec, int fk, dim3 grid, dim3 block, hipStream_t s) {
     return prec == 0 ? launch_pair<double>(a, fk, grid, block, s) : launch_pair<float>(a, fk, grid, block, s);
+}
+
+template <typename R>
+hipError_t launch_pair_app(const PairArgs &a, int fk, dim3 grid, dim3 block, hipStream_t s) {
+    switch (fk) {
+    case FIELD_UNIFORM: hipLaunchKernelGGL((k_pair_append<R, FIELD_UNIFORM>), grid, block, 0, s, a); break;
+    case FIELD_PLANE: hipLaunchKernelGGL((k_pair_append<R, FIELD_PLANE>), grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_pair_append<R, FIELD_YEE>), grid, block, 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_append(const PairArgs &a, int prec, int fk, dim3 grid, dim3 block, hipStream_t s) {
+    return prec == 0 ? launch_pair_app<double>(a, fk, grid, block, s) : launch_pair_app<float>(a, fk, grid, block, s);
 }
 
 hipError_t launch_compact(const CompactArgs &a, int prec, dim3 grid, dim3 block, hipStream_t s) {

@@ -137,8 +137,8 @@ class Tables:
 
 
 class Workspace:
-    def __init__(self, max_particles: int):
-        self.h = B.qed_workspace_create(max_particles)
+    def __init__(self, max_particles: int, max_leptons: int | None = None):
+        self.h = B.qed_workspace_create(max_particles, max_particles if max_leptons is None else max_leptons)
 
     def status(self, clear=True, raise_on_error=True):
         return B.qed_sync_status(self.h, clear=clear, raise_on_error=raise_on_error)

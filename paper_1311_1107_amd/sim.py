@@ -49,7 +49,7 @@ class Run:
         self.ph = D.Species(cap_ph, prec, chi=True, device=device) if push else None
         self.rec = D.Species(cap_rec, prec, chi=True, device=device) if wl.record_photons else None
         caps = [n0 + cap_pair, cap_pair, cap_ph, cap_rec, 1]
-        self.ws = D.Workspace(max(caps))
+        self.ws = D.Workspace(max(caps), max_leptons=n0 + cap_pair)
         # one energy slot per 256-particle tile keeps the sums reproducible at the default block
         slots = (max(caps) + 255) // 256 + 1 if deterministic_tally else 4096
         self.tally = D.Tally(slots, device=device)
