@@ -40,6 +40,7 @@ def parse():
     p.add_argument("--copy-calibration", action="store_true",
                    help="run a 1 GiB device copy first (reference for the traffic counters)")
     p.add_argument("--compact-every", type=int, default=16)
+    p.add_argument("--sort-every", type=int, default=16, help="cell-order the particles every k steps (Yee)")
     return p.parse_args()
 
 
@@ -122,10 +123,13 @@ def main():
     K = min(K, wl.steps)
     n0 = len(wl.electrons["x"])
 
-    run = S.Run(wl, prec=prec, compact_every=args.compact_every, **caps)
+    run = S.Run(wl, prec=prec, compact_every=args.compact_every, sort_every=args.sort_every, **caps)
     init = {k: v.clone() for k, v in run.el.a.items()}
+    init_el = run.el
 
     def reset():
+        if run.el is not init_el:                  # a sort swapped the electron buffers
+            run.alt["el"], run.el = run.el, init_el
         for k, v in init.items():
             run.el.a[k].copy_(v)
         run.el.count.fill_(n0)
@@ -134,6 +138,7 @@ def main():
                 sp.count.zero_()
         run.uid_next.fill_(n0)
         run.tally.zero()
+        run._photon_view()
 
     for k in range(args.warmup):
         run.step(k)
@@ -143,8 +148,7 @@ def main():
 
     # per-kernel event timing on the stream the kernels run on
     stream = torch.cuda.current_stream()
-    kinds = ("fill", "push_e", "push_p", "pair", "compact")
-    evs = {k: [] for k in kinds}
+    evs = {}
 
     def timed(kind, fn):
         a = torch.cuda.Event(enable_timing=True)
@@ -152,34 +156,17 @@ def main():
         a.record(stream)
         fn()
         b.record(stream)
-        evs[kind].append((a, b))
-
-    units, tabs = run.units, run.tables
-    pp = run.ph.struct() if run.ph is not None else None
-    pr = run.rec.struct() if run.rec is not None else None
-    uid = run.uid_next.data_ptr()
+        evs.setdefault(kind, []).append((a, b))
 
     def step(n):
-        st = D.step(n * wl.dt, wl.dt, wl.seed, **run.step_kw)
-        if run.grid is not None:
-            timed("fill", lambda: run.fill_field(n))
-        if run.ph is not None:
-            run.ph_snap.copy_(run.ph.count)
-        timed("push_e", lambda: B.qed_push_emit(tabs.h, run.ws.h, units, -1.0, run.el.struct(), run.field, pp, pr,
-                                                run.tally.s, st, uid, run.sched))
-        timed("push_p", lambda: B.qed_push_emit(tabs.h, run.ws.h, units, +1.0, run.po.struct(), run.field, pp, pr,
-                                                run.tally.s, st, uid, run.sched))
-        if run.ph is not None:
-            timed("pair", lambda: B.qed_pair_create(tabs.h, run.ws.h, units, run.ph_step, run.field,
-                                                    run.el.struct(), run.po.struct(), run.tally.s, st, uid,
-                                                    run.sched))
-            if args.compact_every and (n + 1) % args.compact_every == 0:
-                timed("compact", run.compact)
+        run.step(n, timed=timed)
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for n in range(K):
         step(n)
+        if (n + 1) % 250 == 0:                     # the host runs at most a queue's depth ahead
+            print(f"bench: step {n + 1}/{K} enqueued", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     rc, rep = run.ws.status(raise_on_error=False)
@@ -216,7 +203,8 @@ def main():
         "dtype": "f64" if prec == B.QED_F64 else "f32+f64",
         "data": "synthetic",
         "config": {"workload": desc, "electrons": n0, "grid": list(wl.field.shape) if hasattr(wl.field, "shape") else None,
-                   "steps_timed": K, "dt": wl.dt, "compact_every": args.compact_every},
+                   "steps_timed": K, "dt": wl.dt, "compact_every": args.compact_every,
+                   "sort_every": args.sort_every},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_launch": dom_bytes / max(dom_n, 1), "avg_launch_ms": dom_ms / max(dom_n, 1)},

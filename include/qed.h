@@ -317,6 +317,29 @@ qed_status qed_autotune_batched(const qed_tables *tab, qed_workspace *ws, const 
                                 int32_t trial_steps, const char *cache_path,
                                 qed_schedule *best, double *best_ms, void *stream);
 
+/* ------------------------------------------------------------------------ *
+ * Cell ordering.  Writes the particles of src into dst (same precision,
+ * capacity >= src's) ordered by the Yee cell that holds them: key
+ * (i ny + j) nz + k with i = floor((x - x0)/dx) etc., particles outside the
+ * grid after all cells; equal keys keep their order (stable), so the result
+ * is a deterministic function of src.  Decayed photons (tau = +INFINITY) are
+ * dropped; *dst->d_count receives the number kept.  Keeps the field gather
+ * of neighbouring threads on shared grid lines.  grid supplies the geometry
+ * (kind QED_FIELD_YEE).  The sorter holds 16 bytes per particle of scratch
+ * (device memory, owned by the caller until qed_sorter_free); max_particles
+ * must be below 2^32 - 1.  src and dst are device species in distinct
+ * buffers; the workspace lends its look-back scratch, so calls on one
+ * workspace are ordered on one stream.  QED_ERR_ARG for a null argument,
+ * a non-Yee geometry or more than 2^31 cells, differing precisions or chi
+ * arrays, aliased buffers, dst->capacity < src->capacity, or
+ * src->capacity above the sorter's maximum; QED_ERR_HIP if a launch fails.
+ * ------------------------------------------------------------------------ */
+typedef struct qed_sorter qed_sorter;
+qed_status qed_sorter_create(int64_t max_particles, qed_sorter **out);
+void qed_sorter_free(qed_sorter *s);
+qed_status qed_sort_by_cell(qed_sorter *s, qed_workspace *ws, qed_species *src, qed_species *dst,
+                            const qed_field *grid, void *stream);
+
 /* Advance a device step counter by one (for graph-captured step sequences). */
 qed_status qed_step_advance(int64_t *d_step, void *stream);
 

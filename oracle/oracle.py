@@ -143,6 +143,7 @@ def lib():
                                      C.POINTER(Field), C.POINTER(Species), C.POINTER(Species),
                                      C.POINTER(Step), _u64p, _dp, C.POINTER(C.c_int64)]
         L.or_pair_create.restype = C.c_int
+        L.or_sort_by_cell.argtypes = [C.POINTER(Species), C.c_int64, C.c_int64, C.c_int64, d, d, d, d, d, d]
         _lib = L
     return _lib
 
@@ -442,3 +443,9 @@ def pair_create(tabs: BoundTables, lambda_m, ph: dict, field: Field, elec: dict,
     uid_next[0] = int(un[0])
     ph["n"], elec["n"], posi["n"] = P.n, Em.n, Ep.n
     return rc
+
+
+def sort_by_cell(s: dict, shape, spacing, origin):
+    st = _species_struct(s)
+    lib().or_sort_by_cell(C.byref(st), *[int(v) for v in shape], *[float(v) for v in spacing],
+                          *[float(v) for v in origin])

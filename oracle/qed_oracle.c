@@ -961,3 +961,53 @@ int or_pair_create(const or_tables *tab, const or_units *un,
     P->n = keep;
     return overflow;
 }
+
+/* ======================================================================== *
+ * 10. Cell ordering of a species (a PIC code's particle sort): stable by the
+ *     key (i ny + j) nz + k of the Yee cell holding the particle, with
+ *     i = floor((x - x0) * (1/dx)) etc.; particles outside the grid last.
+ * ======================================================================== */
+typedef struct { uint64_t key; int64_t idx; } or_keyidx;
+
+static int cmp_keyidx(const void *a, const void *b)
+{
+    const or_keyidx *p = (const or_keyidx *)a, *q = (const or_keyidx *)b;
+    if (p->key != q->key) return p->key < q->key ? -1 : 1;
+    return p->idx < q->idx ? -1 : (p->idx > q->idx ? 1 : 0);
+}
+
+void or_sort_by_cell(or_species *s, int64_t nx, int64_t ny, int64_t nz, double dx, double dy, double dz,
+                     double x0, double y0, double z0)
+{
+    int64_t n = s->n;
+    if (n < 2) return;
+    double idx_ = 1.0 / dx, idy = 1.0 / dy, idz = 1.0 / dz;
+    uint64_t ncell = (uint64_t)(nx * ny * nz);
+    or_keyidx *ki = (or_keyidx *)malloc(sizeof(or_keyidx) * n);
+    for (int64_t i = 0; i < n; ++i) {
+        double gx = (s->x[i] - x0) * idx_, gy = (s->y[i] - y0) * idy, gz = (s->z[i] - z0) * idz;
+        uint64_t key = ncell;
+        if (gx >= 0.0 && gy >= 0.0 && gz >= 0.0) {
+            double fi = floor(gx), fj = floor(gy), fk = floor(gz);
+            if (fi < (double)nx && fj < (double)ny && fk < (double)nz)
+                key = (uint64_t)((((int64_t)fi * ny) + (int64_t)fj) * nz + (int64_t)fk);
+        }
+        ki[i].key = key;
+        ki[i].idx = i;
+    }
+    qsort(ki, (size_t)n, sizeof(or_keyidx), cmp_keyidx);
+    double *tmp = (double *)malloc(sizeof(double) * n);
+    double *arr[9] = { s->x, s->y, s->z, s->ux, s->uy, s->uz, s->tau, s->w, s->chi };
+    for (int a = 0; a < 9; ++a) {
+        if (!arr[a]) continue;
+        for (int64_t j = 0; j < n; ++j) tmp[j] = arr[a][ki[j].idx];
+        memcpy(arr[a], tmp, sizeof(double) * n);
+    }
+    uint64_t *tu = (uint64_t *)malloc(sizeof(uint64_t) * n);
+    for (int64_t j = 0; j < n; ++j) tu[j] = s->uid[ki[j].idx];
+    memcpy(s->uid, tu, sizeof(uint64_t) * n);
+    uint32_t *te = (uint32_t *)malloc(sizeof(uint32_t) * n);
+    for (int64_t j = 0; j < n; ++j) te[j] = s->n_ev[ki[j].idx];
+    memcpy(s->n_ev, te, sizeof(uint32_t) * n);
+    free(tmp); free(tu); free(te); free(ki);
+}

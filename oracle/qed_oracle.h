@@ -182,6 +182,11 @@ int or_pair_create(const or_tables *tab, const or_units *u,
                    const or_step *st, uint64_t *uid_next,
                    double *tally, int64_t *count);
 
+/* Stable reorder by Yee cell (i ny + j) nz + k, i = floor((x - x0)*(1/dx)) etc.;
+ * particles outside the grid last. */
+void or_sort_by_cell(or_species *s, int64_t nx, int64_t ny, int64_t nz, double dx, double dy, double dz,
+                     double x0, double y0, double z0);
+
 #ifdef __cplusplus
 }
 #endif

@@ -115,6 +115,9 @@ _SIGS = {
                               _P(qed_species), _P(qed_step), _P(qed_schedule), C.c_int32, C.c_int32,
                               C.c_char_p, _P(qed_schedule), _dp, _vp], C.c_int32),
     "qed_step_advance": ([_vp, _vp], C.c_int32),
+    "qed_sorter_create": ([C.c_int64, _P(_vp)], C.c_int32),
+    "qed_sorter_free": ([_vp], None),
+    "qed_sort_by_cell": ([_vp, _vp, _P(qed_species), _P(qed_species), _P(qed_field), _vp], C.c_int32),
 }
 
 _lib = None
@@ -271,6 +274,20 @@ def qed_tally_reduce(tally: qed_tally, stream=None):
     _check(lib().qed_tally_reduce(C.byref(tally), e.ctypes.data_as(_dp), c.ctypes.data_as(C.POINTER(C.c_int64)),
                                   _stream(stream)))
     return e, c
+
+
+def qed_sorter_create(max_particles: int) -> C.c_void_p:
+    h = C.c_void_p()
+    _check(lib().qed_sorter_create(int(max_particles), C.byref(h)))
+    return h
+
+
+def qed_sorter_free(handle):
+    lib().qed_sorter_free(handle)
+
+
+def qed_sort_by_cell(sorter, ws, src, dst, grid_field, stream=None):
+    _check(lib().qed_sort_by_cell(sorter, ws, C.byref(src), C.byref(dst), C.byref(grid_field), _stream(stream)))
 
 
 def qed_step_advance(d_step_ptr, stream=None):

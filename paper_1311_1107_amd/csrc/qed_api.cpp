@@ -13,6 +13,7 @@
 
 #include "qed.h"
 #include "qed_kernels.h"
+#include "qed_sort.h"
 
 namespace qedtab {
 int build_tables(double e_chi_min, double e_chi_max, int e_n_chi, int e_n_q, double e_logit,
@@ -54,6 +55,14 @@ struct qed_tables {
     float *d32;
     size_t off[6];    // element offsets of the five tables (and the total)
     qed::TablesDev dev;
+};
+
+struct qed_sorter {
+    int64_t max_particles;
+    uint32_t *keys;               // 4 * max: key0, key1, idx0, idx1
+    uint32_t *hist;               // 2 * 16 * tiles: histograms and their prefixes
+    unsigned long long *live;
+    int64_t hist_len;
 };
 
 struct qed_workspace {
@@ -528,6 +537,69 @@ qed_status qed_compact(qed_workspace *ws, qed_species *ph, const qed_schedule *s
     dim3 grid, block;
     if ((s = shape(ws, sched, ph->capacity, grid, block))) return s;
     HIP_TRY(qed::launch_compact(a, ph->prec, grid, block, (hipStream_t)stream));
+    return QED_OK;
+}
+
+// -------------------------------------------------------------- cell sort --
+qed_status qed_sorter_create(int64_t max_particles, qed_sorter **out) {
+    if (!out) return fail(QED_ERR_ARG, "qed_sorter_create: null out");
+    *out = nullptr;
+    if (max_particles < 1 || max_particles >= (int64_t)0xffffffffll)
+        return fail(QED_ERR_ARG, "qed_sorter_create: max_particles must be in [1, 2^32-1)");
+    qed_sorter *s = new qed_sorter();
+    s->max_particles = max_particles;
+    s->hist_len = 16 * ((max_particles + 4095) / 4096 + 1);
+    if (hipMalloc(&s->keys, sizeof(uint32_t) * 4 * max_particles) != hipSuccess ||
+        hipMalloc(&s->hist, sizeof(uint32_t) * 2 * s->hist_len) != hipSuccess ||
+        hipMalloc(&s->live, 64) != hipSuccess) {
+        qed_sorter_free(s);
+        return fail(QED_ERR_NOMEM, "qed_sorter_create: device allocation failed");
+    }
+    *out = s;
+    return QED_OK;
+}
+
+void qed_sorter_free(qed_sorter *s) {
+    if (!s) return;
+    (void)hipFree(s->keys);
+    (void)hipFree(s->hist);
+    (void)hipFree(s->live);
+    delete s;
+}
+
+qed_status qed_sort_by_cell(qed_sorter *so, qed_workspace *ws, qed_species *src, qed_species *dst,
+                            const qed_field *grid, void *stream) {
+    if (!so || !ws || !src || !dst || !grid) return fail(QED_ERR_ARG, "qed_sort_by_cell: null argument");
+    if (grid->kind != QED_FIELD_YEE || grid->nx < 1 || grid->ny < 1 || grid->nz < 1 || !(grid->dx > 0) ||
+        !(grid->dy > 0) || !(grid->dz > 0))
+        return fail(QED_ERR_ARG, "qed_sort_by_cell: needs a Yee grid geometry");
+    const int64_t ncell = grid->nx * grid->ny * grid->nz;
+    if (ncell >= (int64_t)0x7fffffff) return fail(QED_ERR_ARG, "qed_sort_by_cell: too many cells");
+    qed::SortArgs a;
+    std::memset(&a, 0, sizeof a);
+    qed_status st;
+    if ((st = species_dev(src, false, "qed_sort_by_cell(src)", a.src))) return st;
+    if ((st = species_dev(dst, false, "qed_sort_by_cell(dst)", a.dst))) return st;
+    if (src->prec != dst->prec) return fail(QED_ERR_ARG, "qed_sort_by_cell: src and dst precisions differ");
+    if (dst->capacity < src->capacity) return fail(QED_ERR_ARG, "qed_sort_by_cell: dst smaller than src");
+    if (src->capacity > so->max_particles) return fail(QED_ERR_ARG, "qed_sort_by_cell: sorter too small");
+    if ((src->chi == nullptr) != (dst->chi == nullptr)) return fail(QED_ERR_ARG, "qed_sort_by_cell: chi arrays differ");
+    if (src->x == dst->x || src->tau == dst->tau || src->d_count == dst->d_count)
+        return fail(QED_ERR_ARG, "qed_sort_by_cell: src and dst must be distinct buffers");
+    int bits = 1;
+    while (((int64_t)1 << bits) - 1 <= ncell) ++bits;      // keys 0..ncell (outside) < key_dead = 2^bits - 1
+    a.key_out = (uint32_t)ncell;
+    a.key_dead = (uint32_t)(((uint64_t)1 << bits) - 1);
+    const int passes = (bits + 3) / 4;
+    a.x0 = grid->x0; a.y0 = grid->y0; a.z0 = grid->z0;
+    a.inv_dx = 1.0 / grid->dx; a.inv_dy = 1.0 / grid->dy; a.inv_dz = 1.0 / grid->dz;
+    a.nx = grid->nx; a.ny = grid->ny; a.nz = grid->nz;
+    const int64_t m = so->max_particles;
+    a.key0 = so->keys; a.key1 = so->keys + m; a.idx0 = so->keys + 2 * m; a.idx1 = so->keys + 3 * m;
+    a.hist = so->hist; a.hoff = so->hist + so->hist_len;
+    a.live = so->live;
+    a.ws = ws->dev;
+    HIP_TRY(qed::launch_sort(a, src->prec, passes, ws->n_cu, src->capacity, (hipStream_t)stream));
     return QED_OK;
 }
 

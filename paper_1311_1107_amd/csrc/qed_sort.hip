@@ -1,0 +1,236 @@
+// qed_sort.hip -- stable reordering of particles by Yee-grid cell.
+//
+// A PIC code keeps its particles ordered by cell so that the field gather of
+// neighbouring threads touches the same grid lines.  The order here is a
+// stable sort by cell key, so that it is a deterministic function of the
+// particle state (the oracle applies the same one): key = (i ny + j) nz + k
+// of the cell holding the particle, nx ny nz for particles outside the grid,
+// and the largest key for decayed photons (tau = +inf), which are dropped.
+//
+// LSD radix sort, 4-bit digits: per pass a count kernel (per-tile digit
+// histograms, digit-major), an exclusive scan of the histograms, and a scatter
+// kernel in which every thread owns 16 consecutive keys; per-thread digit
+// counts and a block scan over (digit, thread) give each key its stable slot.
+// A final kernel gathers the particles into the destination arrays.
+#include "qed_sort.h"
+
+namespace qed {
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;   // 4096 keys per tile
+constexpr int kDigits = 16;
+
+// particle count of the source, clamped to its capacity (every pass agrees on it)
+__device__ __forceinline__ int64_t sort_count(const int64_t *count, int64_t cap) {
+    const int64_t n = *count;
+    return n < 0 ? 0 : (n > cap ? cap : n);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_sort_keys(SortArgs a) {
+    const int64_t n = sort_count(a.src.count, a.src.cap);
+    const R *X = (const R *)a.src.x, *Y = (const R *)a.src.y, *Z = (const R *)a.src.z;
+    unsigned long long live = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t key;
+        if (a.src.tau[i] == HUGE_VAL) {
+            key = a.key_dead;
+        } else {
+            ++live;
+            const double gx = ((double)X[i] - a.x0) * a.inv_dx;
+            const double gy = ((double)Y[i] - a.y0) * a.inv_dy;
+            const double gz = ((double)Z[i] - a.z0) * a.inv_dz;
+            key = a.key_out;
+            if (gx >= 0.0 && gy >= 0.0 && gz >= 0.0) {
+                const double fi = floor(gx), fj = floor(gy), fk = floor(gz);
+                if (fi < (double)a.nx && fj < (double)a.ny && fk < (double)a.nz)
+                    key = (uint32_t)(((int64_t)fi * a.ny + (int64_t)fj) * a.nz + (int64_t)fk);
+            }
+        }
+        a.key0[i] = key;
+        a.idx0[i] = (uint32_t)i;
+    }
+    live = (unsigned long long)wave_sum_u32((uint32_t)live);
+    if (lane_id() == 0 && live) atomicAdd((unsigned long long *)a.live, live);
+}
+
+__global__ void k_sort_zero(unsigned long long *live) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *live = 0ull;
+}
+
+// per-tile digit histograms, stored digit-major: hist[d * n_tiles + tile]
+__global__ void __launch_bounds__(256)
+k_radix_count(const uint32_t *keys, const int64_t *count, int64_t cap, int shift, uint32_t *hist) {
+    __shared__ uint32_t s_h[kDigits];
+    const int64_t n = sort_count(count, cap);
+    const int64_t n_tiles = (n + kSortTile - 1) / kSortTile;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        if (threadIdx.x < kDigits) s_h[threadIdx.x] = 0u;
+        __syncthreads();
+        const int64_t b = tile * kSortTile;
+        for (int j = threadIdx.x; j < kSortTile; j += blockDim.x) {
+            const int64_t i = b + j;
+            if (i < n) atomicAdd(&s_h[(keys[i] >> shift) & (kDigits - 1)], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x < kDigits) hist[(int64_t)threadIdx.x * n_tiles + tile] = s_h[threadIdx.x];
+        __syncthreads();
+    }
+}
+
+// exclusive scan of a u32 array (decoupled look-back over blocks of 4096)
+__global__ void __launch_bounds__(256)
+k_scan_u32(const uint32_t *in, uint32_t *out, const int64_t *count, int64_t cap, int64_t mult, WsDev ws) {
+    __shared__ uint64_t s_ticket;
+    __shared__ uint32_t s_wave[2 * kMaxWaves];
+    __shared__ uint32_t s_pref;
+    const int tid = threadIdx.x;
+    const int64_t n_items = (sort_count(count, cap) + kSortTile - 1) / kSortTile * mult;
+    const int64_t n_st = (n_items + kSortTile - 1) / kSortTile;
+    for (;;) {
+        if (tid == 0) s_ticket = atomicAdd((unsigned long long *)ws.ticket, 1ull);
+        __syncthreads();
+        const uint64_t tk = s_ticket;
+        const uint32_t epoch = (uint32_t)(tk >> 32);
+        const int64_t st = (int64_t)(tk & 0xffffffffull);
+        if (st >= n_st) {
+            if (tid == 0 && st == n_st + (int64_t)gridDim.x - 1)
+                atomicAdd((unsigned long long *)ws.ticket,
+                          (1ull << 32) - (unsigned long long)(n_st + (int64_t)gridDim.x));
+            break;
+        }
+        const int64_t b = st * kSortTile + (int64_t)tid * kSortItems;
+        uint32_t v[kSortItems], sum = 0;
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) {
+            v[j] = b + j < n_items ? in[b + j] : 0u;
+            sum += v[j];
+        }
+        uint32_t e, e1, tot, tot1;
+        block_scan2(sum, 0u, e, e1, tot, tot1, s_wave);
+        if (tid < kWave) {
+            uint32_t p0, p1;
+            lookback2(ws.lb, st, epoch, tot, 0u, p0, p1);
+            if (tid == 0) s_pref = p0;
+        }
+        __syncthreads();
+        uint32_t r = s_pref + e;
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) {
+            if (b + j < n_items) out[b + j] = r;
+            r += v[j];
+        }
+        __syncthreads();
+    }
+}
+
+// stable scatter of one 4-bit digit
+__global__ void __launch_bounds__(256)
+k_radix_scatter(const uint32_t *kin, const uint32_t *iin, uint32_t *kout, uint32_t *iout,
+                const int64_t *count, int64_t cap, int shift, const uint32_t *hoff) {
+    __shared__ uint32_t s_c[kDigits * kSortThreads];     // (digit, thread) counts, then offsets
+    __shared__ uint32_t s_wave[2 * kMaxWaves];
+    const int tid = threadIdx.x;
+    const int64_t n = sort_count(count, cap);
+    const int64_t n_tiles = (n + kSortTile - 1) / kSortTile;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t b = tile * kSortTile + (int64_t)tid * kSortItems;
+        uint32_t k[kSortItems], v[kSortItems];
+        uint32_t c[kDigits];
+#pragma unroll
+        for (int d = 0; d < kDigits; ++d) c[d] = 0u;
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) {
+            const bool in = b + j < n;
+            k[j] = in ? kin[b + j] : 0xffffffffu;
+            v[j] = in ? iin[b + j] : 0u;
+            if (in) {
+                const uint32_t d = (k[j] >> shift) & (kDigits - 1);
+#pragma unroll
+                for (int q = 0; q < kDigits; ++q) c[q] += (d == (uint32_t)q);
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < kDigits; ++d) s_c[d * kSortThreads + tid] = c[d];
+        __syncthreads();
+        // exclusive scan of s_c in (digit, thread) order: thread t owns entries 16t .. 16t+15
+        uint32_t part[kSortItems], sum = 0;
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) { part[j] = s_c[tid * kSortItems + j]; sum += part[j]; }
+        uint32_t e, e1, tot, tot1;
+        block_scan2(sum, 0u, e, e1, tot, tot1, s_wave);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) { s_c[tid * kSortItems + j] = e; e += part[j]; }
+        __syncthreads();
+        // digit d of this tile starts at hoff[d * n_tiles + tile] globally and at
+        // s_c[d * 256] within the tile; this thread's keys of digit d follow s_c[d * 256 + tid]
+#pragma unroll
+        for (int d = 0; d < kDigits; ++d)
+            c[d] = hoff[(int64_t)d * n_tiles + tile] + s_c[d * kSortThreads + tid] - s_c[d * kSortThreads];
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) {
+            if (b + j < n) {
+                const uint32_t d = (k[j] >> shift) & (kDigits - 1);
+                uint32_t pos = 0;
+#pragma unroll
+                for (int q = 0; q < kDigits; ++q)
+                    if (d == (uint32_t)q) { pos = c[q]; c[q] = pos + 1; }
+                kout[pos] = k[j];
+                iout[pos] = v[j];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// gather the live particles into the destination, in sorted order
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_sort_permute(SortArgs a) {
+    const int64_t live = (int64_t)*a.live;
+    const uint32_t *idx = a.idx_final;
+    const bool chi = a.src.chi != nullptr && a.dst.chi != nullptr;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < live; j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = idx[j];
+        ((R *)a.dst.x)[j] = ((const R *)a.src.x)[i];
+        ((R *)a.dst.y)[j] = ((const R *)a.src.y)[i];
+        ((R *)a.dst.z)[j] = ((const R *)a.src.z)[i];
+        ((R *)a.dst.ux)[j] = ((const R *)a.src.ux)[i];
+        ((R *)a.dst.uy)[j] = ((const R *)a.src.uy)[i];
+        ((R *)a.dst.uz)[j] = ((const R *)a.src.uz)[i];
+        ((R *)a.dst.w)[j] = ((const R *)a.src.w)[i];
+        if (chi) ((R *)a.dst.chi)[j] = ((const R *)a.src.chi)[i];
+        a.dst.tau[j] = a.src.tau[i];
+        a.dst.uid[j] = a.src.uid[i];
+        a.dst.n_ev[j] = a.src.n_ev[i];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.dst.count = live;
+}
+
+hipError_t launch_sort(const SortArgs &a, int prec, int passes, int n_cu, int64_t capacity, hipStream_t s) {
+    const int64_t tiles = (capacity + kSortTile - 1) / kSortTile;
+    const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)n_cu * 8));
+    const unsigned ge = (unsigned)std::max<int64_t>(1, std::min<int64_t>((capacity + 255) / 256, (int64_t)n_cu * 16));
+    const unsigned gs = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tiles * kDigits + kSortTile - 1) / kSortTile, n_cu));
+    hipLaunchKernelGGL(k_sort_zero, dim3(1), dim3(64), 0, s, a.live);
+    if (prec == 0) hipLaunchKernelGGL((k_sort_keys<double>), dim3(ge), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_sort_keys<float>), dim3(ge), dim3(256), 0, s, a);
+    uint32_t *kb[2] = {a.key0, a.key1}, *ib[2] = {a.idx0, a.idx1};
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 4 * p;
+        hipLaunchKernelGGL(k_radix_count, dim3(gb), dim3(256), 0, s, kb[p & 1], a.src.count, a.src.cap, shift, a.hist);
+        hipLaunchKernelGGL(k_scan_u32, dim3(gs), dim3(256), 0, s, a.hist, a.hoff, a.src.count, a.src.cap, (int64_t)kDigits, a.ws);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(gb), dim3(256), 0, s, kb[p & 1], ib[p & 1], kb[(p + 1) & 1],
+                           ib[(p + 1) & 1], a.src.count, a.src.cap, shift, a.hoff);
+    }
+    SortArgs b = a;
+    b.idx_final = ib[passes & 1];
+    if (prec == 0) hipLaunchKernelGGL((k_sort_permute<double>), dim3(ge), dim3(256), 0, s, b);
+    else hipLaunchKernelGGL((k_sort_permute<float>), dim3(ge), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+}  // namespace qed

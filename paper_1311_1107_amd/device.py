@@ -151,6 +151,22 @@ class Workspace:
             pass
 
 
+class Sorter:
+    """Scratch of the cell ordering (qed_sort_by_cell) for up to max_particles."""
+
+    def __init__(self, max_particles: int):
+        self.max_particles = int(max_particles)
+        self.h = B.qed_sorter_create(self.max_particles)
+
+    def sort(self, ws: "Workspace", src: Species, dst: Species, grid_field: B.qed_field):
+        B.qed_sort_by_cell(self.h, ws.h, src.struct(), dst.struct(), grid_field)
+
+    def __del__(self):
+        h, self.h = getattr(self, "h", None), None
+        if h:
+            B.qed_sorter_free(h)
+
+
 def plane_wave(a0: float, n_periods: float = 10.0) -> B.qed_field:
     f = B.qed_field()
     f.kind = B.QED_FIELD_PLANE_WAVE

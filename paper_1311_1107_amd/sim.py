@@ -31,7 +31,7 @@ class Run:
                  photon_capacity: int | None = None, record_capacity: int | None = None,
                  pair_capacity: int | None = None, rad_model: int = B.QED_RAD_HYBRID,
                  chi_switch: float = 1e-3, gamma_photon_min: float = 2.0, max_events: int = 4,
-                 sched: B.qed_schedule | None = None, compact_every: int = 16,
+                 sched: B.qed_schedule | None = None, compact_every: int = 16, sort_every: int = 0,
                  deterministic_tally: bool = True, device: str = "cuda"):
         self.wl = wl
         self.prec = prec
@@ -74,12 +74,35 @@ class Run:
             self.field = D.yee(self.grid, f.shape, f.spacing, f.origin)
         else:
             raise TypeError("unknown field description")
+        # cell ordering (Yee field only): a second buffer per species, swapped after each sort
+        self.sort_every = sort_every if self.grid is not None else 0
+        if self.sort_every:
+            self.sorter = D.Sorter(max(caps))
+            self.alt = {"el": D.Species(self.el.capacity, prec, chi=True, device=device),
+                        "po": D.Species(self.po.capacity, prec, chi=True, device=device)}
+            if self.ph is not None:
+                self.alt["ph"] = D.Species(self.ph.capacity, prec, chi=True, device=device)
+        self._photon_view()
+
+    def _photon_view(self):
         # photon view whose count is the snapshot taken at the start of a step
         if self.ph is not None:
             s = self.ph.struct()
             self.ph_step = B.qed_species()
             C.memmove(C.addressof(self.ph_step), C.addressof(s), C.sizeof(s))
             self.ph_step.d_count = self.ph_snap.data_ptr()
+
+    def sort(self):
+        """Stable cell order of every species (drops decayed photons)."""
+        for name in ("el", "po", "ph"):
+            src = getattr(self, name)
+            if src is None:
+                continue
+            dst = self.alt[name]
+            self.sorter.sort(self.ws, src, dst, self.field)
+            setattr(self, name, dst)
+            self.alt[name] = src
+        self._photon_view()
 
     # ------------------------------------------------------------------
     def fill_field(self, n: int):
@@ -89,23 +112,29 @@ class Run:
             tp = self.tpar[n].reshape(-1)
             B.qed_yee_fill_separable(self.grid.data_ptr(), nx, ny, nz, f.a0, self.tperp.data_ptr(), tp.data_ptr())
 
-    def step(self, n: int):
+    def step(self, n: int, timed=None):
+        """Step n.  `timed(kind, fn)`, if given, wraps every launch (for timing)."""
+        run = timed or (lambda kind, fn: fn())
         st = D.step(n * self.wl.dt, self.wl.dt, self.wl.seed, **self.step_kw)
-        self.fill_field(n)
+        if self.grid is not None:
+            run("fill", lambda: self.fill_field(n))
         if self.ph is not None:
             self.ph_snap.copy_(self.ph.count)
         pp = self.ph.struct() if self.ph is not None else None
         pr = self.rec.struct() if self.rec is not None else None
         uid = self.uid_next.data_ptr()
-        B.qed_push_emit(self.tables.h, self.ws.h, self.units, -1.0, self.el.struct(), self.field, pp, pr,
-                        self.tally.s, st, uid, self.sched)
-        B.qed_push_emit(self.tables.h, self.ws.h, self.units, +1.0, self.po.struct(), self.field, pp, pr,
-                        self.tally.s, st, uid, self.sched)
+        run("push_e", lambda: B.qed_push_emit(self.tables.h, self.ws.h, self.units, -1.0, self.el.struct(),
+                                              self.field, pp, pr, self.tally.s, st, uid, self.sched))
+        run("push_p", lambda: B.qed_push_emit(self.tables.h, self.ws.h, self.units, +1.0, self.po.struct(),
+                                              self.field, pp, pr, self.tally.s, st, uid, self.sched))
         if self.ph is not None:
-            B.qed_pair_create(self.tables.h, self.ws.h, self.units, self.ph_step, self.field, self.el.struct(),
-                              self.po.struct(), self.tally.s, st, uid, self.sched)
+            run("pair", lambda: B.qed_pair_create(self.tables.h, self.ws.h, self.units, self.ph_step, self.field,
+                                                  self.el.struct(), self.po.struct(), self.tally.s, st, uid,
+                                                  self.sched))
             if self.compact_every and (n + 1) % self.compact_every == 0:
-                self.compact()
+                run("compact", self.compact)
+        if self.sort_every and (n + 1) % self.sort_every == 0:
+            run("sort", self.sort)
 
     def compact(self):
         if self.ph is not None:

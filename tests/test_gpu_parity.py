@@ -188,23 +188,24 @@ def _sensitivity(a: dict, b: dict) -> np.ndarray:
     return np.linalg.norm(ua - ub, axis=1) / np.maximum(np.linalg.norm(ua, axis=1), 1.0)
 
 
-def test_yee_pairs_fp64_parity(gpu_oracle_tables, bound_tables):
-    """Yee grid, pushed photons and Breit-Wheeler pairs.  Counts and ids are
-    bit-exact.  Low-gamma secondaries in this a0 = 800 field amplify rounding:
-    the oracle itself, run again with one input moved by one ulp, differs by
-    up to ~1e-11 for a few of them.  So at least 99 % of the momenta must
-    agree within 1e-12 and all within 100 x the oracle's worst one-ulp
-    self-sensitivity in this run."""
+@pytest.mark.parametrize("sort_every", [0, 5])
+def test_yee_pairs_fp64_parity(gpu_oracle_tables, bound_tables, sort_every):
+    """Yee grid, pushed photons and Breit-Wheeler pairs, with and without
+    cell ordering every 5 steps.  Counts and ids are bit-exact.  Low-gamma
+    secondaries in this a0 = 800 field amplify rounding: the oracle itself,
+    run again with one input moved by one ulp, differs by up to ~1e-11 for a
+    few of them.  So at least 99 % of the momenta must agree within 1e-12 and
+    all within 100 x the oracle's worst one-ulp self-sensitivity in this run."""
     wl = _yee_small()
-    print("case: Yee 64x32x32 n=2000 steps=260 seed=12", flush=True)
-    caps = dict(photon_capacity=80 * 2000, record_capacity=8 * 2000, pair_capacity=12 * 2000)
-    want = oracle_run(wl, bound_tables, wl.steps, **caps)
+    print(f"case: Yee 64x32x32 n=2000 steps=260 seed=12 sort_every={sort_every}", flush=True)
+    caps = dict(photon_capacity=160 * 2000, record_capacity=8 * 2000, pair_capacity=12 * 2000)
+    want = oracle_run(wl, bound_tables, wl.steps, sort_every=sort_every, **caps)
     assert want["tally"]["N_overflow"] == 0
     assert want["tally"]["N_pair"] > 1000 and want["tally"]["N_cap"] > 0
     wl_p = _yee_small()
     wl_p.electrons["ux"] = np.nextafter(wl_p.electrons["ux"], 0.0)
-    pert = oracle_run(wl_p, bound_tables, wl.steps, **caps)
-    run = S.Run(wl, tables=gpu_oracle_tables, compact_every=7, **caps)
+    pert = oracle_run(wl_p, bound_tables, wl.steps, sort_every=sort_every, **caps)
+    run = S.Run(wl, tables=gpu_oracle_tables, compact_every=7, sort_every=sort_every, **caps)
     run.run(wl.steps)
     got = run.result()
     for sp in ("electrons", "positrons", "photons", "recorded"):
@@ -224,6 +225,81 @@ def test_yee_pairs_fp64_parity(gpu_oracle_tables, bound_tables):
         if k.startswith("N_"):
             assert got["tally"][k] == v, k
     run.ws.status()
+
+
+# ------------------------------------------------------------ cell order ----
+SORT_SHAPE, SORT_SPACING, SORT_ORIGIN = (16, 8, 12), (0.5, 0.25, 0.75), (-1.0, 0.5, 2.0)
+
+
+def _sort_particles(n, seed, prec):
+    r = np.random.default_rng(seed)
+    lo = np.array(SORT_ORIGIN)
+    hi = lo + np.array(SORT_SHAPE) * np.array(SORT_SPACING)
+    pos = r.uniform(lo - 0.5, hi + 0.5, size=(n, 3))
+    m = n // 4                                    # on cell faces: ties and edges
+    pos[:m] = lo + np.floor(r.uniform(0, 1, (m, 3)) * SORT_SHAPE) * SORT_SPACING
+    ft = np.float64 if prec == B.QED_F64 else np.float32
+    p = {"x": pos[:, 0], "y": pos[:, 1], "z": pos[:, 2]}
+    for k in ("ux", "uy", "uz", "w", "chi"):
+        p[k] = r.normal(size=n)
+    p = {k: v.astype(ft).astype(np.float64) for k, v in p.items()}
+    tau = r.exponential(size=n)
+    tau[r.random(n) < 0.2] = np.inf               # decayed photons
+    p["tau"] = tau
+    p["uid"] = r.permutation(np.arange(7, 7 + n, dtype=np.uint64))
+    p["n_ev"] = r.integers(0, 5, n).astype(np.uint32)
+    return p
+
+
+@pytest.mark.parametrize("prec,n", [(B.QED_F64, 0), (B.QED_F64, 1), (B.QED_F64, 3 * 4096 + 77),
+                                    (B.QED_F64, 1_200_013), (B.QED_F32, 50_001)])
+def test_sort_by_cell_matches_oracle(prec, n):
+    """qed_sort_by_cell against the oracle's stable cell sort of the live
+    particles: bit-exact permutation and fields; decayed photons dropped.
+    1.2e6 particles take the histogram scan over several look-back blocks."""
+    _need_gpu()
+    print(f"case: sort prec={prec} n={n}", flush=True)
+    p = _sort_particles(n, seed=21 + n, prec=prec)
+    cap = n + 5
+    src = D.Species(cap, prec)
+    src.upload(p)
+    dst = D.Species(cap, prec)
+    ws = D.Workspace(cap)
+    so = D.Sorter(cap)
+    grid = torch.zeros(6, dtype=torch.float32, device="cuda")
+    f = D.yee(grid, SORT_SHAPE, SORT_SPACING, SORT_ORIGIN)
+    for _ in range(2):                            # a second call reuses sorter and workspace
+        so.sort(ws, src, dst, f)
+        torch.cuda.synchronize()
+        got = dst.download()
+        live = np.isfinite(p["tau"])
+        o = O.species_from({k: v[live] for k, v in p.items()})
+        O.sort_by_cell(o, SORT_SHAPE, SORT_SPACING, SORT_ORIGIN)
+        want = O.view(o)
+        assert len(got["x"]) == int(live.sum())
+        for k in ("uid", "n_ev", "tau", "x", "y", "z", "ux", "uy", "uz", "w", "chi"):
+            assert np.array_equal(got[k].astype(want[k].dtype), want[k]), k
+    ws.status()
+
+
+def test_sort_rejects_bad_arguments():
+    _need_gpu()
+    src = D.Species(100)
+    small = D.Species(50)
+    ws = D.Workspace(100)
+    so = D.Sorter(100)
+    grid = torch.zeros(6, dtype=torch.float32, device="cuda")
+    f = D.yee(grid, SORT_SHAPE, SORT_SPACING, SORT_ORIGIN)
+    with pytest.raises(B.QedError):
+        so.sort(ws, src, small, f)                # destination too small
+    with pytest.raises(B.QedError):
+        so.sort(ws, src, src, f)                  # aliased
+    with pytest.raises(B.QedError):
+        so.sort(ws, src, D.Species(100, B.QED_F32), f)
+    with pytest.raises(B.QedError):
+        so.sort(ws, src, D.Species(100), D.plane_wave(1.0))
+    with pytest.raises(B.QedError):
+        D.Sorter(10).sort(ws, src, D.Species(100), f)
 
 
 # --------------------------------------------------------- batched form ----
