@@ -178,19 +178,23 @@ def main():
     lepton_steps = tal["N_mc"] + tal["N_sokolov"] + tal["N_nan"]
     photon_steps = tal["N_phstep"]
     psteps = lepton_steps + photon_steps
-    # algorithmic bytes (FP64): lepton x,u read+write 96 B, tau read+write 16 B, weight 8 B;
-    # per emission uid/n_event 16 B; per stored photon 84 B written.
-    # photon step: x,k,tau read 56 B, x,tau written 32 B; per pair 20 B read + 2 x 84 B written.
+    # algorithmic bytes per unit (es = 8 for FP64, 4 for FP32 reals; tau is always FP64):
+    #   lepton-step: x,u read and written 12 es, tau read and written 16 B, weight read es (energy tally)
+    #   emission event: uid read 8 B, n_event read and written 8 B
+    #   stored photon: x, k, w, chi 8 es, tau 8 B, uid 8 B, n_event 4 B written
+    #   photon-step: x, k, tau read 6 es + 8 B; x, tau written 3 es + 8 B
+    #   pair event: photon x, k, w read 7 es, tau written 8 B, two leptons written 2 (8 es + 20 B)
     es = 8 if prec == B.QED_F64 else 4
-    lep_bytes = lepton_steps * (12 * es + 16 + es) + tal["N_emit"] * 16 + (tal["N_push"] + tal["N_rec"]) * (10 * es + 12)
-    ph_bytes = photon_steps * (7 * es + 8 + 3 * es + 8) + tal["N_pair"] * (20 + 2 * (10 * es + 12))
+    rec_bytes = 8 * es + 20
+    lep_bytes = lepton_steps * (13 * es + 16) + tal["N_emit"] * 16 + (tal["N_push"] + tal["N_rec"]) * rec_bytes
+    ph_bytes = photon_steps * (9 * es + 16) + tal["N_pair"] * (7 * es + 8 + 2 * rec_bytes)
     push_ms = kernel_ms.get("push_e", 0) + kernel_ms.get("push_p", 0)
     pair_ms = kernel_ms.get("pair", 0)
     if pair_ms >= push_ms:
         dom, dom_bytes, dom_ms, dom_n = "qed_pair_create (photon step)", ph_bytes, pair_ms, n_launch.get("pair", 1)
     else:
         dom, dom_bytes, dom_ms = "qed_push_emit (lepton step)", lep_bytes, push_ms
-        dom_n = n_launch.get("push_e", 1)
+        dom_n = n_launch.get("push_e", 0) + n_launch.get("push_p", 0)
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
 
     out = {

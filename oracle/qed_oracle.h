@@ -175,7 +175,11 @@ int or_push_emit(const or_tables *tab, const or_units *u, double q,
 /* One step of the pushed photons [0, n_limit): Breit-Wheeler decay into pairs
  * (Sec. 3), straight-line push of the survivors and stable removal of decayed
  * photons.  Photons from n_limit on were created in the current step and are
- * left as they are (moved down behind the survivors). */
+ * left as they are (moved down behind the survivors).
+ * The paper fixes only chi_+ = chi_gamma - chi_-.  The split of the energy,
+ * gamma_pm = 1 + (gamma_gamma - 2) chi_pm/chi_gamma along the photon direction,
+ * is a reading: pinned by energy and chi conservation, its partition is
+ * parity unpinned by the paper. */
 int or_pair_create(const or_tables *tab, const or_units *u,
                    or_species *ph, int64_t n_limit, const or_field *f,
                    or_species *elec, or_species *posi,

@@ -1,13 +1,16 @@
 // qed_kernels.hip -- gfx950 kernels of the per-particle radiation and QED step
 // (Lobet et al., arXiv:1311.1107, Secs. 2-3).
 //
-// All particle kernels are persistent: a fixed grid of workgroups takes tiles
-// of consecutive particles from a ticket counter, so tiles are processed in
-// index order and the decoupled look-back sees its predecessors running.
+// The particle kernels are persistent: a fixed grid of workgroups walks tiles
+// of consecutive particles, each XCD taking a contiguous range of tiles.
 // Particles are structure-of-arrays; each tile reads and writes its particles
-// once with coalesced accesses; new particles are appended at offsets given by
-// a wave-ballot/shuffle scan within the tile plus the look-back prefix across
-// tiles, which reproduces the serial order of the parents.
+// once with coalesced accesses.  A step that creates particles runs in three
+// passes: the physics pass advances every particle and records per-tile
+// append counts (and, for emissions, a staged record per emitting particle),
+// a scan pass forms the prefixes over tiles with a decoupled look-back, and an
+// append pass writes the new particles at tile prefix + in-tile rank, which
+// reproduces the serial order of the parents.  The in-place compaction keeps
+// the single-pass ticketed look-back.
 #include "qed_kernels.h"
 
 namespace qed {

@@ -9,6 +9,8 @@ Order within step n (time t = n dt):
      (qed_pair_create); photons emitted in 2-3 are stored at level n+1 and
      are first advanced at step n+1, as are the pairs created in 4
   5. every `compact_every` steps, decayed photons are removed (qed_compact)
+  6. (Yee field) every `sort_every` steps, every species is put in stable cell
+     order (qed_sort_by_cell), which also drops decayed photons
 """
 from __future__ import annotations
 
@@ -127,13 +129,15 @@ class Run:
                                               self.field, pp, pr, self.tally.s, st, uid, self.sched))
         run("push_p", lambda: B.qed_push_emit(self.tables.h, self.ws.h, self.units, +1.0, self.po.struct(),
                                               self.field, pp, pr, self.tally.s, st, uid, self.sched))
+        sorting = bool(self.sort_every) and (n + 1) % self.sort_every == 0
         if self.ph is not None:
             run("pair", lambda: B.qed_pair_create(self.tables.h, self.ws.h, self.units, self.ph_step, self.field,
                                                   self.el.struct(), self.po.struct(), self.tally.s, st, uid,
                                                   self.sched))
-            if self.compact_every and (n + 1) % self.compact_every == 0:
+            # the cell sort drops decayed photons itself
+            if self.compact_every and (n + 1) % self.compact_every == 0 and not sorting:
                 run("compact", self.compact)
-        if self.sort_every and (n + 1) % self.sort_every == 0:
+        if sorting:
             run("sort", self.sort)
 
     def compact(self):
