@@ -41,6 +41,8 @@ def parse():
                    help="run a 1 GiB device copy first (reference for the traffic counters)")
     p.add_argument("--compact-every", type=int, default=16)
     p.add_argument("--sort-every", type=int, default=16, help="cell-order the particles every k steps (Yee)")
+    p.add_argument("--batched-steps", type=int, default=1000,
+                   help="steps of the FP32-batched vs FP64-plain comparison (0 skips it)")
     return p.parse_args()
 
 
@@ -83,6 +85,93 @@ def cpu_baseline(wl, n_sample: int, steps: int):
     return {"value": ps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"{m} electrons (uid subset) of the same workload, {steps} steps, "
                       f"{ps} particle-steps in {dt:.1f} s, single thread"}
+
+
+def batched_comparison(steps: int, seed: int = 4):
+    """The batched-form bunches (64 bunches, sizes log-uniform 1e3..1e6,
+    a0 ~ U(50, 500), gamma0 ~ U(500, 5000), plane waves): FP64 plain (one
+    launch per bunch per step, eager) against FP32 batched (one persistent
+    launch per step, autotuned schedule, HIP-graph replays), and the KS test
+    of their photon spectra (same seed, and seed + 1000 for the FP32 run)."""
+    import numpy as np
+    import torch
+    from scipy import stats
+
+    from paper_1311_1107_amd import batched as BT
+    from paper_1311_1107_amd import binding as B
+    from paper_1311_1107_amd import device as D
+    from paper_1311_1107_amd import sim as S
+    from paper_1311_1107_amd import workloads as W
+
+    e, off, a0s, _ = W.bunches(n_bunches=64, seed=seed)
+    n = len(e["x"])
+    tabs = D.Tables(S.EMIT_SPEC, S.PAIR_SPEC)
+    cap = 40 * n
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(stream)
+        fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b)
+
+    def photon_gamma(bun, m=400_000):
+        k = bun.rec.n()
+        rng = np.random.default_rng(0)
+        idx = torch.from_numpy(np.sort(rng.integers(0, k, size=min(m, k)))).cuda()
+        g = torch.sqrt(bun.rec.a["ux"][idx].double() ** 2 + bun.rec.a["uy"][idx].double() ** 2 +
+                       bun.rec.a["uz"][idx].double() ** 2)
+        return g.cpu().numpy()
+
+    def finish(bun, ms):
+        rc, _ = bun.ws.status(raise_on_error=False)
+        tal = bun.tally.reduce()
+        ps = tal["N_mc"] + tal["N_sokolov"] + tal["N_nan"]
+        return {"ms_per_step": ms / steps, "particle_steps_per_s": ps / (ms * 1e-3), "photons": bun.rec.n(),
+                "emissions": tal["N_emit"], "status": int(rc)}
+
+    # FP64 plain
+    plain = BT.Bunches(e, off, a0s, B.QED_F64, tabs, seed=seed, record_capacity=cap)
+    ms = timed(lambda: [plain.step_plain(k) for k in range(steps)])
+    r_plain = finish(plain, ms)
+    g_plain = photon_gamma(plain)
+    del plain
+    torch.cuda.empty_cache()
+    print("bench: FP64 plain bunches done", file=sys.stderr, flush=True)
+
+    def fp32_batched(sd):
+        bun = BT.Bunches(e, off, a0s, B.QED_F32, tabs, seed=sd, record_capacity=cap)
+        best, _ = bun.autotune(trial_steps=3)
+        chunk = 10
+        bun.capture(chunk)
+        ms = timed(lambda: [bun.replay() for _ in range(steps // chunk)])
+        out = finish(bun, ms)
+        out["schedule"] = {"block": best.block, "blocks_per_cu": best.blocks_per_cu}
+        out["graph_steps"] = chunk
+        return bun, out
+
+    bun, r_b = fp32_batched(seed)
+    g_b = photon_gamma(bun)
+    del bun
+    torch.cuda.empty_cache()
+    bun, r_c = fp32_batched(seed + 1000)
+    g_c = photon_gamma(bun)
+    del bun
+    torch.cuda.empty_cache()
+    print("bench: FP32 batched bunches done", file=sys.stderr, flush=True)
+    return {
+        "workload": f"{len(a0s)} bunches, {n} e- (sizes 10^U(3,6)), a0 ~ U(50,500), gamma0 ~ U(500,5000), "
+                    f"plane waves, {steps} steps, photons recorded",
+        "fp64_plain": r_plain, "fp32_batched_graph": r_b,
+        "speedup": r_plain["ms_per_step"] / r_b["ms_per_step"],
+        "ks_photon_gamma_same_seed_p": float(stats.ks_2samp(g_plain, g_b).pvalue),
+        "ks_photon_gamma_seed_plus_1000_p": float(stats.ks_2samp(g_plain, g_c).pvalue),
+        "ks_sample": len(g_plain),
+    }
 
 
 def main():
@@ -216,6 +305,10 @@ def main():
                    "launches": n_launch, "final_counts": counts, "emissions": tal["N_emit"], "pairs": tal["N_pair"],
                    "status": int(rc), "lepton_bytes": lep_bytes, "photon_bytes": ph_bytes},
     }
+    if args.batched_steps > 0:
+        del run
+        torch.cuda.empty_cache()
+        out["batched_vs_plain"] = batched_comparison(args.batched_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample, K)
     print(json.dumps(out), flush=True)

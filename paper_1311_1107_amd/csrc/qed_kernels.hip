@@ -542,28 +542,30 @@ __device__ __forceinline__ uint32_t list_tiles(const uint32_t *cnt, int64_t c, i
 template <typename R>
 __global__ void __launch_bounds__(256)
 k_push_append(PushArgs a) {
-    __shared__ uint32_t s_wave[3 * kMaxWaves];
-    __shared__ uint32_t s_list[256];
     __shared__ int64_t s_cnt[N_COUNT_USED];
-    const int tid = threadIdx.x;
     const int64_t n = *a.lep.count;
     const int64_t tile_sz = a.tile_sz;
     const int64_t n_tiles = (n + tile_sz - 1) / tile_sz;
-    const int64_t n_chunks = (n_tiles + blockDim.x - 1) / blockDim.x;
     const LaunchInfo info = *a.ws.info;
     const R dtr = (R)a.st.dt;
     const R *rec = (const R *)a.ws.stage.rec;
     const int64_t slots = a.ws.stage.slots;
+    const int wid = threadIdx.x / kWave, nw = blockDim.x / kWave, lane = lane_id();
     int cnt[N_COUNT_USED];
 #pragma unroll
     for (int k = 0; k < N_COUNT_USED; ++k) cnt[k] = 0;
-    for (int64_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
-        const uint32_t m = list_tiles(a.ws.stage.n_rec, c, n_tiles, s_list, s_wave);
-        for (uint32_t qi = 0; qi < m; ++qi) {
-            const int64_t tile = c * blockDim.x + s_list[qi];
-            const uint32_t nrec = a.ws.stage.n_rec[tile];
-            const bool have = tid < (int)nrec;
-            const int64_t sl = tile * tile_sz + tid;
+    // the block walks the physics blocks' tiles (same grid, same XCD), one
+    // tile per wave; a wave writes a tile's records 64 at a time, in order
+    for (int64_t it = wid;; it += nw) {
+        const int64_t tile = xcd_tile(it, n_tiles);
+        if (tile < 0) break;
+        const uint32_t nrec = a.ws.stage.n_rec[tile];
+        if (nrec == 0u) continue;
+        uint32_t base0 = a.ws.tile_pre0[tile], base1 = a.ws.tile_pre1[tile];
+        for (uint32_t r0 = 0; r0 < nrec; r0 += kWave) {
+            const uint32_t r = r0 + (uint32_t)lane;
+            const bool have = r < nrec;
+            const int64_t sl = tile * tile_sz + r;
             uint32_t meta = 0, c0 = 0, c1 = 0;
             if (have) {
                 meta = a.ws.stage.meta[sl];
@@ -576,10 +578,11 @@ k_push_append(PushArgs a) {
                         c1 += d == 1u;
                     }
             }
-            uint32_t e0, e1, t0, t1;
-            block_scan2(c0, c1, e0, e1, t0, t1, s_wave);
+            // both counts in one scan: at most 4 x 256 per tile, so 16 bits each
+            uint32_t tot;
+            const uint32_t ex = wave_excl_scan(c0 | (c1 << 16), tot);
             if (have) {
-                uint32_t g0 = a.ws.tile_pre0[tile] + e0, g1 = a.ws.tile_pre1[tile] + e1;
+                uint32_t g0 = base0 + (ex & 0xffffu), g1 = base1 + (ex >> 16);
                 const R x0 = rec[0 * slots + sl], y0 = rec[1 * slots + sl], z0 = rec[2 * slots + sl];
                 const R hx = rec[3 * slots + sl], hy = rec[4 * slots + sl], hz = rec[5 * slots + sl];
                 const R wgt = rec[6 * slots + sl];
@@ -608,7 +611,8 @@ k_push_append(PushArgs a) {
                     S.tau[j] = initial_tau(a.st.seed, nid);
                 }
             }
-            __syncthreads();
+            base0 += tot & 0xffffu;
+            base1 += tot >> 16;
         }
     }
     block_counts(a.tal, cnt, s_cnt);

@@ -414,3 +414,69 @@ def test_fp32_spectra_ks(gpu_oracle_tables, bound_tables):
         p = ks_2samp(g_g, g_w).pvalue
         print(f"FP32 photon spectrum KS seed {seed}: p = {p:.3g} ({len(g_g)} vs {len(g_w)})", flush=True)
         assert p > 0.01
+
+
+# ------------------------------------------------- graph and autotuner ----
+def _small_bunches(prec, tabs, seed=4):
+    from paper_1311_1107_amd import batched as BT
+    e, off, a0s = _bunch_setup(seed=seed)
+    return BT.Bunches(e, off, a0s, prec, tabs, seed=seed, record_capacity=16 * len(e["x"]))
+
+
+def _snapshot(bun):
+    torch.cuda.synchronize()
+    el = bun.el.download()
+    rec = bun.rec.download()
+    return {"el": el, "rec": rec, "uid": int(bun.uid.item()), "step": int(bun.d_step.item())}
+
+
+def _same(a, b):
+    assert a["uid"] == b["uid"] and a["step"] == b["step"]
+    for part in ("el", "rec"):
+        for k in a[part]:
+            assert np.array_equal(a[part][k], b[part][k]), (part, k)
+
+
+@pytest.mark.parametrize("prec", [B.QED_F32, B.QED_F64])
+def test_graph_replay_matches_eager(gpu_oracle_tables, prec):
+    """Five batched steps captured in a HIP graph and replayed three times,
+    with eager work and synchronisations between the replays, give exactly
+    the state of fifteen eager steps after every replay."""
+    print(f"case: graph replay prec={prec}", flush=True)
+    eager = _small_bunches(prec, gpu_oracle_tables)
+    snaps = []
+    for k in range(15):
+        eager.step_batched()
+        if (k + 1) % 5 == 0:
+            snaps.append(_snapshot(eager))
+    g = _small_bunches(prec, gpu_oracle_tables)
+    g.capture(5)
+    assert int(g.d_step.item()) == 0 and g.rec.n() == 0          # capture runs nothing
+    scratch = torch.arange(1 << 16, dtype=torch.float64, device="cuda")
+    for r in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        _same(_snapshot(g), snaps[r])
+        scratch.mul_(1.5).sum().item()                             # eager work between replays
+        g.tally.reduce()
+    g.ws.status()
+
+
+def test_autotune_leaves_state_and_caches(gpu_oracle_tables, tmp_path):
+    from paper_1311_1107_amd import batched as BT
+    bun = _small_bunches(B.QED_F32, gpu_oracle_tables)
+    bun.step_batched()
+    before = _snapshot(bun)
+    cache = str(tmp_path / "tune.txt")
+    best, ms = bun.autotune(trial_steps=2, cache_path=cache)
+    assert (best.block, best.blocks_per_cu) in BT.CANDIDATES and ms > 0
+    _same(_snapshot(bun), before)                                  # trials run on scratch state
+    best2, ms2 = bun.autotune(trial_steps=2, cache_path=cache)     # read back from the cache
+    assert (best2.block, best2.blocks_per_cu) == (best.block, best.blocks_per_cu) and ms2 == pytest.approx(ms, rel=1e-3)
+    # the tuned schedule gives the same result as the default one
+    ref = _small_bunches(B.QED_F32, gpu_oracle_tables)
+    for _ in range(4):
+        ref.step_batched()
+    for _ in range(3):
+        bun.step_batched()
+    _same(_snapshot(bun), _snapshot(ref))
