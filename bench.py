@@ -46,6 +46,30 @@ def parse():
     return p.parse_args()
 
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "qed_pair_create_yee1e7_f64_traffic.md")
+KERNEL_SOURCES = ["paper_1311_1107_amd/csrc/qed_kernels.hip", "paper_1311_1107_amd/csrc/qed_kernels.h",
+                  "paper_1311_1107_amd/csrc/qed_device.h"]
+
+
+def measured_traffic():
+    """HBM bytes per qed_pair_create call from the committed counter summary,
+    or None if the kernel sources have changed since the counters were taken."""
+    import hashlib
+
+    try:
+        lines = open(TRAFFIC_SUMMARY).read().splitlines()
+    except OSError:
+        return None
+    vals = dict(l.split(": ", 1) for l in lines if l.startswith(("traffic_bytes_per_call: ", "kernel_source_sha256: ")))
+    h = hashlib.sha256()
+    for src in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if vals.get("kernel_source_sha256") != h.hexdigest() or "traffic_bytes_per_call" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_call"])
+
+
 def cpu_baseline(wl, n_sample: int, steps: int):
     """The oracle, single-threaded, on a fixed uid subset of the same workload."""
     import numpy as np
@@ -299,7 +323,10 @@ def main():
                    "steps_timed": K, "dt": wl.dt, "compact_every": args.compact_every,
                    "sort_every": args.sort_every},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     # counters were taken on the default command: 1e7 electrons, 2000 steps, sort/compact every 16
+                     "traffic": (measured_traffic() if dom.startswith("qed_pair_create") and K == 2000 and n0 == 10_000_000
+                                 and args.sort_every == 16 and args.compact_every == 16 else None),
                      "bytes_per_launch": dom_bytes / max(dom_n, 1), "avg_launch_ms": dom_ms / max(dom_n, 1)},
         "detail": {"lepton_steps": lepton_steps, "photon_steps": photon_steps, "kernel_ms": kernel_ms,
                    "launches": n_launch, "final_counts": counts, "emissions": tal["N_emit"], "pairs": tal["N_pair"],
