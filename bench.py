@@ -198,6 +198,181 @@ def batched_comparison(steps: int, seed: int = 4):
     }
 
 
+def _timed_steps(run, K, stream):
+    """K steps of a sim.Run with HIP events around every library call."""
+    import torch
+
+    evs = {}
+
+    def timed(kind, fn):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        evs.setdefault(kind, []).append((a, b))
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for n in range(K):
+        run.step(n, timed=timed)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = {k: sum(a.elapsed_time(b) for a, b in v) for k, v in evs.items() if v}
+    return wall, kernel_ms, {k: len(v) for k, v in evs.items() if v}
+
+
+def _energy_balance(run, res, init_el):
+    """|dK - W_field + E_rad + E_gamma + E_sub - E_pair| / (E_rad + E_gamma + E_sub) over a run."""
+    import numpy as np
+
+    def kin(sp):
+        u2 = sp["ux"].astype(np.float64) ** 2 + sp["uy"].astype(np.float64) ** 2 + sp["uz"].astype(np.float64) ** 2
+        return float(np.sum(sp["w"].astype(np.float64) * (np.sqrt(1.0 + u2) - 1.0)))
+
+    t = res["tally"]
+    k0 = kin(init_el)
+    k1 = kin(res["electrons"]) + kin(res["positrons"])
+    e_gamma = t["E_epush"] + t["E_erec"] + t["E_edrop"]
+    # pairs: the created leptons carry E_pair - 2 (rest mass) per pair weight; E_pair is the photons' energy
+    denom = t["E_erad"] + e_gamma + t["E_esub"]
+    return abs((k1 - k0) - t["E_work"] + t["E_erad"] + e_gamma + t["E_esub"] - t["E_epair"]) / max(denom, 1e-300)
+
+
+def bench_plane(args):
+    """Plane-wave beam (1e5 e-, gamma0 2000, a0 = 100, 1000 steps, photons
+    recorded): the FP64 plain form and the FP32 form on the same electrons."""
+    import numpy as np
+    import torch
+    from scipy import stats
+
+    from paper_1311_1107_amd import binding as B
+    from paper_1311_1107_amd import sim as S
+    from paper_1311_1107_amd import workloads as W
+
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, prec, seed in (("f64", B.QED_F64, 1), ("f32", B.QED_F32, 1), ("f32_seed1001", B.QED_F32, 1001)):
+        wl = W.plane_wave_beam(n=args.electrons or 100_000)
+        wl.seed = seed
+        n0 = len(wl.electrons["x"])
+        K = min(args.steps or wl.steps, wl.steps)
+        run = S.Run(wl, prec=prec, record_capacity=40 * n0)
+        init_el = run.el.download()
+        wall, kms, nl = _timed_steps(run, K, stream)
+        rc, _ = run.ws.status(raise_on_error=False)
+        r = run.result()
+        t = r["tally"]
+        ps = t["N_mc"] + t["N_sokolov"] + t["N_nan"]
+        rec = r["recorded"]
+        gam = np.sqrt(rec["ux"].astype(np.float64) ** 2 + rec["uy"].astype(np.float64) ** 2 + rec["uz"].astype(np.float64) ** 2)
+        res[name] = {"pss": ps / wall, "ms_per_step": wall * 1e3 / K, "kernel_ms": kms, "launches": nl,
+                     "photons": len(gam), "emissions": t["N_emit"], "status": int(rc),
+                     "energy_balance": _energy_balance(run, r, init_el), "gamma": gam, "K": K, "n0": n0,
+                     "lep_steps": ps, "N_push": t["N_push"], "N_rec": t["N_rec"], "N_emit": t["N_emit"]}
+        del run
+        torch.cuda.empty_cache()
+    f64, f32 = res["f64"], res["f32"]
+    es = 8
+    lep_bytes = f64["lep_steps"] * (13 * es + 16) + f64["N_emit"] * 16 + (f64["N_push"] + f64["N_rec"]) * (8 * es + 20)
+    push_ms = f64["kernel_ms"].get("push_e", 0.0)
+    achieved = lep_bytes / (push_ms * 1e-3) / 1e9 if push_ms > 0 else 0.0
+    n_l = f64["launches"].get("push_e", 1)
+    out = {
+        "metric": "QED particle-steps/s", "value": f64["pss"], "unit": "particle-steps/s", "n_gpus": 1,
+        "steps": f64["K"], "warmup": 0, "ms_per_step": f64["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{f64['n0']} e- gamma0 2000 (1% spread) vs a0=100 10-period plane wave, "
+                               f"{f64['K']} steps, photons recorded (FP64 plain)"},
+        "roofline": {"bound": "hbm", "kernel": "qed_push_emit (lepton step)", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": lep_bytes / n_l, "avg_launch_ms": push_ms / n_l,
+                     "note": "working set ~11 MB per step: cache-resident and launch-bound"},
+        "fp32_form": {"value": f32["pss"], "ms_per_step": f32["ms_per_step"], "speedup": f32["pss"] / f64["pss"],
+                      "ks_photon_gamma_same_seed_p": float(stats.ks_2samp(f64["gamma"], f32["gamma"]).pvalue),
+                      "ks_photon_gamma_seed_plus_1000_p": float(stats.ks_2samp(f64["gamma"], res["f32_seed1001"]["gamma"]).pvalue),
+                      "photons_f64": f64["photons"], "photons_f32": f32["photons"],
+                      "energy_balance_f64": f64["energy_balance"], "energy_balance_f32": f32["energy_balance"]},
+        "detail": {k: {kk: vv for kk, vv in v.items() if kk != "gamma"} for k, v in res.items()},
+    }
+    return out
+
+
+def bench_cascade(args):
+    """High-chi cascade: 5e7 e-, gamma0 1e4, a0 = 1000 plane wave, 500 steps,
+    FP32 form; photons with chi_gamma > 0.2 at creation are pushed and tested
+    for pairs, the rest tallied; decayed photons compacted every step."""
+    import torch
+
+    from paper_1311_1107_amd import binding as B
+    from paper_1311_1107_amd import sim as S
+    from paper_1311_1107_amd import workloads as W
+
+    wl = W.cascade_beam(n=args.electrons or 50_000_000)
+    n0 = len(wl.electrons["x"])
+    K = min(args.steps or wl.steps, wl.steps)
+    run = S.Run(wl, prec=B.QED_F32, photon_capacity=4 * n0, pair_capacity=4 * n0, compact_every=1)
+    stream = torch.cuda.current_stream()
+    growth = []
+    chunk = 10
+    wall = 0.0
+    kms, nl = {}, {}
+    done = 0
+    stopped = None
+    while done < K:
+        k = min(chunk, K - done)
+        # the chunk's steps continue the run's step numbering
+        w, km, n_ = _timed_steps(_Offset(run, done), k, stream)
+        wall += w
+        for key, v in km.items():
+            kms[key] = kms.get(key, 0.0) + v
+        for key, v in n_.items():
+            nl[key] = nl.get(key, 0) + v
+        done += k
+        rc, rep = run.ws.status(clear=False, raise_on_error=False)
+        if done % 50 == 0 or rc != 0:
+            growth.append({"step": done, **run.counts()})
+            print(f"bench: cascade step {done}/{K}", file=sys.stderr, flush=True)
+        if rc != 0:
+            # a buffer is full: stop and report the growth up to this step
+            stopped = {"step": done, "status": int(rc)}
+            break
+    rc, _ = run.ws.status(raise_on_error=False)
+    t = run.tally.reduce()
+    lep = t["N_mc"] + t["N_sokolov"] + t["N_nan"]
+    ph = t["N_phstep"]
+    es = 4
+    rec_bytes = 8 * es + 20
+    lep_bytes = lep * (13 * es + 16) + t["N_emit"] * 16 + (t["N_push"] + t["N_rec"]) * rec_bytes
+    ph_bytes = ph * (9 * es + 16) + t["N_pair"] * (7 * es + 8 + 2 * rec_bytes)
+    push_ms = kms.get("push_e", 0.0) + kms.get("push_p", 0.0)
+    pair_ms = kms.get("pair", 0.0)
+    total_bytes = lep_bytes + ph_bytes
+    kern_ms = push_ms + pair_ms
+    achieved = total_bytes / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else 0.0
+    return {
+        "metric": "QED particle-steps/s", "value": (lep + ph) / wall, "unit": "particle-steps/s", "n_gpus": 1,
+        "steps": done, "warmup": 0, "ms_per_step": wall * 1e3 / done, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"{n0} e- gamma0 1e4 (1% spread) vs a0=1000 10-period plane wave, {K} steps, "
+                               "FP32 form, photons with chi_gamma>0.2 pushed + pairs, compaction every step"},
+        "roofline": {"bound": "hbm", "kernel": "qed_push_emit + qed_pair_create", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "detail": {"growth": growth, "stopped_at_capacity": stopped, "kernel_ms": kms, "launches": nl,
+                   "status": int(rc), "tally": t},
+    }
+
+
+class _Offset:
+    """A sim.Run whose step numbers start at `start` (for a run timed in chunks)."""
+
+    def __init__(self, run, start):
+        self.run, self.start = run, start
+
+    def step(self, n, timed=None):
+        self.run.step(self.start + n, timed=timed)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -222,6 +397,15 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    if args.workload in ("plane", "cascade", "batched"):
+        if args.workload == "plane":
+            out = bench_plane(args)
+        elif args.workload == "cascade":
+            out = bench_cascade(args)
+        else:
+            out = batched_comparison(args.steps or 1000)
+        print(json.dumps(out), flush=True)
+        return
     if args.workload == "yee":
         wl = W.yee_beam(n=args.electrons or 10_000_000)
         caps = dict(photon_capacity=42 * len(wl.electrons["x"]), record_capacity=6 * len(wl.electrons["x"]),

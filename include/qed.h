@@ -340,6 +340,24 @@ void qed_sorter_free(qed_sorter *s);
 qed_status qed_sort_by_cell(qed_sorter *s, qed_workspace *ws, qed_species *src, qed_species *dst,
                             const qed_field *grid, void *stream);
 
+/* ------------------------------------------------------------------------ *
+ * Log-binned energy spectrum of a species (the photon and lepton spectra the
+ * paper's diagnostics compare, Sec. 4).  The energy of entry i is
+ * e = |u| for photons (photons != 0: |k| = gamma_gamma) or e = sqrt(1+|u|^2)
+ * (the Lorentz factor) for leptons, taken in FP64 for either precision.  Its
+ * bin is b = 1 + floor(n_bins * ln(e/e_min) / ln(e_max/e_min)) for
+ * e_min <= e < e_max, 0 below e_min (and for e = 0 or non-finite e), and
+ * n_bins + 1 at or above e_max.  Entries [0, *d_count) are counted; decayed
+ * photons (tau = +-INFINITY) are skipped.  The call ADDS to
+ * count[n_bins + 2] [device] (entries per bin) and wsum[n_bins + 2]
+ * [device] (the sum over the bin of round(w * weight_scale), in integers so
+ * that the sums do not depend on the order of the additions; weights that
+ * are multiples of 1/weight_scale are summed exactly).  1 <= n_bins <= 1024,
+ * 0 < e_min < e_max, weight_scale > 0; QED_ERR_ARG otherwise.
+ * ------------------------------------------------------------------------ */
+qed_status qed_spectrum(const qed_species *s, int32_t photons, double e_min, double e_max, int32_t n_bins,
+                        double weight_scale, int64_t *count, int64_t *wsum, void *stream);
+
 /* Advance a device step counter by one (for graph-captured step sequences). */
 qed_status qed_step_advance(int64_t *d_step, void *stream);
 

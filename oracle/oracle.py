@@ -449,3 +449,28 @@ def sort_by_cell(s: dict, shape, spacing, origin):
     st = _species_struct(s)
     lib().or_sort_by_cell(C.byref(st), *[int(v) for v in shape], *[float(v) for v in spacing],
                           *[float(v) for v in origin])
+
+
+def spectrum(s: dict, photons: bool, e_min: float, e_max: float, n_bins: int, weight_scale: float):
+    """Log-binned energy spectrum, by its definition.  e = |u| for photons
+    (|k| = gamma_gamma) or sqrt(1 + |u|^2) for leptons; bin 0 below e_min
+    (and for e = 0 or non-finite e), 1 + floor(n ln(e/e_min)/ln(e_max/e_min))
+    in range, n + 1 at or above e_max; decayed photons (tau = +-inf) are
+    skipped.  Returns (counts, weight sums in units of 1/weight_scale)."""
+    v = view(s)
+    u2 = v["ux"] ** 2 + v["uy"] ** 2 + v["uz"] ** 2
+    e = np.sqrt(u2) if photons else np.sqrt(1.0 + u2)
+    keep = ~np.isinf(v["tau"]) if photons else np.ones(len(e), bool)
+    e, w = e[keep], v["w"][keep]
+    b = np.zeros(len(e), np.int64)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        hi = e >= e_max
+        mid = (e >= e_min) & ~hi
+        f = np.floor((np.log(e[mid]) - np.log(e_min)) * (n_bins / np.log(e_max / e_min)))
+    b[mid] = 1 + np.clip(f, 0, n_bins - 1).astype(np.int64)
+    b[hi] = n_bins + 1
+    counts = np.bincount(b, minlength=n_bins + 2).astype(np.int64)
+    wsum = np.bincount(b, weights=None, minlength=n_bins + 2).astype(np.int64) * 0
+    np.add.at(wsum, b, np.rint(w * weight_scale).astype(np.int64))
+    return counts, wsum
+

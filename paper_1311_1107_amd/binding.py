@@ -115,6 +115,8 @@ _SIGS = {
                               _P(qed_species), _P(qed_step), _P(qed_schedule), C.c_int32, C.c_int32,
                               C.c_char_p, _P(qed_schedule), _dp, _vp], C.c_int32),
     "qed_step_advance": ([_vp, _vp], C.c_int32),
+    "qed_spectrum": ([_P(qed_species), C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_double, _vp, _vp, _vp],
+                     C.c_int32),
     "qed_sorter_create": ([C.c_int64, _P(_vp)], C.c_int32),
     "qed_sorter_free": ([_vp], None),
     "qed_sort_by_cell": ([_vp, _vp, _P(qed_species), _P(qed_species), _P(qed_field), _vp], C.c_int32),
@@ -288,6 +290,11 @@ def qed_sorter_free(handle):
 
 def qed_sort_by_cell(sorter, ws, src, dst, grid_field, stream=None):
     _check(lib().qed_sort_by_cell(sorter, ws, C.byref(src), C.byref(dst), C.byref(grid_field), _stream(stream)))
+
+
+def qed_spectrum(species, photons, e_min, e_max, n_bins, weight_scale, count_ptr, wsum_ptr, stream=None):
+    _check(lib().qed_spectrum(C.byref(species), 1 if photons else 0, float(e_min), float(e_max), int(n_bins),
+                              float(weight_scale), C.c_void_p(count_ptr), C.c_void_p(wsum_ptr), _stream(stream)))
 
 
 def qed_step_advance(d_step_ptr, stream=None):

@@ -409,6 +409,31 @@ qed_status qed_yee_fill_separable(float *grid, int64_t nx, int64_t ny, int64_t n
     return QED_OK;
 }
 
+qed_status qed_spectrum(const qed_species *s, int32_t photons, double e_min, double e_max, int32_t n_bins,
+                        double weight_scale, int64_t *count, int64_t *wsum, void *stream) {
+    if (!s || !count || !wsum) return fail(QED_ERR_ARG, "qed_spectrum: null argument");
+    if (n_bins < 1 || n_bins > 1024) return fail(QED_ERR_ARG, "qed_spectrum: n_bins must be 1..1024");
+    if (!(e_min > 0.0) || !(e_max > e_min) || !std::isfinite(e_max))
+        return fail(QED_ERR_ARG, "qed_spectrum: need 0 < e_min < e_max");
+    if (!(weight_scale > 0.0) || !std::isfinite(weight_scale)) return fail(QED_ERR_ARG, "qed_spectrum: weight_scale must be > 0");
+    qed::SpectrumArgs a;
+    std::memset(&a, 0, sizeof a);
+    qed_status st = species_dev(s, false, "qed_spectrum", a.s);
+    if (st) return st;
+    a.photons = photons ? 1 : 0;
+    a.n_bins = n_bins;
+    a.e_min = e_min;
+    a.e_max = e_max;
+    a.ln_emin = std::log(e_min);
+    a.inv_dln = (double)n_bins / std::log(e_max / e_min);
+    a.wscale = weight_scale;
+    a.count = (unsigned long long *)count;
+    a.wsum = (unsigned long long *)wsum;
+    const int nb = (int)std::min<int64_t>(2048, std::max<int64_t>(1, (s->capacity + 255) / 256));
+    HIP_TRY(qed::launch_spectrum(a, s->prec, nb, (hipStream_t)stream));
+    return QED_OK;
+}
+
 qed_status qed_step_advance(int64_t *d_step, void *stream) {
     if (!d_step) return fail(QED_ERR_ARG, "qed_step_advance: null counter");
     HIP_TRY(qed::launch_step_advance(d_step, (hipStream_t)stream));

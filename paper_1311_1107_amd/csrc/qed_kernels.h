@@ -138,4 +138,12 @@ hipError_t launch_yee_fill(float *grid, int64_t nx, int64_t ny, int64_t nz, doub
                            const double *tperp, const double *tpar, int n_blocks, hipStream_t s);
 hipError_t launch_step_advance(int64_t *d_step, hipStream_t s);
 
+struct SpectrumArgs {
+    SpeciesDev s;
+    int photons, n_bins;
+    double ln_emin, inv_dln, e_min, e_max, wscale;
+    unsigned long long *count, *wsum;
+};
+hipError_t launch_spectrum(const SpectrumArgs &a, int prec, int n_blocks, hipStream_t s);
+
 }  // namespace qed

@@ -958,6 +958,54 @@ hipError_t launch_yee_fill(float *grid, int64_t nx, int64_t ny, int64_t nz, doub
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------------
+// Log-binned spectrum: per-block LDS histograms of counts and of integer
+// (fixed-point) weights, added to the global bins once per block.  Integer
+// additions commute, so the result does not depend on the schedule.
+// ------------------------------------------------------------------------
+constexpr int kMaxSpecBins = 1024 + 2;
+
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_spectrum(SpectrumArgs a) {
+    __shared__ unsigned long long s_c[kMaxSpecBins], s_w[kMaxSpecBins];
+    const int nb = a.n_bins + 2;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) { s_c[b] = 0ull; s_w[b] = 0ull; }
+    __syncthreads();
+    const int64_t n = *a.s.count < a.s.cap ? *a.s.count : a.s.cap;
+    const R *UX = (const R *)a.s.ux, *UY = (const R *)a.s.uy, *UZ = (const R *)a.s.uz, *W = (const R *)a.s.w;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double tau = a.s.tau[i];
+        if (a.photons && (tau == HUGE_VAL || tau == -HUGE_VAL)) continue;
+        const double ux = (double)UX[i], uy = (double)UY[i], uz = (double)UZ[i];
+        const double u2 = ux * ux + uy * uy + uz * uz;
+        const double e = a.photons ? sqrt(u2) : sqrt(1.0 + u2);
+        int b = 0;
+        if (e >= a.e_max) {
+            b = a.n_bins + 1;
+        } else if (e >= a.e_min) {
+            const double f = floor((log(e) - a.ln_emin) * a.inv_dln);
+            b = 1 + (f < 0.0 ? 0 : (f >= (double)a.n_bins ? a.n_bins - 1 : (int)f));
+        }
+        const long long wf = llrint((double)W[i] * a.wscale);
+        atomicAdd(&s_c[b], 1ull);
+        atomicAdd(&s_w[b], (unsigned long long)wf);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        if (s_c[b]) {
+            atomicAdd(a.count + b, s_c[b]);
+            atomicAdd(a.wsum + b, s_w[b]);
+        }
+    }
+}
+
+hipError_t launch_spectrum(const SpectrumArgs &a, int prec, int n_blocks, hipStream_t s) {
+    if (prec == 0) hipLaunchKernelGGL((k_spectrum<double>), dim3(n_blocks), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_spectrum<float>), dim3(n_blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_step_advance(int64_t *d_step, hipStream_t s) {
     hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(64), 0, s, d_step);
     return hipGetLastError();

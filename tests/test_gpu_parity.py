@@ -480,3 +480,42 @@ def test_autotune_leaves_state_and_caches(gpu_oracle_tables, tmp_path):
     for _ in range(3):
         bun.step_batched()
     _same(_snapshot(bun), _snapshot(ref))
+
+
+# ------------------------------------------------------------- spectrum ----
+@pytest.mark.parametrize("prec,photons,n", [(B.QED_F64, True, 70_001), (B.QED_F64, False, 70_001),
+                                            (B.QED_F32, True, 5_000), (B.QED_F64, True, 0)])
+def test_spectrum_matches_oracle(prec, photons, n):
+    """qed_spectrum against the oracle's binning of the same (device-precision)
+    values: counts and fixed-point weight sums bit-exact; a second call adds."""
+    _need_gpu()
+    print(f"case: spectrum prec={prec} photons={photons} n={n}", flush=True)
+    r = np.random.default_rng(17 + n)
+    mag = 10.0 ** r.uniform(-1, 5, n)
+    d = r.normal(size=(n, 3))
+    d /= np.maximum(np.linalg.norm(d, axis=1), 1e-300)[:, None]
+    ft = np.float64 if prec == B.QED_F64 else np.float32
+    p = {"x": np.zeros(n), "y": np.zeros(n), "z": np.zeros(n),
+         "ux": (mag * d[:, 0]).astype(ft).astype(np.float64), "uy": (mag * d[:, 1]).astype(ft).astype(np.float64),
+         "uz": (mag * d[:, 2]).astype(ft).astype(np.float64), "w": r.choice([0.5, 1.0, 2.25], n),
+         "tau": r.exponential(size=n)}
+    if n:
+        p["tau"][r.random(n) < 0.1] = np.inf
+        p["ux"][:2] = 0.0
+        p["uy"][:2] = 0.0
+        p["uz"][:2] = 0.0
+    sp = D.Species(max(n, 1), prec)
+    sp.upload(p)
+    nb = 97
+    cnt = torch.zeros(nb + 2, dtype=torch.int64, device="cuda")
+    ws = torch.zeros(nb + 2, dtype=torch.int64, device="cuda")
+    want_c, want_w = O.spectrum(O.species_from(p), photons, 2.0, 1e4, nb, 8.0)
+    for rep in (1, 2):
+        B.qed_spectrum(sp.struct(), photons, 2.0, 1e4, nb, 8.0, cnt.data_ptr(), ws.data_ptr())
+        torch.cuda.synchronize()
+        assert np.array_equal(cnt.cpu().numpy(), rep * want_c)
+        assert np.array_equal(ws.cpu().numpy(), rep * want_w)
+    with pytest.raises(B.QedError):
+        B.qed_spectrum(sp.struct(), photons, 0.0, 1e4, nb, 8.0, cnt.data_ptr(), ws.data_ptr())
+    with pytest.raises(B.QedError):
+        B.qed_spectrum(sp.struct(), photons, 2.0, 1e4, 2000, 8.0, cnt.data_ptr(), ws.data_ptr())
