@@ -13,16 +13,13 @@
 // the single-pass ticketed look-back.
 #include "qed_kernels.h"
 
+#include <climits>
+
 namespace qed {
 
 // ------------------------------------------------------------------------
 // fields
 // ------------------------------------------------------------------------
-__constant__ double kYeeStag[6][3] = {
-    {0.5, 0.0, 0.0}, {0.0, 0.5, 0.0}, {0.0, 0.0, 0.5},
-    {0.0, 0.5, 0.5}, {0.5, 0.0, 0.5}, {0.5, 0.5, 0.0},
-};
-
 // Plane wave from a_y = a0 sin^2(pi phi/Phi) sin(phi), phi = t - x:
 // E_y = B_z = -(da_y/dphi).
 template <typename R>
@@ -52,18 +49,77 @@ __device__ __forceinline__ float plane_wave_da<float>(double t, float x, double 
     return (float)a0 * ((float)(kPi / Phi) * (2.0f * se * ce) * sp + se * se * cp);
 }
 
+// Quadratic (TSC) weights for offset d from the nearest node.
+template <typename R>
+__device__ __forceinline__ void tsc_w(R d, R w[3]) {
+    w[0] = R(0.5) * (R(0.5) - d) * (R(0.5) - d);
+    w[1] = fma(-d, d, R(0.75));
+    w[2] = R(0.5) * (R(0.5) + d) * (R(0.5) + d);
+}
+
 // Quadratic (TSC) weights about the nearest node.
 template <typename R>
 __device__ __forceinline__ int64_t tsc(R g, R w[3]) {
     // far outside the grid (or NaN): a node index that every bounds test rejects
     if (!(g > R(-1.0e6) && g < R(1.0e6))) g = R(-1.0e6);
     const R f = floor(g + R(0.5));
-    const R d = g - f;
-    w[0] = R(0.5) * (R(0.5) - d) * (R(0.5) - d);
-    w[1] = R(0.75) - d * d;
-    w[2] = R(0.5) * (R(0.5) + d) * (R(0.5) + d);
+    tsc_w<R>(g - f, w);
     return (int64_t)f;
 }
+
+// Sum of w_x[a] w_y[b] w_z[c] v[a][b][c] in one fixed order with explicit
+// FMAs, so that the direct and the LDS-staged gathers give the same bits for
+// the same node values.
+template <typename R>
+__device__ __forceinline__ R tsc_sum(const R wx[3], const R wy[3], const R wz[3], const float v[27]) {
+    R acc = R(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const float *r = v + 9 * a + 3 * b;
+            R row = wz[0] * (R)r[0];
+            row = fma(wz[1], (R)r[1], row);
+            row = fma(wz[2], (R)r[2], row);
+            acc = fma(wx[a] * wy[b], row, acc);
+        }
+    return acc;
+}
+
+// Stencils of one particle: along each axis the first node and the offset
+// from the nearest node, for components on integer nodes ([0]) and on
+// half-integer nodes ([1]); the weights are formed where they are used.
+template <typename R>
+struct Stencil {
+    int s[3][2];
+    R d[3][2];
+};
+
+template <typename R>
+__device__ __forceinline__ void make_stencil(const FieldDev &f, R x, R y, R z, Stencil<R> &st) {
+    const R g[3] = {(x - (R)f.x0) * (R)f.inv_dx, (y - (R)f.y0) * (R)f.inv_dy, (z - (R)f.z0) * (R)f.inv_dz};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            R gg = h ? g[d] - R(0.5) : g[d];
+            // far outside the grid (or NaN): a node index that every bounds test rejects
+            if (!(gg > R(-1.0e6) && gg < R(1.0e6))) gg = R(-1.0e6);
+            const R fl = floor(gg + R(0.5));
+            st.d[d][h] = gg - fl;
+            st.s[d][h] = (int)fl - 1;
+        }
+    }
+}
+
+
+// Yee staggering of Ex Ey Ez Bx By Bz along x, y, z: 1 = half a cell off.
+constexpr int kHalf[6][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {0, 1, 1}, {1, 0, 1}, {1, 1, 0}};
+
+__constant__ double kYeeStag[6][3] = {
+    {0.5, 0.0, 0.0}, {0.0, 0.5, 0.0}, {0.0, 0.0, 0.5},
+    {0.0, 0.5, 0.5}, {0.5, 0.0, 0.5}, {0.5, 0.5, 0.0},
+};
 
 template <typename R>
 __device__ __forceinline__ void yee_gather(const FieldDev &f, R x, R y, R z, R E[3], R B[3]) {
@@ -85,26 +141,134 @@ __device__ __forceinline__ void yee_gather(const FieldDev &f, R x, R y, R z, R E
 #pragma unroll
                 for (int b = 0; b < 3; ++b) {
                     const float *r = p + (a * ny + b) * nz;
-                    const R wab = wx[a] * wy[b];
-                    acc += wab * (wz[0] * (R)r[0] + wz[1] * (R)r[1] + wz[2] * (R)r[2]);
+                    R row = wz[0] * (R)r[0];
+                    row = fma(wz[1], (R)r[1], row);
+                    row = fma(wz[2], (R)r[2], row);
+                    acc = fma(wx[a] * wy[b], row, acc);
                 }
         } else {
-            for (int a = 0; a < 3; ++a) {
-                const int64_t i = i0 + a;
-                if (i < 0 || i >= nx) continue;
+            // nodes outside the grid count as zero, in the same order of operations
+            for (int a = 0; a < 3; ++a)
                 for (int b = 0; b < 3; ++b) {
-                    const int64_t j = j0 + b;
-                    if (j < 0 || j >= ny) continue;
+                    const int64_t i = i0 + a, j = j0 + b;
+                    const bool row_in = i >= 0 && i < nx && j >= 0 && j < ny;
+                    float r[3];
+#pragma unroll
                     for (int cc = 0; cc < 3; ++cc) {
                         const int64_t k = k0 + cc;
-                        if (k < 0 || k >= nz) continue;
-                        acc += (wx[a] * wy[b]) * wz[cc] * (R)g[(i * ny + j) * nz + k];
+                        r[cc] = row_in && k >= 0 && k < nz ? g[(i * ny + j) * nz + k] : 0.0f;
                     }
+                    R row = wz[0] * (R)r[0];
+                    row = fma(wz[1], (R)r[1], row);
+                    row = fma(wz[2], (R)r[2], row);
+                    acc = fma(wx[a] * wy[b], row, acc);
                 }
-            }
         }
         out[c] = acc;
     }
+    E[0] = out[0]; E[1] = out[1]; E[2] = out[2];
+    B[0] = out[3]; B[1] = out[4]; B[2] = out[5];
+}
+
+// ------------------------------------------------------------------------
+// Wave-cooperative gather through LDS.  A direct gather moves 162 dwords per
+// lane through the texture data path, which bounds a cell-ordered photon
+// step.  Here a wave whose stencils all fall in a box of kWB nodes (6 along
+// x, where photons drift, and 5 along y and z) loads the six components of
+// that box into its own LDS region once (about 14 dwords per lane) and every
+// lane reads its 3x3x3 stencils there at fixed strides.  Other waves gather
+// directly.  Both paths sum with tsc_sum over the same node values, so the
+// path taken never changes a result.  No block barrier: each wave owns its
+// region.
+// ------------------------------------------------------------------------
+constexpr int kWBX = 6, kWBY = 5, kWBZ = 5;
+constexpr int kWBVol = kWBX * kWBY * kWBZ;
+constexpr int kWBFloats = 6 * kWBVol;
+
+__device__ __forceinline__ int wave_min_i32(int v) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        const int o = __shfl_xor(v, d, kWave);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+// Called by all lanes of the wave; act marks lanes that need the field.
+template <typename R>
+__device__ __forceinline__ void yee_gather_wave(const FieldDev &f, bool act, R x, R y, R z, R E[3], R B[3],
+                                                float *box) {
+    const int64_t nx = f.nx, ny = f.ny, nz = f.nz, ncell = nx * ny * nz;
+    Stencil<R> st;
+    make_stencil<R>(f, x, y, z, st);
+    const int64_t nn[3] = {nx, ny, nz};
+    int lo[3], hi[3];
+    bool near = act;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int s0 = st.s[d][0], s1 = st.s[d][1];
+        lo[d] = s0 < s1 ? s0 : s1;
+        hi[d] = (s0 > s1 ? s0 : s1) + 2;
+        near = near && hi[d] >= 0 && (int64_t)lo[d] < nn[d];
+    }
+    const uint64_t m_near = __ballot(near);
+    if (m_near == 0ull) {                                   // the whole wave sees a zero field
+        E[0] = E[1] = E[2] = B[0] = B[1] = B[2] = R(0);
+        return;
+    }
+    int o[3], ext[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        o[d] = wave_min_i32(near ? lo[d] : INT_MAX);
+        ext[d] = -wave_min_i32(near ? -hi[d] : INT_MAX) - o[d] + 1;    // nodes spanned along d
+    }
+    if (ext[0] > kWBX || ext[1] > kWBY || ext[2] > kWBZ) {
+        if (near) yee_gather<R>(f, x, y, z, E, B);
+        else E[0] = E[1] = E[2] = B[0] = B[1] = B[2] = R(0);
+        return;
+    }
+    // stage the box: node e = (p kWBY + q) kWBZ + r
+#pragma unroll
+    for (int u = 0; u < (kWBVol + kWave - 1) / kWave; ++u) {
+        const int e = lane_id() + u * kWave;
+        const int p = e / (kWBY * kWBZ), q = (e / kWBZ) % kWBY, r = e % kWBZ;
+        // only the nodes the wave's stencils span are loaded (the rest are never read)
+        if (e < kWBVol && p < ext[0] && q < ext[1] && r < ext[2]) {
+            const int64_t i = o[0] + p, j = o[1] + q, k = o[2] + r;
+            const bool in = i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz;
+            const int64_t off = in ? (i * ny + j) * nz + k : 0;
+            float v[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) v[c] = in ? f.grid[c * ncell + off] : 0.0f;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) box[c * kWBVol + e] = v[c];
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    R out[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const int hx = kHalf[c][0], hy = kHalf[c][1], hz = kHalf[c][2];
+        const int base = near ? ((st.s[0][hx] - o[0]) * kWBY + (st.s[1][hy] - o[1])) * kWBZ + (st.s[2][hz] - o[2]) : 0;
+        const float *p = box + c * kWBVol + base;
+        float v[27];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) v[9 * a + 3 * b + cc] = p[(a * kWBY + b) * kWBZ + cc];
+        R wx[3], wy[3], wz[3];
+        tsc_w<R>(st.d[0][hx], wx);
+        tsc_w<R>(st.d[1][hy], wy);
+        tsc_w<R>(st.d[2][hz], wz);
+        out[c] = near ? tsc_sum<R>(wx, wy, wz, v) : R(0);
+    }
+    // the box is rewritten only after every lane has read it
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
     E[0] = out[0]; E[1] = out[1]; E[2] = out[2];
     B[0] = out[3]; B[1] = out[4]; B[2] = out[5];
 }
@@ -629,6 +793,7 @@ template <typename R, int FK>
 __global__ void __launch_bounds__(256)
 k_pair_create(PairArgs a) {
     __shared__ R s_lp[kMaxChiNodes];
+    __shared__ float s_box[FK == FIELD_YEE ? kMaxWaves * kWBFloats : 1];
     __shared__ uint32_t s_wave[3 * kMaxWaves];
     __shared__ double s_red[kNEnergy * kMaxWaves];
     __shared__ int64_t s_cnt[N_COUNT_USED];
@@ -660,35 +825,41 @@ k_pair_create(PairArgs a) {
 #pragma unroll
         for (int k = 0; k < kNEnergy; ++k) en[k] = 0.0;
         bool event = false;
+        double tau = HUGE_VAL;
+        R x = R(0), y = R(0), z = R(0), kx = R(0), ky = R(0), kz = R(0);
         if (i < n) {
-            double tau = a.ph.tau[i];
+            tau = a.ph.tau[i];
             if (tau != HUGE_VAL) {
-                const R x = X[i], y = Y[i], z = Z[i];
-                const R kx = KX[i], ky = KY[i], kz = KZ[i];
-                R E[3], B[3];
-                field_at<R, FK>(a.f, t, x, y, z, a.f.a0, a.f.Phi, E, B);
-                const R kk = Math<R>::sqrt_(kx * kx + ky * ky + kz * kz);
-                const R chig = chi_of<R>(es_inv, kk, kx, ky, kz, E, B);
-                cnt[C_PHSTEP]++;
-                R Wp = R(0);
-                if (kk > R(2) && chig >= chi_min) {
-                    bool above = false;
-                    const R l = lerp_rate<R>(s_lp, tb.p_n_chi, lnchi0, inv_d, Math<R>::log_(chig), above);
-                    Wp = Ah * Math<R>::exp_(l - R(8) / (R(3) * chig)) / kk;
-                    if (above) cnt[C_RANGE]++;
-                }
-                tau -= (double)Wp * dt;
-                if (Wp > R(0) && tau <= 0.0) {
-                    event = true;
-                    cnt[C_PAIR]++;
-                    en[E_PAIR] = (double)((const R *)a.ph.w)[i] * (double)kk;
-                    a.ph.tau[i] = -HUGE_VAL;
-                } else {
-                    X[i] = x + dtr * (kx / kk);
-                    Y[i] = y + dtr * (ky / kk);
-                    Z[i] = z + dtr * (kz / kk);
-                    a.ph.tau[i] = tau;
-                }
+                x = X[i]; y = Y[i]; z = Z[i];
+                kx = KX[i]; ky = KY[i]; kz = KZ[i];
+            }
+        }
+        const bool live = i < n && tau != HUGE_VAL;
+        R E[3], B[3];
+        if constexpr (FK == FIELD_YEE) yee_gather_wave<R>(a.f, live, x, y, z, E, B, s_box + (tid / kWave) * kWBFloats);
+        if (live) {
+            if constexpr (FK != FIELD_YEE) field_at<R, FK>(a.f, t, x, y, z, a.f.a0, a.f.Phi, E, B);
+            const R kk = Math<R>::sqrt_(kx * kx + ky * ky + kz * kz);
+            const R chig = chi_of<R>(es_inv, kk, kx, ky, kz, E, B);
+            cnt[C_PHSTEP]++;
+            R Wp = R(0);
+            if (kk > R(2) && chig >= chi_min) {
+                bool above = false;
+                const R l = lerp_rate<R>(s_lp, tb.p_n_chi, lnchi0, inv_d, Math<R>::log_(chig), above);
+                Wp = Ah * Math<R>::exp_(l - R(8) / (R(3) * chig)) / kk;
+                if (above) cnt[C_RANGE]++;
+            }
+            tau -= (double)Wp * dt;
+            if (Wp > R(0) && tau <= 0.0) {
+                event = true;
+                cnt[C_PAIR]++;
+                en[E_PAIR] = (double)((const R *)a.ph.w)[i] * (double)kk;
+                a.ph.tau[i] = -HUGE_VAL;
+            } else {
+                X[i] = x + dtr * (kx / kk);
+                Y[i] = y + dtr * (ky / kk);
+                Z[i] = z + dtr * (kz / kk);
+                a.ph.tau[i] = tau;
             }
         }
         uint32_t rank, tot, d0, d1;
