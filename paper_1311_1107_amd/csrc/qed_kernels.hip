@@ -377,6 +377,7 @@ template <typename R, int FK>
 __global__ void __launch_bounds__(256)
 k_push_emit(PushArgs a) {
     __shared__ R s_lh[kMaxChiNodes];
+    __shared__ float s_box[FK == FIELD_YEE && sizeof(R) == 4 ? kMaxWaves * kWBFloats : 1];
     __shared__ R s_lg[kMaxChiNodes];
     __shared__ uint32_t s_wave[3 * kMaxWaves];
     __shared__ int64_t s_b0;
@@ -435,6 +436,13 @@ k_push_emit(PushArgs a) {
         R x = R(0), y = R(0), z = R(0);
         R uhx = R(0), uhy = R(0), uhz = R(0);       // photon direction
         R wgt = R(0);
+        // The wave gather pays off for the FP32 lepton step; in FP64 its registers
+        // would halve the occupancy of this kernel, so the FP64 step gathers directly.
+        constexpr bool kWaveGather = FK == FIELD_YEE && sizeof(R) == 4;
+        R E[3], B[3];
+        if constexpr (kWaveGather)
+            yee_gather_wave<R>(a.f, live, live ? X[i] : R(0), live ? Y[i] : R(0), live ? Z[i] : R(0), E, B,
+                               s_box + (tid / kWave) * kWBFloats);
         if (live) {
             x = X[i]; y = Y[i]; z = Z[i];
             const R ux = UX[i], uy = UY[i], uz = UZ[i];
@@ -445,8 +453,7 @@ k_push_emit(PushArgs a) {
                 a0 = a.f.a0s[b];
                 Phi = 2.0 * kPi * a.f.nper[b];
             }
-            R E[3], B[3];
-            field_at<R, FK>(a.f, t, x, y, z, a0, Phi, E, B);
+            if constexpr (!kWaveGather) field_at<R, FK>(a.f, t, x, y, z, a0, Phi, E, B);
             const R g_old = Math<R>::sqrt_(R(1) + (ux * ux + uy * uy + uz * uz));
 
             // Boris: half electric kick, magnetic rotation, half kick

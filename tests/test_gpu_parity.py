@@ -519,3 +519,43 @@ def test_spectrum_matches_oracle(prec, photons, n):
         B.qed_spectrum(sp.struct(), photons, 0.0, 1e4, nb, 8.0, cnt.data_ptr(), ws.data_ptr())
     with pytest.raises(B.QedError):
         B.qed_spectrum(sp.struct(), photons, 2.0, 1e4, 2000, 8.0, cnt.data_ptr(), ws.data_ptr())
+
+
+def test_fp32_yee_one_step_within_1e5(gpu_oracle_tables, bound_tables):
+    """FP32 form on the Yee grid (wave-cooperative gather in the lepton and
+    photon steps): one step from identical state, momenta within 1e-5."""
+    wl = _yee_small(seed=13, n=2000, steps=260)
+    k = 120
+    print(f"case: FP32 Yee one step at {k}", flush=True)
+    caps = dict(photon_capacity=160 * 2000, record_capacity=8 * 2000, pair_capacity=12 * 2000)
+    mid = oracle_run(wl, bound_tables, k, **caps)
+    assert mid["tally"]["N_emit"] > 0
+    state = {kk: v.copy() for kk, v in mid["electrons"].items()}
+    n = len(state["x"])
+    wl2 = W.Workload(wl.name, state, wl.field, wl.steps, wl.dt, wl.seed, push_photons=True,
+                     chi_photon_push_min=wl.chi_photon_push_min)
+    o = O.species_from(state)
+    o["tau"][:n] = state["tau"]
+    o["n_ev"][:n] = state["n_ev"]
+    f = wl.field
+    field = O.make_field(O.FIELD_YEE_SEPARABLE, a0=f.a0, shape=f.shape, spacing=f.spacing, origin=f.origin,
+                         tperp=f.tperp, tpar=f.tpar[k])
+    st = O.make_step(k * wl.dt, wl.dt, wl.seed, chi_photon_push_min=wl.chi_photon_push_min)
+    ph = O.new_species(16 * n)
+    rec = O.new_species(16 * n)
+    O.push_emit(bound_tables, W.LAMBDA_M, -1.0, o, field, ph, rec, st, [10**9], O.Tally())
+    want = O.view(o)
+    run = S.Run(wl2, prec=B.QED_F32, tables=gpu_oracle_tables, photon_capacity=16 * n, record_capacity=16 * n,
+                pair_capacity=n)
+    run.el.a["tau"][:n] = torch.from_numpy(state["tau"]).cuda()
+    run.el.a["n_ev"][:n] = torch.from_numpy(state["n_ev"].view(np.int32)).cuda()
+    run.step(k)
+    got = run.result()["electrons"]
+    assert len(got["x"]) == n
+    same_events = got["n_ev"] == want["n_ev"]
+    assert same_events.mean() > 0.99
+    u_g = np.stack([got["ux"], got["uy"], got["uz"]], 1).astype(np.float64)[same_events]
+    u_w = np.stack([want["ux"], want["uy"], want["uz"]], 1)[same_events]
+    rel = np.linalg.norm(u_g - u_w, axis=1) / np.maximum(np.linalg.norm(u_w, axis=1), 1.0)
+    print(f"FP32 Yee one-step momentum rel err: max {rel.max():.2e} median {np.median(rel):.2e}", flush=True)
+    assert rel.max() <= 1e-5
