@@ -22,7 +22,7 @@ import torch
 
 from . import binding as B
 from . import device as D
-from .workloads import LAMBDA_M, PlaneWave, Workload, YeePulse
+from .workloads import LAMBDA_M, PlaneWave, Uniform, Workload, YeePulse
 
 EMIT_SPEC = dict(chi_min=1e-3, chi_max=1e2, n_chi=128, n_q=128, logit_max=18.0)
 PAIR_SPEC = dict(chi_min=1e-2, chi_max=1e2, n_chi=128, n_q=128, logit_max=18.0)
@@ -67,6 +67,9 @@ class Run:
         f = wl.field
         if isinstance(f, PlaneWave):
             self.field = D.plane_wave(f.a0, f.n_periods)
+            self.grid = None
+        elif isinstance(f, Uniform):
+            self.field = D.uniform(f.E, f.B)
             self.grid = None
         elif isinstance(f, YeePulse):
             nx, ny, nz = f.shape

@@ -34,6 +34,13 @@ class PlaneWave:
 
 
 @dataclass
+class Uniform:
+    """Constant fields (normalised units)."""
+    E: tuple = (0.0, 0.0, 0.0)
+    B: tuple = (0.0, 0.0, 0.0)
+
+
+@dataclass
 class YeePulse:
     """Focused pulse on a Yee grid, value[c,i,j,k] = a0 * tperp[c,j,k] * tpar[step,c,i]."""
     shape: tuple
@@ -92,6 +99,17 @@ def cascade_beam(n=50_000_000, a0=1000.0, gamma0=1.0e4, steps=500, seed=5) -> Wo
     w = Workload("high-chi cascade", beam_in_box(n, gamma0, 0.01, rng), PlaneWave(a0), steps,
                  seed=seed, push_photons=True, chi_photon_push_min=0.2, record_photons=False)
     return w
+
+
+def constant_b(n=100_000, gamma0=3000.0, b_tesla=7.48e6, steps=600, seed=7) -> Workload:
+    """The validation case of Sec. 4: electrons of gamma0 = 3000 moving along x
+    in a uniform B along z of 7.48 MT (chi_e ~ 5 at the start); every photon
+    is pushed and may decay into a pair; 600 steps of T/100 (about 16 fs)."""
+    b_ref = 9.1093837015e-31 * OMEGA_R / 1.602176634e-19      # m omega_r / e [T]
+    p0 = math.sqrt(gamma0 * gamma0 - 1.0)
+    e = _electrons(np.zeros(n), np.zeros(n), np.zeros(n), np.full(n, p0), np.zeros(n), np.zeros(n))
+    return Workload("constant-B cascade", e, Uniform(B=(0.0, 0.0, b_tesla / b_ref)), steps, seed=seed,
+                    push_photons=True, chi_photon_push_min=0.0, record_photons=False)
 
 
 def bunches(n_bunches=64, seed=4, scale=1.0, lo=3.0, hi=6.0):

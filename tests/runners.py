@@ -6,7 +6,7 @@ from __future__ import annotations
 import numpy as np
 
 from oracle import oracle as O
-from paper_1311_1107_amd.workloads import LAMBDA_M, PlaneWave, YeePulse
+from paper_1311_1107_amd.workloads import LAMBDA_M, PlaneWave, Uniform, YeePulse
 
 
 def oracle_run(wl, tabs: O.BoundTables, steps: int, photon_capacity=None, record_capacity=None,
@@ -24,6 +24,8 @@ def oracle_run(wl, tabs: O.BoundTables, steps: int, photon_capacity=None, record
     f = wl.field
     if isinstance(f, PlaneWave):
         field = O.make_field(O.FIELD_PLANE_WAVE, a0=f.a0, n_periods=f.n_periods)
+    elif isinstance(f, Uniform):
+        field = O.make_field(O.FIELD_UNIFORM, E=f.E, B=f.B)
     for n in range(start, start + steps):
         if isinstance(f, YeePulse) and lazy_grid:
             field = O.make_field(O.FIELD_YEE_SEPARABLE, a0=f.a0, shape=f.shape, spacing=f.spacing,

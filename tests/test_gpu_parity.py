@@ -559,3 +559,51 @@ def test_fp32_yee_one_step_within_1e5(gpu_oracle_tables, bound_tables):
     rel = np.linalg.norm(u_g - u_w, axis=1) / np.maximum(np.linalg.norm(u_w, axis=1), 1.0)
     print(f"FP32 Yee one-step momentum rel err: max {rel.max():.2e} median {np.median(rel):.2e}", flush=True)
     assert rel.max() <= 1e-5
+
+
+# ------------------------------------------------ constant-B validation ----
+def test_constant_b_fp64_parity(gpu_oracle_tables, bound_tables):
+    """The validation case of Sec. 4 (gamma 3000 in 7.48 MT, pure Monte Carlo,
+    every photon pushed and tested for pairs) through the uniform-field path:
+    bit-exact counts and ids, momenta within 1e-12."""
+    wl = W.constant_b(n=700, steps=120)
+    print("case: constant B n=700 steps=120", flush=True)
+    caps = dict(photon_capacity=120 * 700, pair_capacity=8 * 700)
+    want = oracle_run(wl, bound_tables, wl.steps, rad_model=O.RAD_MC, **caps)
+    assert want["tally"]["N_pair"] > 100 and want["tally"]["N_overflow"] == 0
+    run = S.Run(wl, tables=gpu_oracle_tables, rad_model=B.QED_RAD_MC, compact_every=5, **caps)
+    run.run(wl.steps)
+    got = run.result()
+    for sp in ("electrons", "positrons", "photons"):
+        assert_species_match(got[sp], want[sp], what=sp)
+    for k, v in want["tally"].items():
+        if k.startswith("N_"):
+            assert got["tally"][k] == v, k
+    run.ws.status()
+
+
+def test_constant_b_follows_kinetic_equations(gpu_oracle_tables, bound_tables):
+    """The library's Monte Carlo ensemble (FP64, 2e4 electrons) against the
+    deterministic solution of the kinetic equations (Eqs. 9-10)."""
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from test_oracle_kinetic import check, kinetic_moments
+
+    from oracle import kinetic as K
+    n0, checkpoints = 20_000, (10, 25, 50, 100, 200, 300)
+    wl = W.constant_b(n=n0, steps=max(checkpoints))
+    print(f"case: constant B kinetic n={n0}", flush=True)
+    run = S.Run(wl, tables=gpu_oracle_tables, rad_model=B.QED_RAD_MC, photon_capacity=160 * n0,
+                pair_capacity=6 * n0, compact_every=8)
+    u = O.units()
+    Bh = wl.field.B[2]
+    mc = {}
+    for n in range(max(checkpoints)):
+        run.step(n)
+        if n + 1 in checkpoints:
+            torch.cuda.synchronize()
+            mc[n + 1] = {"electrons": K.mc_moments(run.el.download(), False, Bh, u["Es_hat"]),
+                         "positrons": K.mc_moments(run.po.download(), False, Bh, u["Es_hat"]),
+                         "photons": K.mc_moments(run.ph.download(), True, Bh, u["Es_hat"])}
+    run.ws.status()
+    kin = kinetic_moments(bound_tables, checkpoints)
+    check(mc, kin, n0, checkpoints)
