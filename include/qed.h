@@ -190,9 +190,22 @@ typedef struct {
     double gamma_photon_min;
     double chi_photon_push_min;
     int32_t no_recoil;        /* test switch: emit without recoil (frozen chi) */
-    int32_t reserved;
+    int32_t variants;         /* 0, or an OR of the QED_VAR_* model variants    */
     const int64_t *d_step;    /* [device] or NULL                               */
 } qed_step;
+
+/* Model variants (alternative readings of the paper; 0 = the default readings).
+ *  QED_VAR_SOKOLOV_G:      the Sokolov correction delta_v of Eq. 4 is computed
+ *                          with tau_0 g(chi_e) instead of the classical tau_0,
+ *                          the same quantum reduction Eq. 5 applies to P_rad.
+ *  QED_VAR_PAIR_MOMENTUM:  a pair splits the photon momentum exactly,
+ *                          u_pm = (chi_pm / chi_gamma) k, gamma_pm =
+ *                          sqrt(1 + |u_pm|^2) (Sec. 3 fixes only chi_+ =
+ *                          chi_gamma - chi_-); the default keeps the energy
+ *                          exact instead, gamma_pm = 1 + (gamma_gamma - 2)
+ *                          chi_pm / chi_gamma along k.
+ * Bits outside these are rejected (QED_ERR_ARG). */
+enum { QED_VAR_SOKOLOV_G = 1, QED_VAR_PAIR_MOMENTUM = 2 };
 
 /* ------------------------------------------------------------------------ *
  * Tallies: FP64 energies (m c^2 x weight), accumulated per tile slot so that

@@ -771,9 +771,12 @@ int or_push_emit(const or_tables *tab, const or_units *un, double q,
                              q * (E[1] + (v[2] * B[0] - v[0] * B[2])),
                              q * (E[2] + (v[0] * B[1] - v[1] * B[0])) };
             double vf = v[0] * fl[0] + v[1] * fl[1] + v[2] * fl[2];
-            double den = 1.0 + tau0 * vf;
-            for (int c = 0; c < 3; ++c) dv[c] = tau0 * (fl[c] - v[c] * vf) / den;
-            double P = (2.0 / 3.0) * A * chi * chi * or_lookup_g(tab, chi);
+            double gq = chi > 0.0 ? or_lookup_g(tab, chi) : 1.0;
+            /* alternative reading: delta_v with the quantum-reduced tau_0 g(chi) */
+            double tq = (st->variants & OR_VAR_SOKOLOV_G) ? tau0 * gq : tau0;
+            double den = 1.0 + tq * vf;
+            for (int c = 0; c < 3; ++c) dv[c] = tq * (fl[c] - v[c] * vf) / den;
+            double P = (2.0 / 3.0) * A * chi * chi * gq;
             double dvB[3] = { dv[1] * B[2] - dv[2] * B[1],
                               dv[2] * B[0] - dv[0] * B[2],
                               dv[0] * B[1] - dv[1] * B[0] };
@@ -910,9 +913,19 @@ int or_pair_create(const or_tables *tab, const or_units *un,
             double eta = or_sample_eta(tab, chig, or_u01(o[0]));
             double chim = eta * chig;
             double chip = chig - chim;
-            double gmn = 1.0 + (kk - 2.0) * (chim / chig);
-            double gpl = 1.0 + (kk - 2.0) * (chip / chig);
-            double pm = sqrt(gmn * gmn - 1.0), pp = sqrt(gpl * gpl - 1.0);
+            double gmn, gpl, pm, pp;
+            if (st->variants & OR_VAR_PAIR_MOMENTUM) {
+                /* alternative reading: the photon momentum is split exactly */
+                pm = (chim / chig) * kk;
+                pp = (chip / chig) * kk;
+                gmn = sqrt(1.0 + pm * pm);
+                gpl = sqrt(1.0 + pp * pp);
+            } else {
+                gmn = 1.0 + (kk - 2.0) * (chim / chig);
+                gpl = 1.0 + (kk - 2.0) * (chip / chig);
+                pm = sqrt(gmn * gmn - 1.0);
+                pp = sqrt(gpl * gpl - 1.0);
+            }
             double wgt = P->w[j];
             count[OR_C_PAIR]++;
             tally[OR_T_EPAIR] += wgt * kk;

@@ -143,7 +143,13 @@ typedef struct {
     double chi_photon_push_min; /* stored photons go to the pushed buffer above this chi */
     int32_t max_events;         /* emissions per particle and step            */
     int32_t no_recoil;          /* test switch: emit without recoil           */
+    int32_t variants;           /* alternative readings, OR of OR_VAR_*       */
 } or_step;
+
+/* Alternative readings: the Sokolov delta_v of Eq. 4 with tau_0 g(chi)
+ * instead of tau_0; a pair that splits the photon momentum exactly,
+ * u_pm = (chi_pm/chi_gamma) k, instead of the energy. */
+enum { OR_VAR_SOKOLOV_G = 1, OR_VAR_PAIR_MOMENTUM = 2 };
 
 /* tallies (FP64 energies in m c^2 times weight, and event counts) */
 enum { OR_T_WORK = 0, OR_T_ERAD, OR_T_EPUSH, OR_T_EREC, OR_T_EDROP, OR_T_ESUB,

@@ -61,12 +61,15 @@ class qed_field(C.Structure):
                 ("x0", C.c_double), ("y0", C.c_double), ("z0", C.c_double)]
 
 
+QED_VAR_SOKOLOV_G, QED_VAR_PAIR_MOMENTUM = 1, 2
+
+
 class qed_step(C.Structure):
     _fields_ = [("t", C.c_double), ("dt", C.c_double), ("seed", C.c_uint64),
                 ("rad_model", C.c_int32), ("max_events", C.c_int32),
                 ("chi_switch", C.c_double), ("gamma_photon_min", C.c_double),
                 ("chi_photon_push_min", C.c_double), ("no_recoil", C.c_int32),
-                ("reserved", C.c_int32), ("d_step", _vp)]
+                ("variants", C.c_int32), ("d_step", _vp)]
 
 
 class qed_tally(C.Structure):

@@ -342,6 +342,8 @@ qed_status step_dev(const qed_step *s, qed::StepDev &d) {
     d.t = s->t; d.dt = s->dt; d.d_step = s->d_step; d.seed = s->seed;
     d.rad = s->rad_model; d.kmax = s->max_events; d.chi_switch = s->chi_switch;
     d.gmin = s->gamma_photon_min; d.chi_push_min = s->chi_photon_push_min; d.no_recoil = s->no_recoil;
+    if (s->variants & ~(QED_VAR_SOKOLOV_G | QED_VAR_PAIR_MOMENTUM)) return fail(QED_ERR_ARG, "step: unknown variant bits");
+    d.variants = s->variants;
     return QED_OK;
 }
 

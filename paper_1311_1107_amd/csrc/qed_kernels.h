@@ -42,7 +42,10 @@ struct StepDev {
     int rad, kmax;
     double chi_switch, gmin, chi_push_min;
     int no_recoil;
+    int variants;                    // VAR_* bits
 };
+
+enum { VAR_SOKOLOV_G = 1, VAR_PAIR_MOMENTUM = 2 };
 
 struct ConstsDev {
     double q, es_inv, A, tau0;

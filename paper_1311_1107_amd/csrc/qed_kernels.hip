@@ -487,15 +487,17 @@ k_push_emit(PushArgs a) {
                 const R fy = q * (E[1] + (vz * B[0] - vx * B[2]));
                 const R fz = q * (E[2] + (vx * B[1] - vy * B[0]));
                 const R vf = vx * fx + vy * fy + vz * fz;
-                const R den = R(1) + tau0 * vf;
-                dvx = tau0 * (fx - vx * vf) / den;
-                dvy = tau0 * (fy - vy * vf) / den;
-                dvz = tau0 * (fz - vz * vf) / den;
                 R g = R(1);
                 if (chi > R(0)) {
                     bool above = false;
                     g = Math<R>::exp_(lerp_rate<R>(s_lg, tb.e_n_chi, lnchi0, inv_d, Math<R>::log_(chi), above));
                 }
+                // variant: delta_v with the quantum-reduced tau_0 g(chi)
+                const R tq = (a.st.variants & VAR_SOKOLOV_G) ? tau0 * g : tau0;
+                const R den = R(1) + tq * vf;
+                dvx = tq * (fx - vx * vf) / den;
+                dvy = tq * (fy - vy * vf) / den;
+                dvz = tq * (fz - vz * vf) / den;
                 const R P = (R(2) / R(3)) * Ah * chi * chi * g;
                 const R bx = dvy * B[2] - dvz * B[1], by = dvz * B[0] - dvx * B[2], bz = dvx * B[1] - dvy * B[0];
                 unx = uLx + dtr * (q * bx - P * uLx / gL);
@@ -927,8 +929,11 @@ k_pair_append(PairArgs a) {
                 const R eta = R(1) / (R(1) + Math<R>::exp_(-s));
                 const R chim = eta * chig;
                 const R chip = chig - chim;
-                const R gmn = R(1) + (kk - R(2)) * (chim / chig);
-                const R gpl = R(1) + (kk - R(2)) * (chip / chig);
+                // default: energy split exactly along k; variant: momentum split exactly
+                const bool pmom = (a.st.variants & VAR_PAIR_MOMENTUM) != 0;
+                const R pm_m = (chim / chig) * kk, pm_p = (chip / chig) * kk;
+                const R gmn = pmom ? Math<R>::sqrt_(R(1) + pm_m * pm_m) : R(1) + (kk - R(2)) * (chim / chig);
+                const R gpl = pmom ? Math<R>::sqrt_(R(1) + pm_p * pm_p) : R(1) + (kk - R(2)) * (chip / chig);
                 const uint32_t g = a.ws.tile_pre0[tile] + e;
                 const uint64_t nid = info.uid0 + 2ull * (uint64_t)g;
 #pragma unroll
@@ -937,7 +942,7 @@ k_pair_append(PairArgs a) {
                     const int64_t j = (side == 0 ? info.base0 : info.base1) + (int64_t)g;
                     if (j >= D.cap) { cnt[C_LOST]++; continue; }
                     const R gmag = side == 0 ? gmn : gpl;
-                    const R pm = Math<R>::sqrt_(gmag * gmag - R(1));
+                    const R pm = pmom ? (side == 0 ? pm_m : pm_p) : Math<R>::sqrt_(gmag * gmag - R(1));
                     const R ux = pm * khx, uy = pm * khy, uz = pm * khz;
                     const uint64_t id = nid + (uint64_t)side;
                     ((R *)D.x)[j] = x + dtr * (ux / gmag);

@@ -193,12 +193,13 @@ def yee(grid: torch.Tensor, shape, spacing, origin) -> B.qed_field:
 
 
 def step(t, dt, seed, rad_model=B.QED_RAD_HYBRID, chi_switch=1e-3, gamma_photon_min=2.0,
-         chi_photon_push_min=1e-3, max_events=4, no_recoil=0, d_step=None) -> B.qed_step:
+         chi_photon_push_min=1e-3, max_events=4, no_recoil=0, d_step=None, variants=0) -> B.qed_step:
     s = B.qed_step()
     s.t, s.dt, s.seed = t, dt, seed
     s.rad_model, s.max_events = rad_model, max_events
     s.chi_switch, s.gamma_photon_min, s.chi_photon_push_min = chi_switch, gamma_photon_min, chi_photon_push_min
     s.no_recoil = no_recoil
+    s.variants = variants
     s.d_step = d_step
     return s
 

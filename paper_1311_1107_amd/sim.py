@@ -34,7 +34,7 @@ class Run:
                  pair_capacity: int | None = None, rad_model: int = B.QED_RAD_HYBRID,
                  chi_switch: float = 1e-3, gamma_photon_min: float = 2.0, max_events: int = 4,
                  sched: B.qed_schedule | None = None, compact_every: int = 16, sort_every: int = 0,
-                 deterministic_tally: bool = True, device: str = "cuda"):
+                 deterministic_tally: bool = True, variants: int = 0, device: str = "cuda"):
         self.wl = wl
         self.prec = prec
         self.units = B.qed_units_init(LAMBDA_M)
@@ -60,7 +60,8 @@ class Run:
         self.sched = sched
         self.compact_every = compact_every
         self.step_kw = dict(rad_model=rad_model, chi_switch=chi_switch, gamma_photon_min=gamma_photon_min,
-                            chi_photon_push_min=wl.chi_photon_push_min, max_events=max_events)
+                            chi_photon_push_min=wl.chi_photon_push_min, max_events=max_events,
+                            variants=variants)
         self.el.upload(wl.electrons)
         B.qed_init_optical_depth(self.el.struct(), wl.seed)
         # field

@@ -11,7 +11,7 @@ from paper_1311_1107_amd.workloads import LAMBDA_M, PlaneWave, Uniform, YeePulse
 
 def oracle_run(wl, tabs: O.BoundTables, steps: int, photon_capacity=None, record_capacity=None,
                pair_capacity=None, rad_model=O.RAD_HYBRID, chi_switch=1e-3, gamma_photon_min=2.0,
-               max_events=4, start=0, lazy_grid=False, compact_every=None, sort_every=0):
+               max_events=4, start=0, lazy_grid=False, compact_every=None, sort_every=0, variants=0):
     n0 = len(wl.electrons["x"])
     cap_pair = pair_capacity if pair_capacity is not None else (n0 if wl.push_photons else 0)
     el = O.species_from(wl.electrons, capacity=n0 + cap_pair)
@@ -35,7 +35,7 @@ def oracle_run(wl, tabs: O.BoundTables, steps: int, photon_capacity=None, record
             field = O.make_field(O.FIELD_YEE, grid=grid, shape=f.shape, spacing=f.spacing, origin=f.origin)
         st = O.make_step(n * wl.dt, wl.dt, wl.seed, rad_model=rad_model, chi_switch=chi_switch,
                          gamma_photon_min=gamma_photon_min, chi_photon_push_min=wl.chi_photon_push_min,
-                         max_events=max_events)
+                         max_events=max_events, variants=variants)
         n_ph0 = ph["n"] if ph is not None else 0
         O.push_emit(tabs, LAMBDA_M, -1.0, el, field, ph, rec, st, uid_next, tally)
         O.push_emit(tabs, LAMBDA_M, +1.0, po, field, ph, rec, st, uid_next, tally)

@@ -607,3 +607,36 @@ def test_constant_b_follows_kinetic_equations(gpu_oracle_tables, bound_tables):
     run.ws.status()
     kin = kinetic_moments(bound_tables, checkpoints)
     check(mc, kin, n0, checkpoints)
+
+
+# ------------------------------------------------------- model variants ----
+def test_model_variants_fp64_parity(gpu_oracle_tables, bound_tables):
+    """The alternative readings (Sokolov delta_v with tau_0 g(chi); momentum-
+    exact pair split), both on, against the oracle with the same variants:
+    the constant-B cascade (pairs) and a plane-wave beam in HYBRID mode
+    (Sokolov steps where chi_e < 1e-3, at the pulse edges)."""
+    var = B.QED_VAR_SOKOLOV_G | B.QED_VAR_PAIR_MOMENTUM
+    print("case: variants constant B n=700 steps=120", flush=True)
+    wl = W.constant_b(n=700, steps=120)
+    caps = dict(photon_capacity=120 * 700, pair_capacity=8 * 700)
+    want = oracle_run(wl, bound_tables, wl.steps, variants=var, **caps)
+    assert want["tally"]["N_pair"] > 100
+    run = S.Run(wl, tables=gpu_oracle_tables, compact_every=5, variants=var, **caps)
+    run.run(wl.steps)
+    got = run.result()
+    for sp in ("electrons", "positrons", "photons"):
+        assert_species_match(got[sp], want[sp], what=sp)
+    print("case: variants plane wave n=1000 steps=400", flush=True)
+    wl = _pw_small(seed=61, n=1000, steps=400)
+    want = oracle_run(wl, bound_tables, wl.steps, record_capacity=16 * 1000, variants=var)
+    assert want["tally"]["N_sokolov"] > 0
+    run = S.Run(wl, tables=gpu_oracle_tables, record_capacity=16 * 1000, variants=var)
+    run.run(wl.steps)
+    got = run.result()
+    assert_species_match(got["electrons"], want["electrons"], what="electrons")
+    assert_species_match(got["recorded"], want["recorded"], what="recorded")
+    _tally_match(got["tally"], want["tally"])
+    with pytest.raises(B.QedError):
+        st = D.step(0.0, W.DT, 1, variants=8)
+        B.qed_push_emit(gpu_oracle_tables.h, run.ws.h, run.units, -1.0, run.el.struct(), run.field, None,
+                        run.rec.struct(), run.tally.s, st, run.uid_next.data_ptr(), None)

@@ -356,3 +356,61 @@ def test_capacity_overflow_is_reported(bound_tables):
     rc = O.push_emit(bound_tables, LAM, -1.0, lep, f, None, rec, st, [0], tally)
     assert rc == 1 and rec["n"] == 10
     assert tally.c[O.C_NAMES.index("overflow")] == tally.c[O.C_NAMES.index("rec")] - 10
+
+
+def test_variant_pair_momentum_split(bound_tables):
+    """Alternative reading of the pair split: the photon momentum is shared
+    exactly (u_- + u_+ = k), each lepton on its mass shell, chi still adds up;
+    the energy then exceeds gamma_gamma by O(1/gamma)."""
+    n = 1500
+    ph = O.new_species(n)
+    ph["ux"][:n] = 4000.0
+    ph["uz"][:n] = np.linspace(-100, 100, n)
+    ph["w"][:n] = 0.5
+    ph["tau"][:n] = 1e-12
+    ph["uid"][:n] = np.arange(n, dtype=np.uint64)
+    ph["n"] = n
+    f = O.make_field(O.FIELD_UNIFORM, B=(0, 150.0, 0))
+    el, po = O.new_species(n), O.new_species(n)
+    k = np.stack([ph["ux"][:n], ph["uy"][:n], ph["uz"][:n]], 1).copy()
+    chig = np.array([O.chi_photon(U, kk, [0, 0, 0], [0, 150.0, 0]) for kk in k])
+    st = O.make_step(0.0, 0.05, 3, variants=O.VAR_PAIR_MOMENTUM)
+    O.pair_create(bound_tables, LAM, ph, f, el, po, st, [5000], O.Tally())
+    assert el["n"] == n and po["n"] == n
+    ue = np.stack([el["ux"][:n], el["uy"][:n], el["uz"][:n]], 1)
+    up = np.stack([po["ux"][:n], po["uy"][:n], po["uz"][:n]], 1)
+    assert np.all(np.linalg.norm(ue + up - k, axis=1) <= 1e-13 * np.linalg.norm(k, axis=1))   # momentum exact
+    ge, gp = np.sqrt(1 + (ue ** 2).sum(1)), np.sqrt(1 + (up ** 2).sum(1))
+    kk = np.linalg.norm(k, axis=1)
+    assert np.all(ge + gp >= kk) and np.all(ge + gp - kk <= 1 / ge + 1 / gp)
+    assert el["chi"][:n] + po["chi"][:n] == pytest.approx(chig, rel=1e-14)
+    # each lepton's share of k is its share of chi
+    assert np.linalg.norm(ue, axis=1) / kk == pytest.approx(el["chi"][:n] / chig, rel=1e-13)
+
+
+def test_variant_sokolov_g_scales_delta_v(bound_tables):
+    """Alternative reading of Eq. 4 (delta_v with tau_0 g(chi)).  For E = 0 and
+    u perpendicular to B, f = q v x B and v.f = 0, so delta_v = tau f and the
+    q delta_v x B force is -tau B^2 v: the variant changes the new momentum
+    by exactly dt tau_0 (1 - g(chi)) B^2 v, along v."""
+    Bz = 300.0
+    n = 8
+    p = np.geomspace(50.0, 5000.0, n)
+    e = {"x": np.zeros(n), "y": np.zeros(n), "z": np.zeros(n), "ux": p, "uy": np.zeros(n), "uz": np.zeros(n)}
+    f = O.make_field(O.FIELD_UNIFORM, B=(0, 0, Bz))
+    out = []
+    for var in (0, O.VAR_SOKOLOV_G):
+        s = O.species_from(e)
+        st = O.make_step(0.0, 0.01, 3, rad_model=O.RAD_SOKOLOV, variants=var)
+        O.push_emit(bound_tables, LAM, -1.0, s, f, None, None, st, [n], O.Tally())
+        out.append(np.stack([s["ux"][:n], s["uy"][:n], s["uz"][:n]], 1))
+    # the Boris rotation keeps |u|, so chi and v are those of the rotated momentum
+    u_rot = out[0] / np.linalg.norm(out[0], axis=1)[:, None]            # direction, to O(tau dt)
+    chi = p * Bz / U["Es_hat"]
+    g = np.array([bound_tables.g(c) for c in chi])
+    gam = np.sqrt(1 + p * p)
+    expect = 0.01 * U["tau0_hat"] * (1 - g) * Bz ** 2 * (p / gam)       # |v| = p / gamma
+    diff = out[1] - out[0]
+    assert np.all(g < 1.0) and np.all(expect > 0)
+    assert np.linalg.norm(diff, axis=1) == pytest.approx(expect, rel=1e-5)
+    assert np.all(np.einsum("ij,ij->i", diff, u_rot) > 0)                  # less drag: along v
