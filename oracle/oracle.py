@@ -79,6 +79,12 @@ class Species(C.Structure):
         ("uid", _u64p), ("n_ev", _u32p)]
 
 
+class MergeSpec(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("x0", "y0", "z0", "dx", "dy", "dz")] + \
+               [(n, C.c_int64) for n in ("nx", "ny", "nz")] + \
+               [(n, C.c_int32) for n in ("massive", "octave_min", "n_octaves", "sub_bins", "n_dir", "min_group")]
+
+
 class Field(C.Structure):
     _fields_ = [("kind", C.c_int32), ("E", C.c_double * 3), ("B", C.c_double * 3),
                 ("a0", C.c_double), ("n_periods", C.c_double),
@@ -144,6 +150,8 @@ def lib():
                                      C.POINTER(Step), _u64p, _dp, C.POINTER(C.c_int64)]
         L.or_pair_create.restype = C.c_int
         L.or_sort_by_cell.argtypes = [C.POINTER(Species), C.c_int64, C.c_int64, C.c_int64, d, d, d, d, d, d]
+        L.or_merge.argtypes = [C.POINTER(MergeSpec), C.POINTER(Species), C.POINTER(Species), C.c_uint64, _u64p]
+        L.or_merge.restype = C.c_int64
         _lib = L
     return _lib
 
@@ -452,6 +460,31 @@ def sort_by_cell(s: dict, shape, spacing, origin):
     st = _species_struct(s)
     lib().or_sort_by_cell(C.byref(st), *[int(v) for v in shape], *[float(v) for v in spacing],
                           *[float(v) for v in origin])
+
+
+def merge_spec(box_origin, spacing, shape, massive: bool, octave_min: int, n_octaves: int, sub_bins: int,
+               n_dir: int, min_group: int) -> MergeSpec:
+    m = MergeSpec()
+    m.x0, m.y0, m.z0 = (float(v) for v in box_origin)
+    m.dx, m.dy, m.dz = (float(v) for v in spacing)
+    m.nx, m.ny, m.nz = (int(v) for v in shape)
+    m.massive = int(bool(massive))
+    m.octave_min, m.n_octaves, m.sub_bins = int(octave_min), int(n_octaves), int(sub_bins)
+    m.n_dir, m.min_group = int(n_dir), int(min_group)
+    return m
+
+
+def merge(spec: MergeSpec, s: dict, seed: int, uid_next: int, capacity: int | None = None):
+    """Merging of super-particles (the oracle's or_merge).  Returns the new
+    species and the advanced id counter; raises if capacity is too small."""
+    dst = new_species(max(1, capacity if capacity is not None else int(s["n"])))
+    u = np.array([uid_next], np.uint64)
+    n = lib().or_merge(C.byref(spec), C.byref(_species_struct(s)), C.byref(_species_struct(dst)), seed,
+                       _ptr(u, C.c_uint64))
+    if n < 0:
+        raise ValueError("or_merge: destination too small")
+    dst["n"] = int(n)
+    return dst, int(u[0])
 
 
 def spectrum(s: dict, photons: bool, e_min: float, e_max: float, n_bins: int, weight_scale: float):

@@ -1024,3 +1024,212 @@ void or_sort_by_cell(or_species *s, int64_t nx, int64_t ny, int64_t nz, double d
     memcpy(s->n_ev, te, sizeof(uint32_t) * n);
     free(tmp); free(tu); free(te); free(ki);
 }
+
+/* ======================================================================== *
+ * 11. Merging of super-particles (coalescence).
+ *
+ * The paper asks only that merging keep energy and momentum (end of Sec. 3).
+ * The scheme written here is the two-particle merge of Vranic et al.
+ * (Comput. Phys. Commun. 191, 65 (2015)), which keeps weight, momentum and
+ * energy exactly, so also on average:
+ *  - a particle is eligible if it is alive (tau finite), inside the box of
+ *    cells, of positive finite weight and with |u|^2 inside the energy range;
+ *  - eligible particles are grouped by (cell, energy bin, direction bin);
+ *    energy bins split each octave of |u|^2 into sub_bins equal parts of the
+ *    mantissa; direction bins cut each face of the cube around the origin
+ *    into n_dir x n_dir squares of the face coordinates u_a/|u_d|, u_b/|u_d|,
+ *    d the axis of the largest |u| component (ties to the lower axis),
+ *    a = d+1, b = d+2 (mod 3);
+ *  - a group of at least min_group members becomes two particles of weight
+ *    W/2 at the weighted mean position, each with the energy per unit weight
+ *    E/W (E = sum w gamma, or sum w |k|) and momenta of equal size |u_new|
+ *    at angles +-theta around P = sum w u, cos theta = |P| / (W |u_new|),
+ *    in the plane of P and P x e_{d+1}, chi the weighted mean;
+ *  - groups below min_group and ineligible particles are kept unchanged.
+ * Output order: groups by (cell, momentum bin), members of a kept group in
+ * input order, then the ineligible particles in input order.  New particles
+ * take ids uid_next + (output slot) and a fresh optical depth; *uid_next
+ * advances by the output count.
+ * ======================================================================== */
+typedef struct { uint64_t cell, mbin; int64_t idx; } or_mkey;
+
+static int cmp_mkey(const void *a, const void *b)
+{
+    const or_mkey *p = (const or_mkey *)a, *q = (const or_mkey *)b;
+    if (p->cell != q->cell) return p->cell < q->cell ? -1 : 1;
+    if (p->mbin != q->mbin) return p->mbin < q->mbin ? -1 : 1;
+    return p->idx < q->idx ? -1 : (p->idx > q->idx ? 1 : 0);
+}
+
+/* momentum bin of u, or -1 if |u|^2 is outside the energy range */
+static int64_t merge_mbin(const or_merge_spec *m, double ux, double uy, double uz, int *face_axis)
+{
+    double u[3] = { ux, uy, uz };
+    double u2 = fma(uz, uz, fma(uy, uy, ux * ux));
+    if (!(u2 > 0.0) || !isfinite(u2)) return -1;
+    int ex;
+    double man = frexp(u2, &ex);                    /* u2 = man 2^ex, man in [0.5, 1) */
+    int64_t oct = (int64_t)ex - 1 - m->octave_min;  /* u2 in [2^(ex-1), 2^ex)          */
+    if (oct < 0 || oct >= m->n_octaves) return -1;
+    int64_t sub = (int64_t)floor((2.0 * man - 1.0) * (double)m->sub_bins);
+    int d = 0;
+    if (fabs(u[1]) > fabs(u[d])) d = 1;
+    if (fabs(u[2]) > fabs(u[d])) d = 2;
+    double ud = fabs(u[d]);
+    int64_t ia = (int64_t)floor((u[(d + 1) % 3] / ud + 1.0) * (0.5 * m->n_dir));
+    int64_t ib = (int64_t)floor((u[(d + 2) % 3] / ud + 1.0) * (0.5 * m->n_dir));
+    if (ia > m->n_dir - 1) ia = m->n_dir - 1;
+    if (ib > m->n_dir - 1) ib = m->n_dir - 1;
+    if (ia < 0) ia = 0;
+    if (ib < 0) ib = 0;
+    int64_t face = 2 * d + (u[d] < 0.0 ? 1 : 0);
+    *face_axis = d;
+    int64_t nd2 = (int64_t)m->n_dir * m->n_dir;
+    return ((oct * m->sub_bins + sub) * 6 + face) * nd2 + ia * m->n_dir + ib;
+}
+
+static void copy_particle(const or_species *s, int64_t i, or_species *d, int64_t j)
+{
+    d->x[j] = s->x[i]; d->y[j] = s->y[i]; d->z[j] = s->z[i];
+    d->ux[j] = s->ux[i]; d->uy[j] = s->uy[i]; d->uz[j] = s->uz[i];
+    d->tau[j] = s->tau[i]; d->w[j] = s->w[i]; d->chi[j] = s->chi[i];
+    d->uid[j] = s->uid[i]; d->n_ev[j] = s->n_ev[i];
+}
+
+static double mag3(const double u[3]) { return sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]); }
+
+/* the two particles replacing the members k[a..b) of one group, at dst[o], dst[o+1] */
+static void merge_group(const or_merge_spec *m, const or_species *src, const or_mkey *k, int64_t a, int64_t b,
+                        or_species *dst, int64_t o, uint64_t seed, uint64_t base)
+{
+    /* sums over the group; energies relative to the first member, so that a
+     * group of identical particles gives back their momentum */
+    const int64_t i0 = k[a].idx;
+    const double u0[3] = { src->ux[i0], src->uy[i0], src->uz[i0] };
+    const double m0 = mag3(u0);
+    const double e0 = m->massive ? sqrt(1.0 + m0 * m0) : m0;
+    double W = 0.0, P[3] = { 0.0, 0.0, 0.0 }, S = 0.0, X[3] = { 0.0, 0.0, 0.0 }, Ch = 0.0;
+    for (int64_t j = a; j < b; ++j) {
+        const int64_t i = k[j].idx;
+        const double w = src->w[i], u[3] = { src->ux[i], src->uy[i], src->uz[i] };
+        const double mi = mag3(u);
+        const double ei = m->massive ? sqrt(1.0 + mi * mi) : mi;
+        W += w;
+        for (int c = 0; c < 3; ++c) P[c] += w * u[c];
+        S += w * (ei - e0);
+        X[0] += w * src->x[i]; X[1] += w * src->y[i]; X[2] += w * src->z[i];
+        Ch += w * src->chi[i];
+    }
+    int d;
+    merge_mbin(m, u0[0], u0[1], u0[2], &d);
+    const double eps = e0 + S / W;                     /* energy per unit weight */
+    /* |u_new|: eps for photons; for leptons sqrt(eps^2 - 1), evaluated as
+     * m0 + (eps - e0)(eps + e0)/(|u_new| + m0) */
+    double un = eps;
+    if (m->massive) {
+        const double ur = sqrt(fmax((eps - 1.0) * (eps + 1.0), 0.0));
+        un = (ur + m0 > 0.0) ? m0 + (S / W) * (eps + e0) / (ur + m0) : 0.0;
+    }
+    const double pn = mag3(P);
+    double ph[3] = { 0.0, 0.0, 0.0 };
+    if (pn > 0.0) {
+        for (int c = 0; c < 3; ++c) ph[c] = P[c] / pn;
+    } else {
+        ph[d] = 1.0;
+    }
+    /* cos theta = |P| / (W |u_new|).  The gap G = W |u_new| - |P| is summed
+     * as sum w (|u_new| - |u|) + sum w |u| |u_hat - P_hat|^2 / 2 (the first
+     * sum is zero for photons), which keeps small angles accurate:
+     * 1 - cos theta = G / (W |u_new|). */
+    double G = 0.0;
+    for (int64_t j = a; j < b; ++j) {
+        const int64_t i = k[j].idx;
+        const double w = src->w[i], u[3] = { src->ux[i], src->uy[i], src->uz[i] };
+        const double mi = mag3(u);
+        if (m->massive) G += w * (un - mi);
+        if (mi > 0.0) {
+            const double q[3] = { u[0] / mi - ph[0], u[1] / mi - ph[1], u[2] / mi - ph[2] };
+            G += w * mi * 0.5 * (q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+        }
+    }
+    double omc = (W * un > 0.0) ? G / (W * un) : 0.0;  /* 1 - cos theta */
+    if (omc < 0.0) omc = 0.0;
+    if (omc > 1.0) omc = 1.0;
+    const double ct = 1.0 - omc;
+    const double st = sqrt(omc * (1.0 + ct));
+    /* n = ph x e_{d+1}, normalised */
+    const int e = (d + 1) % 3;
+    double ev[3] = { 0.0, 0.0, 0.0 };
+    ev[e] = 1.0;
+    double nv[3] = { ph[1] * ev[2] - ph[2] * ev[1], ph[2] * ev[0] - ph[0] * ev[2], ph[0] * ev[1] - ph[1] * ev[0] };
+    const double nn = mag3(nv);
+    for (int c = 0; c < 3; ++c) nv[c] /= nn;
+    for (int side = 0; side < 2; ++side, ++o) {
+        const double sg = side == 0 ? 1.0 : -1.0;
+        dst->x[o] = X[0] / W; dst->y[o] = X[1] / W; dst->z[o] = X[2] / W;
+        dst->ux[o] = un * (ct * ph[0] + sg * st * nv[0]);
+        dst->uy[o] = un * (ct * ph[1] + sg * st * nv[1]);
+        dst->uz[o] = un * (ct * ph[2] + sg * st * nv[2]);
+        dst->w[o] = 0.5 * W;
+        dst->chi[o] = Ch / W;
+        dst->uid[o] = base + (uint64_t)o;
+        dst->n_ev[o] = 0;
+        dst->tau[o] = initial_tau(seed, dst->uid[o]);
+    }
+}
+
+int64_t or_merge(const or_merge_spec *m, const or_species *src, or_species *dst, uint64_t seed, uint64_t *uid_next)
+{
+    const int64_t n = src->n;
+    const uint64_t ncell = (uint64_t)(m->nx * m->ny * m->nz);
+    const double idx_ = 1.0 / m->dx, idy = 1.0 / m->dy, idz = 1.0 / m->dz;
+    or_mkey *k = (or_mkey *)malloc(sizeof(or_mkey) * (n > 0 ? n : 1));
+    int64_t live = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (isinf(src->tau[i]) && src->tau[i] > 0.0) continue;           /* decayed photon: dropped */
+        uint64_t cell = ncell, mbin = 0;
+        const double gx = (src->x[i] - m->x0) * idx_, gy = (src->y[i] - m->y0) * idy, gz = (src->z[i] - m->z0) * idz;
+        if (gx >= 0.0 && gy >= 0.0 && gz >= 0.0) {
+            const double fi = floor(gx), fj = floor(gy), fk = floor(gz);
+            if (fi < (double)m->nx && fj < (double)m->ny && fk < (double)m->nz)
+                cell = (uint64_t)((((int64_t)fi * m->ny) + (int64_t)fj) * m->nz + (int64_t)fk);
+        }
+        int d;
+        const int64_t mb = merge_mbin(m, src->ux[i], src->uy[i], src->uz[i], &d);
+        if (cell == ncell || mb < 0 || !(src->w[i] > 0.0) || !isfinite(src->w[i]))
+            cell = ncell;                                                  /* kept as it is */
+        else
+            mbin = (uint64_t)mb;
+        k[live].cell = cell; k[live].mbin = mbin; k[live].idx = i;
+        ++live;
+    }
+    qsort(k, (size_t)live, sizeof(or_mkey), cmp_mkey);
+    /* output count first, so that a short destination is refused untouched */
+    int64_t n_out = 0;
+    for (int64_t a = 0; a < live;) {
+        int64_t b = a + 1;
+        if (k[a].cell != ncell)
+            while (b < live && k[b].cell == k[a].cell && k[b].mbin == k[a].mbin) ++b;
+        n_out += (b - a >= m->min_group) ? 2 : (b - a);
+        a = b;
+    }
+    if (n_out > dst->capacity) { free(k); return -1; }
+    const uint64_t base = *uid_next;
+    int64_t o = 0;
+    for (int64_t a = 0; a < live;) {
+        int64_t b = a + 1;
+        if (k[a].cell != ncell)
+            while (b < live && k[b].cell == k[a].cell && k[b].mbin == k[a].mbin) ++b;
+        if (b - a < m->min_group) {
+            for (int64_t j = a; j < b; ++j) copy_particle(src, k[j].idx, dst, o++);
+        } else {
+            merge_group(m, src, k, a, b, dst, o, seed, base);
+            o += 2;
+        }
+        a = b;
+    }
+    dst->n = o;
+    *uid_next = base + (uint64_t)o;
+    free(k);
+    return o;
+}

@@ -197,6 +197,24 @@ int or_pair_create(const or_tables *tab, const or_units *u,
 void or_sort_by_cell(or_species *s, int64_t nx, int64_t ny, int64_t nz, double dx, double dy, double dz,
                      double x0, double y0, double z0);
 
+/* Merging of super-particles (coalescence; the paper fixes only that energy
+ * and momentum are kept).  Two-particle merge per group of (cell, energy bin,
+ * direction bin), keeping weight, momentum and energy: see the definition in
+ * qed_oracle.c.  Decayed photons are dropped.  Returns the output count, or
+ * -1 (dst untouched) if it exceeds dst->capacity. */
+typedef struct {
+    double x0, y0, z0, dx, dy, dz;      /* cells of the box                    */
+    int64_t nx, ny, nz;
+    int32_t massive;                    /* 1: leptons (energy gamma), 0: photons (|k|) */
+    int32_t octave_min, n_octaves;      /* |u|^2 in [2^octave_min, 2^(octave_min+n_octaves)) */
+    int32_t sub_bins;                   /* bins per octave of |u|^2 (power of two) */
+    int32_t n_dir;                      /* direction bins per face edge          */
+    int32_t min_group;                  /* groups this large or larger are merged */
+} or_merge_spec;
+
+int64_t or_merge(const or_merge_spec *m, const or_species *src, or_species *dst, uint64_t seed,
+                 uint64_t *uid_next);
+
 #ifdef __cplusplus
 }
 #endif

@@ -188,3 +188,42 @@ def subset(wl: Workload, idx) -> Workload:
     e = {k: v[idx].copy() for k, v in wl.electrons.items()}
     return Workload(wl.name + " (subset)", e, wl.field, wl.steps, wl.dt, wl.seed,
                     wl.push_photons, wl.chi_photon_push_min, wl.record_photons, dict(wl.extra))
+
+
+# --------------------------------------------------------------------------
+# particle clouds for the merging tests
+# --------------------------------------------------------------------------
+def merge_cloud(n: int, seed: int, photons: bool = True, shape=(4, 3, 5), spacing=(0.5, 0.5, 0.5),
+                origin=(-1.0, 0.0, 0.5), n_beams: int = 5, spread: float = 0.05, e_range=(1.0, 1.0e4)):
+    """Super-particles clustered in space and momentum, as after a burst of
+    emission: positions uniform over a box of cells (5 % outside it),
+    momenta along n_beams random directions with an angular spread and
+    energies log-uniform over e_range (|k| for photons, |u| for leptons).
+    A few entries are special: decayed photons (tau = +inf), zero weights
+    and momenta outside a 2^-8 .. 2^40 range of |u|^2.  Returns a dict of
+    numpy FP64 arrays plus uid (permuted) and n_ev."""
+    r = np.random.Generator(np.random.PCG64(seed))
+    lo = np.asarray(origin, float)
+    hi = lo + np.asarray(shape) * np.asarray(spacing)
+    pos = r.uniform(lo, hi, size=(n, 3))
+    out = r.random(n) < 0.05
+    pos[out] = r.uniform(lo - 1.0, hi + 1.0, size=(int(out.sum()), 3))
+    dirs = r.normal(size=(n_beams, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    d = dirs[r.integers(0, n_beams, n)] + spread * r.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    mag = 10.0 ** r.uniform(math.log10(e_range[0]), math.log10(e_range[1]), n)
+    u = d * mag[:, None]
+    w = r.uniform(0.5, 2.0, n)
+    tau = r.exponential(1.0, n)
+    k = r.random(n)
+    if photons:
+        tau[k < 0.03] = np.inf
+    w[(k >= 0.03) & (k < 0.04)] = 0.0
+    u[(k >= 0.04) & (k < 0.045)] *= 2.0 ** 21          # |u|^2 above 2^40
+    u[(k >= 0.045) & (k < 0.05)] *= 1e-3                # small |u|
+    return {"x": pos[:, 0].copy(), "y": pos[:, 1].copy(), "z": pos[:, 2].copy(),
+            "ux": u[:, 0].copy(), "uy": u[:, 1].copy(), "uz": u[:, 2].copy(),
+            "tau": tau, "w": w, "chi": r.uniform(0.0, 2.0, n),
+            "uid": r.permutation(np.arange(5000, 5000 + n, dtype=np.uint64)),
+            "n_ev": r.integers(0, 7, n).astype(np.uint32)}
