@@ -371,6 +371,59 @@ qed_status qed_sort_by_cell(qed_sorter *s, qed_workspace *ws, qed_species *src, 
 qed_status qed_spectrum(const qed_species *s, int32_t photons, double e_min, double e_max, int32_t n_bins,
                         double weight_scale, int64_t *count, int64_t *wsum, void *stream);
 
+/* ------------------------------------------------------------------------ *
+ * Merging of super-particles (coalescence).  The paper requires only that a
+ * merge keep energy and momentum (end of Sec. 3); this is the two-particle
+ * merge of Vranic et al. (Comput. Phys. Commun. 191, 65 (2015)), which keeps
+ * weight, momentum and energy exactly.
+ *  Eligible: alive (tau not +INFINITY), inside the box of cells
+ *  (i = floor((x - x0) * (1/dx)) in [0, nx) etc.), weight > 0 and finite,
+ *  |u|^2 in [2^octave_min, 2^(octave_min + n_octaves)).
+ *  Groups: eligible particles with equal (cell, energy bin, direction bin).
+ *  With |u|^2 = m 2^e (frexp, m in [0.5, 1)) the energy bin is
+ *  (e - 1 - octave_min) * sub_bins + floor((2m - 1) sub_bins).  The
+ *  direction bin: face 2d + (u_d < 0), d the axis of the largest |u_c|
+ *  (ties to the lower axis), then floor((u_c/|u_d| + 1) n_dir / 2) (clamped
+ *  to n_dir - 1) for c = d+1 and d+2 (mod 3).  All in FP64 for either
+ *  precision, |u|^2 as fma(uz, uz, fma(uy, uy, ux ux)).
+ *  A group of at least min_group members becomes two particles: weight W/2
+ *  each (W the group's weight), the weighted mean position and chi, energy
+ *  per unit weight E/W (E = sum w gamma for leptons, sum w |k| for photons),
+ *  momenta of equal size |u_new| at angles +-theta about P = sum w u with
+ *  cos theta = |P| / (W |u_new|), split along P x e_(d+1); new ids
+ *  *d_uid_next + (output index), n_event 0, tau drawn as in
+ *  qed_init_optical_depth with seed.  Smaller groups and ineligible
+ *  particles are copied unchanged; decayed photons are dropped.
+ *  Order of dst: groups by (cell, bin) ascending, members of a copied group
+ *  in src order; then the ineligible particles in src order.
+ *  *dst->d_count receives the output count and *d_uid_next [device] advances
+ *  by it.  massive: 1 for leptons, 0 for photons.  src and dst are device
+ *  species of one precision in distinct buffers, chi arrays both present or
+ *  both NULL, dst->capacity >= src->capacity.  The merger holds 28 bytes per
+ *  particle of scratch; calls on one workspace are ordered on one stream.
+ *  QED_ERR_ARG: a null argument, nx ny nz below 1 or a product of 2^31 - 2
+ *  or more, dx dy dz not > 0, n_octaves < 1, sub_bins not a power of two in
+ *  1..64, n_dir outside 1..64, more than 2^31 momentum bins, min_group < 2,
+ *  octave_min outside -1074..1023, mismatched or aliased species,
+ *  src->capacity above the merger's maximum or the workspace's reach
+ *  (4096 x its look-back tiles); QED_ERR_HIP if a launch fails.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    double x0, y0, z0, dx, dy, dz;      /* box of cells                         */
+    int64_t nx, ny, nz;
+    int32_t massive;                    /* 1 leptons, 0 photons                 */
+    int32_t octave_min, n_octaves;      /* energy range of |u|^2, in octaves    */
+    int32_t sub_bins;                   /* energy bins per octave (power of 2)  */
+    int32_t n_dir;                      /* direction bins per face edge         */
+    int32_t min_group;                  /* merge groups of at least this many   */
+} qed_merge_spec;
+
+typedef struct qed_merger qed_merger;
+qed_status qed_merger_create(int64_t max_particles, qed_merger **out);
+void qed_merger_free(qed_merger *m);
+qed_status qed_merge(qed_merger *m, qed_workspace *ws, const qed_merge_spec *spec, qed_species *src,
+                     qed_species *dst, uint64_t seed, uint64_t *d_uid_next, void *stream);
+
 /* Advance a device step counter by one (for graph-captured step sequences). */
 qed_status qed_step_advance(int64_t *d_step, void *stream);
 

@@ -64,6 +64,12 @@ class qed_field(C.Structure):
 QED_VAR_SOKOLOV_G, QED_VAR_PAIR_MOMENTUM = 1, 2
 
 
+class qed_merge_spec(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("x0", "y0", "z0", "dx", "dy", "dz")] + \
+               [(n, C.c_int64) for n in ("nx", "ny", "nz")] + \
+               [(n, C.c_int32) for n in ("massive", "octave_min", "n_octaves", "sub_bins", "n_dir", "min_group")]
+
+
 class qed_step(C.Structure):
     _fields_ = [("t", C.c_double), ("dt", C.c_double), ("seed", C.c_uint64),
                 ("rad_model", C.c_int32), ("max_events", C.c_int32),
@@ -123,6 +129,10 @@ _SIGS = {
     "qed_sorter_create": ([C.c_int64, _P(_vp)], C.c_int32),
     "qed_sorter_free": ([_vp], None),
     "qed_sort_by_cell": ([_vp, _vp, _P(qed_species), _P(qed_species), _P(qed_field), _vp], C.c_int32),
+    "qed_merger_create": ([C.c_int64, _P(_vp)], C.c_int32),
+    "qed_merger_free": ([_vp], None),
+    "qed_merge": ([_vp, _vp, _P(qed_merge_spec), _P(qed_species), _P(qed_species), C.c_uint64, _vp, _vp],
+                  C.c_int32),
 }
 
 _lib = None
@@ -293,6 +303,21 @@ def qed_sorter_free(handle):
 
 def qed_sort_by_cell(sorter, ws, src, dst, grid_field, stream=None):
     _check(lib().qed_sort_by_cell(sorter, ws, C.byref(src), C.byref(dst), C.byref(grid_field), _stream(stream)))
+
+
+def qed_merger_create(max_particles: int) -> C.c_void_p:
+    h = C.c_void_p()
+    _check(lib().qed_merger_create(int(max_particles), C.byref(h)))
+    return h
+
+
+def qed_merger_free(handle):
+    lib().qed_merger_free(handle)
+
+
+def qed_merge(merger, ws, spec, src, dst, seed, uid_next_ptr, stream=None):
+    _check(lib().qed_merge(merger, ws, C.byref(spec), C.byref(src), C.byref(dst), int(seed),
+                           C.c_void_p(uid_next_ptr), _stream(stream)))
 
 
 def qed_spectrum(species, photons, e_min, e_max, n_bins, weight_scale, count_ptr, wsum_ptr, stream=None):

@@ -26,6 +26,7 @@ DEVICE = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "
 SOURCES = [
     ("qed_kernels.hip", True),
     ("qed_sort.hip", True),
+    ("qed_merge.hip", True),
     ("qed_api.cpp", True),
     ("qed_tables.cpp", False),
 ]

@@ -65,6 +65,14 @@ struct qed_sorter {
     int64_t hist_len;
 };
 
+struct qed_merger {
+    int64_t max_particles;
+    uint32_t *buf;                // 7 * max + 2: key0, key1, idx0, idx1, mkey, g (max + 1), o (max + 1)
+    uint32_t *hist;               // 2 * hist_len
+    int64_t *cnt;
+    int64_t hist_len;
+};
+
 struct qed_workspace {
     int device;
     int n_cu;
@@ -627,6 +635,89 @@ qed_status qed_sort_by_cell(qed_sorter *so, qed_workspace *ws, qed_species *src,
     a.live = so->live;
     a.ws = ws->dev;
     HIP_TRY(qed::launch_sort(a, src->prec, passes, ws->n_cu, src->capacity, (hipStream_t)stream));
+    return QED_OK;
+}
+
+// ------------------------------------------------------------------ merging --
+qed_status qed_merger_create(int64_t max_particles, qed_merger **out) {
+    if (!out) return fail(QED_ERR_ARG, "qed_merger_create: null out");
+    *out = nullptr;
+    if (max_particles < 1 || max_particles >= (int64_t)0xffffffffll)
+        return fail(QED_ERR_ARG, "qed_merger_create: max_particles must be in [1, 2^32-1)");
+    qed_merger *m = new qed_merger();
+    m->max_particles = max_particles;
+    m->hist_len = 16 * ((max_particles + 4095) / 4096 + 1);
+    if (hipMalloc(&m->buf, sizeof(uint32_t) * (7 * max_particles + 2)) != hipSuccess ||
+        hipMalloc(&m->hist, sizeof(uint32_t) * 2 * m->hist_len) != hipSuccess ||
+        hipMalloc(&m->cnt, 64) != hipSuccess) {
+        qed_merger_free(m);
+        return fail(QED_ERR_NOMEM, "qed_merger_create: device allocation failed");
+    }
+    *out = m;
+    return QED_OK;
+}
+
+void qed_merger_free(qed_merger *m) {
+    if (!m) return;
+    (void)hipFree(m->buf);
+    (void)hipFree(m->hist);
+    (void)hipFree(m->cnt);
+    delete m;
+}
+
+static int bits_for(uint64_t v) {            // bits needed to hold the values 0..v
+    int b = 0;
+    while (b < 64 && (v >> b) != 0) ++b;
+    return b;
+}
+
+qed_status qed_merge(qed_merger *mg, qed_workspace *ws, const qed_merge_spec *sp, qed_species *src,
+                     qed_species *dst, uint64_t seed, uint64_t *d_uid_next, void *stream) {
+    if (!mg || !ws || !sp || !src || !dst || !d_uid_next) return fail(QED_ERR_ARG, "qed_merge: null argument");
+    const int64_t lim = (int64_t)0x7fffffff;
+    if (sp->nx < 1 || sp->ny < 1 || sp->nz < 1 || sp->nx > lim || sp->ny > lim || sp->nz > lim ||
+        (double)sp->nx * (double)sp->ny * (double)sp->nz >= (double)(lim - 1))
+        return fail(QED_ERR_ARG, "qed_merge: need 1 <= nx, ny, nz and nx ny nz < 2^31 - 2");
+    if (!(sp->dx > 0) || !(sp->dy > 0) || !(sp->dz > 0) || !std::isfinite(sp->x0) || !std::isfinite(sp->y0) ||
+        !std::isfinite(sp->z0))
+        return fail(QED_ERR_ARG, "qed_merge: cell sizes must be > 0 and the origin finite");
+    if (sp->n_octaves < 1 || sp->sub_bins < 1 || sp->sub_bins > 64 || (sp->sub_bins & (sp->sub_bins - 1)) ||
+        sp->n_dir < 1 || sp->n_dir > 64 || sp->min_group < 2 || sp->octave_min < -1074 || sp->octave_min > 1023 ||
+        (sp->massive != 0 && sp->massive != 1))
+        return fail(QED_ERR_ARG, "qed_merge: bad energy or direction bins, min_group or massive flag");
+    const double n_mbins = (double)sp->n_octaves * sp->sub_bins * 6.0 * sp->n_dir * sp->n_dir;
+    if (n_mbins > 2147483648.0) return fail(QED_ERR_ARG, "qed_merge: more than 2^31 momentum bins");
+    qed::MergeArgs a;
+    std::memset(&a, 0, sizeof a);
+    qed_status st;
+    if ((st = species_dev(src, false, "qed_merge(src)", a.src))) return st;
+    if ((st = species_dev(dst, false, "qed_merge(dst)", a.dst))) return st;
+    if (src->prec != dst->prec) return fail(QED_ERR_ARG, "qed_merge: src and dst precisions differ");
+    if (dst->capacity < src->capacity) return fail(QED_ERR_ARG, "qed_merge: dst smaller than src");
+    if (src->capacity > mg->max_particles) return fail(QED_ERR_ARG, "qed_merge: merger too small");
+    if ((src->capacity + 4095) / 4096 > ws->max_tiles) return fail(QED_ERR_ARG, "qed_merge: workspace too small");
+    if ((src->chi == nullptr) != (dst->chi == nullptr)) return fail(QED_ERR_ARG, "qed_merge: chi arrays differ");
+    if (src->x == dst->x || src->tau == dst->tau || src->d_count == dst->d_count || src->uid == dst->uid)
+        return fail(QED_ERR_ARG, "qed_merge: src and dst must be distinct buffers");
+    const int64_t ncell = sp->nx * sp->ny * sp->nz;
+    const int cbits = bits_for((uint64_t)ncell + 1);          // keys 0..ncell < key_dead = 2^cbits - 1
+    a.key_out = (uint32_t)ncell;
+    a.key_dead = (uint32_t)(((uint64_t)1 << cbits) - 1);
+    const int mbits = bits_for((uint64_t)n_mbins - 1);
+    a.x0 = sp->x0; a.y0 = sp->y0; a.z0 = sp->z0;
+    a.inv_dx = 1.0 / sp->dx; a.inv_dy = 1.0 / sp->dy; a.inv_dz = 1.0 / sp->dz;
+    a.nx = sp->nx; a.ny = sp->ny; a.nz = sp->nz;
+    a.massive = sp->massive; a.octave_min = sp->octave_min; a.n_octaves = sp->n_octaves;
+    a.sub_bins = sp->sub_bins; a.n_dir = sp->n_dir; a.min_group = sp->min_group;
+    a.seed = seed;
+    a.uid_next = d_uid_next;
+    const int64_t m = mg->max_particles;
+    a.key[0] = mg->buf; a.key[1] = mg->buf + m; a.idx[0] = mg->buf + 2 * m; a.idx[1] = mg->buf + 3 * m;
+    a.mkey = mg->buf + 4 * m; a.g = mg->buf + 5 * m; a.o = mg->buf + 6 * m + 1;
+    a.hist = mg->hist; a.hoff = mg->hist + mg->hist_len;
+    a.cnt = mg->cnt;
+    a.ws = ws->dev;
+    HIP_TRY(qed::launch_merge(a, src->prec, (mbits + 3) / 4, (cbits + 3) / 4, ws->n_cu, (hipStream_t)stream));
     return QED_OK;
 }
 

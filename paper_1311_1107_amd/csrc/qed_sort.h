@@ -18,6 +18,38 @@ struct SortArgs {
     WsDev ws;
 };
 
+// LSD radix passes over (key, index) pairs: the first *count entries (clamped
+// to cap) of key[cur], idx[cur], 4-bit digits from digit first_pass on,
+// ping-ponging between the two buffers; returns the buffer holding the result.
+struct RadixBufs {
+    uint32_t *key[2], *idx[2];
+    uint32_t *hist, *hoff;           // 16 * ceil(cap / 4096) entries each
+};
+int launch_radix_passes(const RadixBufs &b, int cur, const int64_t *count, int64_t cap, int first_pass, int passes,
+                        int n_cu, WsDev ws, hipStream_t s);
+
+// exclusive scan of the first *count (clamped to cap) entries of in
+void launch_scan_u32(const uint32_t *in, uint32_t *out, const int64_t *count, int64_t cap, int n_cu, WsDev ws,
+                     hipStream_t s);
+
+// Merging of super-particles (qed_merge.hip).
+struct MergeArgs {
+    SpeciesDev src, dst;
+    double x0, y0, z0, inv_dx, inv_dy, inv_dz;
+    int64_t nx, ny, nz;
+    int massive, octave_min, n_octaves, sub_bins, n_dir, min_group;
+    uint32_t key_out, key_dead;      // cell keys of kept-as-is particles and of decayed photons
+    uint64_t seed;
+    uint64_t *uid_next;
+    // scratch: see launch_merge
+    uint32_t *key[2], *idx[2], *mkey, *g, *o;
+    uint32_t *hist, *hoff;
+    int64_t *cnt;                    // live, groups, outputs, first new id
+    WsDev ws;
+};
+
+hipError_t launch_merge(MergeArgs a, int prec, int mbin_passes, int cell_passes, int n_cu, hipStream_t s);
+
 hipError_t launch_sort(const SortArgs &a, int prec, int passes, int n_cu, int64_t capacity, hipStream_t s);
 
 }  // namespace qed

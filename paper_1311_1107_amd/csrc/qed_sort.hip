@@ -80,14 +80,16 @@ k_radix_count(const uint32_t *keys, const int64_t *count, int64_t cap, int shift
     }
 }
 
-// exclusive scan of a u32 array (decoupled look-back over blocks of 4096)
+// exclusive scan of a u32 array of ceil(*count / div) * mult items
+// (decoupled look-back over blocks of 4096)
 __global__ void __launch_bounds__(256)
-k_scan_u32(const uint32_t *in, uint32_t *out, const int64_t *count, int64_t cap, int64_t mult, WsDev ws) {
+k_scan_u32(const uint32_t *in, uint32_t *out, const int64_t *count, int64_t cap, int64_t div, int64_t mult,
+           WsDev ws) {
     __shared__ uint64_t s_ticket;
     __shared__ uint32_t s_wave[2 * kMaxWaves];
     __shared__ uint32_t s_pref;
     const int tid = threadIdx.x;
-    const int64_t n_items = (sort_count(count, cap) + kSortTile - 1) / kSortTile * mult;
+    const int64_t n_items = (sort_count(count, cap) + div - 1) / div * mult;
     const int64_t n_st = (n_items + kSortTile - 1) / kSortTile;
     for (;;) {
         if (tid == 0) s_ticket = atomicAdd((unsigned long long *)ws.ticket, 1ull);
@@ -210,26 +212,44 @@ k_sort_permute(SortArgs a) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *a.dst.count = live;
 }
 
-hipError_t launch_sort(const SortArgs &a, int prec, int passes, int n_cu, int64_t capacity, hipStream_t s) {
+static unsigned radix_grid(int64_t capacity, int n_cu) {
     const int64_t tiles = (capacity + kSortTile - 1) / kSortTile;
-    const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)n_cu * 8));
-    const unsigned ge = (unsigned)std::max<int64_t>(1, std::min<int64_t>((capacity + 255) / 256, (int64_t)n_cu * 16));
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)n_cu * 8));
+}
+
+int launch_radix_passes(const RadixBufs &b, int cur, const int64_t *count, int64_t cap, int first_pass, int passes,
+                        int n_cu, WsDev ws, hipStream_t s) {
+    const int64_t tiles = (cap + kSortTile - 1) / kSortTile;
+    const unsigned gb = radix_grid(cap, n_cu);
     const unsigned gs = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tiles * kDigits + kSortTile - 1) / kSortTile, n_cu));
+    for (int p = 0; p < passes; ++p, cur ^= 1) {
+        const int shift = 4 * (first_pass + p);
+        hipLaunchKernelGGL(k_radix_count, dim3(gb), dim3(256), 0, s, b.key[cur], count, cap, shift, b.hist);
+        hipLaunchKernelGGL(k_scan_u32, dim3(gs), dim3(256), 0, s, b.hist, b.hoff, count, cap, (int64_t)kSortTile,
+                           (int64_t)kDigits, ws);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(gb), dim3(256), 0, s, b.key[cur], b.idx[cur], b.key[cur ^ 1],
+                           b.idx[cur ^ 1], count, cap, shift, b.hoff);
+    }
+    return cur;
+}
+
+void launch_scan_u32(const uint32_t *in, uint32_t *out, const int64_t *count, int64_t cap, int n_cu, WsDev ws,
+                     hipStream_t s) {
+    const unsigned gs = (unsigned)std::max<int64_t>(1, std::min<int64_t>((cap + kSortTile - 1) / kSortTile, (int64_t)n_cu));
+    hipLaunchKernelGGL(k_scan_u32, dim3(gs), dim3(256), 0, s, in, out, count, cap, (int64_t)1, (int64_t)1, ws);
+}
+
+hipError_t launch_sort(const SortArgs &a, int prec, int passes, int n_cu, int64_t capacity, hipStream_t s) {
+    const unsigned ge = (unsigned)std::max<int64_t>(1, std::min<int64_t>((capacity + 255) / 256, (int64_t)n_cu * 16));
     hipLaunchKernelGGL(k_sort_zero, dim3(1), dim3(64), 0, s, a.live);
     if (prec == 0) hipLaunchKernelGGL((k_sort_keys<double>), dim3(ge), dim3(256), 0, s, a);
     else hipLaunchKernelGGL((k_sort_keys<float>), dim3(ge), dim3(256), 0, s, a);
-    uint32_t *kb[2] = {a.key0, a.key1}, *ib[2] = {a.idx0, a.idx1};
-    for (int p = 0; p < passes; ++p) {
-        const int shift = 4 * p;
-        hipLaunchKernelGGL(k_radix_count, dim3(gb), dim3(256), 0, s, kb[p & 1], a.src.count, a.src.cap, shift, a.hist);
-        hipLaunchKernelGGL(k_scan_u32, dim3(gs), dim3(256), 0, s, a.hist, a.hoff, a.src.count, a.src.cap, (int64_t)kDigits, a.ws);
-        hipLaunchKernelGGL(k_radix_scatter, dim3(gb), dim3(256), 0, s, kb[p & 1], ib[p & 1], kb[(p + 1) & 1],
-                           ib[(p + 1) & 1], a.src.count, a.src.cap, shift, a.hoff);
-    }
-    SortArgs b = a;
-    b.idx_final = ib[passes & 1];
-    if (prec == 0) hipLaunchKernelGGL((k_sort_permute<double>), dim3(ge), dim3(256), 0, s, b);
-    else hipLaunchKernelGGL((k_sort_permute<float>), dim3(ge), dim3(256), 0, s, b);
+    RadixBufs b = {{a.key0, a.key1}, {a.idx0, a.idx1}, a.hist, a.hoff};
+    const int fin = launch_radix_passes(b, 0, a.src.count, a.src.cap, 0, passes, n_cu, a.ws, s);
+    SortArgs c = a;
+    c.idx_final = b.idx[fin];
+    if (prec == 0) hipLaunchKernelGGL((k_sort_permute<double>), dim3(ge), dim3(256), 0, s, c);
+    else hipLaunchKernelGGL((k_sort_permute<float>), dim3(ge), dim3(256), 0, s, c);
     return hipGetLastError();
 }
 

@@ -167,6 +167,35 @@ class Sorter:
             B.qed_sorter_free(h)
 
 
+class Merger:
+    """Scratch of the super-particle merging (qed_merge) for up to max_particles."""
+
+    def __init__(self, max_particles: int):
+        self.max_particles = int(max_particles)
+        self.h = B.qed_merger_create(self.max_particles)
+
+    def merge(self, ws: "Workspace", spec: B.qed_merge_spec, src: Species, dst: Species, seed: int,
+              uid_next: torch.Tensor):
+        B.qed_merge(self.h, ws.h, spec, src.struct(), dst.struct(), seed, uid_next.data_ptr())
+
+    def __del__(self):
+        h, self.h = getattr(self, "h", None), None
+        if h:
+            B.qed_merger_free(h)
+
+
+def merge_spec(origin, spacing, shape, massive: bool, octave_min: int, n_octaves: int, sub_bins: int, n_dir: int,
+               min_group: int) -> B.qed_merge_spec:
+    m = B.qed_merge_spec()
+    m.x0, m.y0, m.z0 = (float(v) for v in origin)
+    m.dx, m.dy, m.dz = (float(v) for v in spacing)
+    m.nx, m.ny, m.nz = (int(v) for v in shape)
+    m.massive = int(bool(massive))
+    m.octave_min, m.n_octaves, m.sub_bins = int(octave_min), int(n_octaves), int(sub_bins)
+    m.n_dir, m.min_group = int(n_dir), int(min_group)
+    return m
+
+
 def plane_wave(a0: float, n_periods: float = 10.0) -> B.qed_field:
     f = B.qed_field()
     f.kind = B.QED_FIELD_PLANE_WAVE
