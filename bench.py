@@ -40,6 +40,8 @@ def parse():
     p.add_argument("--copy-calibration", action="store_true",
                    help="run a 1 GiB device copy first (reference for the traffic counters)")
     p.add_argument("--compact-every", type=int, default=16)
+    p.add_argument("--no-merge", action="store_true",
+                   help="cascade: stop at the first full buffer instead of merging super-particles")
     p.add_argument("--sort-every", type=int, default=16, help="cell-order the particles every k steps (Yee)")
     p.add_argument("--batched-steps", type=int, default=1000,
                    help="steps of the FP32-batched vs FP64-plain comparison (0 skips it)")
@@ -301,7 +303,10 @@ def bench_plane(args):
 def bench_cascade(args):
     """High-chi cascade: 5e7 e-, gamma0 1e4, a0 = 1000 plane wave, 500 steps,
     FP32 form; photons with chi_gamma > 0.2 at creation are pushed and tested
-    for pairs, the rest tallied; decayed photons compacted every step."""
+    for pairs, the rest tallied; decayed photons compacted every step.  Every
+    10 steps a species past half of its buffer is merged (qed_merge over
+    lambda/2 cells), unless --no-merge: then the run stops at the first step
+    whose appends did not fit."""
     import torch
 
     from paper_1311_1107_amd import binding as B
@@ -311,7 +316,11 @@ def bench_cascade(args):
     wl = W.cascade_beam(n=args.electrons or 50_000_000)
     n0 = len(wl.electrons["x"])
     K = min(args.steps or wl.steps, wl.steps)
-    run = S.Run(wl, prec=B.QED_F32, photon_capacity=4 * n0, pair_capacity=4 * n0, compact_every=1)
+    lam = W.LAM
+    pol = None if args.no_merge else S.MergePolicy(
+        origin=(-10.0 * lam, -2.0 * lam, -2.0 * lam), spacing=(0.5 * lam,) * 3, shape=(60, 48, 48), sub_bins=4,
+        n_dir=16, min_group=4, threshold=0.5)
+    run = S.Run(wl, prec=B.QED_F32, photon_capacity=4 * n0, pair_capacity=4 * n0, compact_every=1, merge=pol)
     stream = torch.cuda.current_stream()
     growth = []
     chunk = 10
@@ -319,6 +328,7 @@ def bench_cascade(args):
     kms, nl = {}, {}
     done = 0
     stopped = None
+    merge_ms = 0.0
     while done < K:
         k = min(chunk, K - done)
         # the chunk's steps continue the run's step numbering
@@ -330,13 +340,29 @@ def bench_cascade(args):
             nl[key] = nl.get(key, 0) + v
         done += k
         rc, rep = run.ws.status(clear=False, raise_on_error=False)
-        if done % 50 == 0 or rc != 0:
-            growth.append({"step": done, **run.counts()})
-            print(f"bench: cascade step {done}/{K}", file=sys.stderr, flush=True)
         if rc != 0:
             # a buffer is full: stop and report the growth up to this step
+            growth.append({"step": done, **run.counts()})
             stopped = {"step": done, "status": int(rc)}
             break
+        if pol is not None:
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            a.record(stream)
+            m = run.merge_if_needed()
+            b.record(stream)
+            torch.cuda.synchronize()
+            wall += time.perf_counter() - t0
+            if m:
+                merge_ms += a.elapsed_time(b)
+                nl["merge"] = nl.get("merge", 0) + len(m)
+        if done % 50 == 0:
+            growth.append({"step": done, **run.counts()})
+            print(f"bench: cascade step {done}/{K}", file=sys.stderr, flush=True)
+    if merge_ms:
+        kms["merge"] = merge_ms
     rc, _ = run.ws.status(raise_on_error=False)
     t = run.tally.reduce()
     lep = t["N_mc"] + t["N_sokolov"] + t["N_nan"]
@@ -350,16 +376,18 @@ def bench_cascade(args):
     total_bytes = lep_bytes + ph_bytes
     kern_ms = push_ms + pair_ms
     achieved = total_bytes / (kern_ms * 1e-3) / 1e9 if kern_ms > 0 else 0.0
+    merging = "merging every 10 steps past half a buffer" if pol is not None else "no merging"
     return {
         "metric": "QED particle-steps/s", "value": (lep + ph) / wall, "unit": "particle-steps/s", "n_gpus": 1,
         "steps": done, "warmup": 0, "ms_per_step": wall * 1e3 / done, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": f"{n0} e- gamma0 1e4 (1% spread) vs a0=1000 10-period plane wave, {K} steps, "
-                               "FP32 form, photons with chi_gamma>0.2 pushed + pairs, compaction every step"},
+                               "FP32 form, photons with chi_gamma>0.2 pushed + pairs, compaction every step, "
+                               + merging},
         "roofline": {"bound": "hbm", "kernel": "qed_push_emit + qed_pair_create", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
         "detail": {"growth": growth, "stopped_at_capacity": stopped, "kernel_ms": kms, "launches": nl,
-                   "status": int(rc), "tally": t},
+                   "merges": run.merges, "status": int(rc), "tally": t},
     }
 
 

@@ -11,11 +11,15 @@ Order within step n (time t = n dt):
   5. every `compact_every` steps, decayed photons are removed (qed_compact)
   6. (Yee field) every `sort_every` steps, every species is put in stable cell
      order (qed_sort_by_cell), which also drops decayed photons
+Between steps, merge_if_needed() merges the super-particles of a species
+that fills more than a set fraction of its buffer (qed_merge, keeping weight,
+momentum and energy).
 """
 from __future__ import annotations
 
 import ctypes as C
 import math
+from dataclasses import dataclass
 
 import numpy as np
 import torch
@@ -28,13 +32,31 @@ EMIT_SPEC = dict(chi_min=1e-3, chi_max=1e2, n_chi=128, n_q=128, logit_max=18.0)
 PAIR_SPEC = dict(chi_min=1e-2, chi_max=1e2, n_chi=128, n_q=128, logit_max=18.0)
 
 
+@dataclass
+class MergePolicy:
+    """When and how to merge super-particles: a species holding more than
+    `threshold` of its capacity is merged over the cells of the box
+    (origin, spacing, shape) and the momentum bins given (see qed_merge)."""
+    origin: tuple
+    spacing: tuple
+    shape: tuple
+    octave_min: int = -8
+    n_octaves: int = 48
+    sub_bins: int = 2
+    n_dir: int = 8
+    min_group: int = 4
+    threshold: float = 0.5
+    species: tuple = ("ph", "el", "po")
+
+
 class Run:
     def __init__(self, wl: Workload, prec: int = B.QED_F64, tables: D.Tables | None = None,
                  photon_capacity: int | None = None, record_capacity: int | None = None,
                  pair_capacity: int | None = None, rad_model: int = B.QED_RAD_HYBRID,
                  chi_switch: float = 1e-3, gamma_photon_min: float = 2.0, max_events: int = 4,
                  sched: B.qed_schedule | None = None, compact_every: int = 16, sort_every: int = 0,
-                 deterministic_tally: bool = True, variants: int = 0, device: str = "cuda"):
+                 deterministic_tally: bool = True, variants: int = 0, merge: MergePolicy | None = None,
+                 device: str = "cuda"):
         self.wl = wl
         self.prec = prec
         self.units = B.qed_units_init(LAMBDA_M)
@@ -88,6 +110,12 @@ class Run:
                         "po": D.Species(self.po.capacity, prec, chi=True, device=device)}
             if self.ph is not None:
                 self.alt["ph"] = D.Species(self.ph.capacity, prec, chi=True, device=device)
+        # merging: second buffers (shared with the cell ordering) made on first use
+        self.merge_policy = merge
+        self.merger = D.Merger(max(caps)) if merge is not None else None
+        self.merges = []
+        if not self.sort_every:
+            self.alt = {}
         self._photon_view()
 
     def _photon_view(self):
@@ -143,6 +171,35 @@ class Run:
                 run("compact", self.compact)
         if sorting:
             run("sort", self.sort)
+
+    def merge_if_needed(self) -> list:
+        """Merge every species of the policy that holds more than its threshold
+        (reads the counts: one host synchronisation).  Returns what was done."""
+        pol = self.merge_policy
+        if pol is None:
+            return []
+        done = []
+        for name in pol.species:
+            src = getattr(self, name)
+            if src is None or src.capacity == 0:
+                continue
+            n = src.n()
+            if n <= pol.threshold * src.capacity:
+                continue
+            dst = self.alt.get(name)
+            if dst is None:
+                dst = self.alt[name] = D.Species(src.capacity, self.prec, chi=True, device=src.count.device)
+            spec = D.merge_spec(pol.origin, pol.spacing, pol.shape, name != "ph", pol.octave_min, pol.n_octaves,
+                                pol.sub_bins, pol.n_dir, pol.min_group)
+            self.merger.merge(self.ws, spec, src, dst, self.wl.seed, self.uid_next)
+            setattr(self, name, dst)
+            self.alt[name] = src
+            rec = {"species": name, "before": n, "after": dst.n()}
+            done.append(rec)
+            self.merges.append(rec)
+        if done:
+            self._photon_view()
+        return done
 
     def compact(self):
         if self.ph is not None:

@@ -218,3 +218,56 @@ def test_merge_rejects_bad_arguments():
     b, _ = _spec(False, shape=(2048, 2048, 1024))
     with pytest.raises(B.QedError):
         mg.merge(ws, b, src, D.Species(100), 1, uid)          # 2^32 cells
+
+
+def _n_eff(v):
+    w = v["w"][~np.isinf(v["tau"])].astype(np.float64)
+    return float(w.sum() ** 2 / max((w * w).sum(), 1e-300))
+
+
+def test_constant_b_with_photon_merging_follows_kinetic_equations(oracle_tables, bound_tables):
+    """The Sec. 4 cascade (2e4 electrons, FP64) with the photons merged
+    whenever they fill 5 % of their buffer: numbers, energies and mean chi of
+    every species stay on the kinetic solution (Eqs. 9-10), within
+    4 / sqrt(N_eff) + 2 %, N_eff = (sum w)^2 / sum w^2 the effective number of
+    super-particles of unequal weights."""
+    _need_gpu()
+    import math
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from test_oracle_kinetic import kinetic_moments
+
+    from oracle import kinetic as K
+    from paper_1311_1107_amd import sim as S
+    n0, checkpoints = 20_000, (50, 100, 200, 300)
+    wl = W.constant_b(n=n0, steps=max(checkpoints))
+    print(f"case: constant B kinetic with photon merging n={n0}", flush=True)
+    pol = S.MergePolicy(origin=(-40.0, -40.0, -2.0), spacing=(4.0, 4.0, 4.0), shape=(20, 20, 1), sub_bins=4,
+                        n_dir=16, min_group=4, threshold=0.05, species=("ph",))
+    tabs = D.Tables(O.EMIT_SPEC, O.PAIR_SPEC, arrays=oracle_tables)
+    run = S.Run(wl, tables=tabs, rad_model=B.QED_RAD_MC, photon_capacity=160 * n0, pair_capacity=6 * n0,
+                compact_every=8, merge=pol)
+    u = O.units()
+    Bh = wl.field.B[2]
+    mc, parts = {}, {}
+    for n in range(max(checkpoints)):
+        run.step(n)
+        if (n + 1) % 10 == 0:
+            run.merge_if_needed()
+        if n + 1 in checkpoints:
+            torch.cuda.synchronize()
+            sp = {"electrons": run.el.download(), "positrons": run.po.download(), "photons": run.ph.download()}
+            mc[n + 1] = {k: K.mc_moments(v, k == "photons", Bh, u["Es_hat"]) for k, v in sp.items()}
+            parts[n + 1] = {k: _n_eff(v) for k, v in sp.items()}
+    run.ws.status()
+    assert len(run.merges) >= 3 and all(m["after"] < 0.7 * m["before"] for m in run.merges), run.merges
+    kin = kinetic_moments(bound_tables, checkpoints)
+    for s in checkpoints:
+        for sp in ("electrons", "positrons", "photons"):
+            tol = 4.0 / math.sqrt(max(parts[s][sp], 1)) + 0.02
+            for q in ("n", "energy", "chi"):
+                a = mc[s][sp][q] / (n0 if q != "chi" else 1.0)
+                b = kin[s][sp][q]
+                print(f"step {s} {sp} {q}: MC {a:.5g} kinetic {b:.5g} (tol {tol:.3f}, N_eff {parts[s][sp]:.0f})")
+                assert a == pytest.approx(b, rel=tol), (s, sp, q)

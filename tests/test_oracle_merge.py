@@ -306,3 +306,53 @@ def test_merge_drops_decayed_photons_and_refuses_small_destination():
     assert not np.isinf(O.view(res)["tau"]).any()
     with pytest.raises(ValueError):
         O.merge(spec(min_group=10 ** 6), O.species_from(p), seed=1, uid_next=0, capacity=int(res["n"]) - 1)
+
+
+def test_cascade_with_photon_merging_follows_kinetic_equations(bound_tables):
+    """The Sec. 4 constant-B cascade in the oracle (3000 electrons) with the
+    photons merged every 10 steps once they pass 5 % of a 160-per-electron
+    buffer: the species' numbers, energies and mean chi stay on the solution
+    of the kinetic equations (Eqs. 9-10) within 4 / sqrt(N_eff) + 2 %, N_eff
+    the effective number of super-particles (sum w)^2 / sum w^2."""
+    import math
+
+    from oracle import kinetic as K
+    from test_oracle_kinetic import B_TESLA, DT, GAMMA0, kinetic_moments
+    n0, cps = 3000, (50, 100, 200, 300)
+    u = O.units()
+    Bh = B_TESLA / u["B_ref"]
+    p0 = math.sqrt(GAMMA0 ** 2 - 1)
+    el = O.species_from({"x": np.zeros(n0), "y": np.zeros(n0), "z": np.zeros(n0), "ux": np.full(n0, p0),
+                         "uy": np.zeros(n0), "uz": np.zeros(n0), "w": np.ones(n0),
+                         "uid": np.arange(n0, dtype=np.uint64)}, capacity=8 * n0)
+    O.init_tau(el, 7)
+    po, ph = O.new_species(8 * n0), O.new_species(200 * n0)
+    un, tally = [n0], O.Tally()
+    field = O.make_field(O.FIELD_UNIFORM, B=(0.0, 0.0, Bh))
+    sp = O.merge_spec((-40, -40, -2), (4, 4, 4), (20, 20, 1), False, -8, 48, 4, 16, 4)
+    mc, neff, merges = {}, {}, []
+    for n in range(max(cps)):
+        st = O.make_step(n * DT, DT, 7, rad_model=O.RAD_MC, chi_photon_push_min=0.0)
+        n_ph0 = ph["n"]
+        O.push_emit(bound_tables, 0.8e-6, -1.0, el, field, ph, None, st, un, tally)
+        O.push_emit(bound_tables, 0.8e-6, +1.0, po, field, ph, None, st, un, tally)
+        O.pair_create(bound_tables, 0.8e-6, ph, field, el, po, st, un, tally, n_limit=n_ph0)
+        if (n + 1) % 10 == 0 and ph["n"] > 0.05 * 160 * n0:
+            before = ph["n"]
+            ph, un[0] = O.merge(sp, ph, 7, un[0], capacity=len(ph["x"]))
+            merges.append((before, ph["n"]))
+        if n + 1 in cps:
+            v = {"electrons": O.view(el), "positrons": O.view(po), "photons": O.view(ph)}
+            mc[n + 1] = {k: K.mc_moments(x, k == "photons", Bh, u["Es_hat"]) for k, x in v.items()}
+            neff[n + 1] = {}
+            for k, x in v.items():
+                w = x["w"][~np.isinf(x["tau"])]
+                neff[n + 1][k] = w.sum() ** 2 / max((w * w).sum(), 1e-300)
+    assert len(merges) >= 10 and merges[0][1] < 0.5 * merges[0][0]
+    kin = kinetic_moments(bound_tables, cps)
+    for s in cps:
+        for k in ("electrons", "positrons", "photons"):
+            tol = 4.0 / math.sqrt(max(neff[s][k], 1.0)) + 0.02
+            for q in ("n", "energy", "chi"):
+                a = mc[s][k][q] / (n0 if q != "chi" else 1.0)
+                assert a == pytest.approx(kin[s][k][q], rel=tol), (s, k, q)
