@@ -150,6 +150,12 @@ def lib():
                                      C.POINTER(Step), _u64p, _dp, C.POINTER(C.c_int64)]
         L.or_pair_create.restype = C.c_int
         L.or_sort_by_cell.argtypes = [C.POINTER(Species), C.c_int64, C.c_int64, C.c_int64, d, d, d, d, d, d]
+        L.or_yee_advance.argtypes = [_fp, _fp, C.c_int64, C.c_int64, C.c_int64, d, d, d, d]
+        L.or_deposit_current.argtypes = [C.POINTER(Species), _dp, _dp, _dp, C.c_int64, d, d, d, C.c_int64, C.c_int64,
+                                         C.c_int64, d, d, d, d, d, d, _dp]
+        L.or_deposit_current.restype = C.c_int64
+        L.or_deposit_charge.argtypes = [C.POINTER(Species), d, d, C.c_int64, C.c_int64, C.c_int64, d, d, d, d, d, d,
+                                        _dp]
         L.or_merge.argtypes = [C.POINTER(MergeSpec), C.POINTER(Species), C.POINTER(Species), C.c_uint64, _u64p]
         L.or_merge.restype = C.c_int64
         _lib = L
@@ -460,6 +466,48 @@ def sort_by_cell(s: dict, shape, spacing, origin):
     st = _species_struct(s)
     lib().or_sort_by_cell(C.byref(st), *[int(v) for v in shape], *[float(v) for v in spacing],
                           *[float(v) for v in origin])
+
+
+def yee_advance(grid6: np.ndarray, J3: np.ndarray | None, shape, spacing, dt: float, steps: int = 1):
+    """Yee advance(s) of an FP32 grid [6][nx][ny][nz] in place (periodic), with
+    the FP32 current J3 [3][nx][ny][nz] (or none)."""
+    assert grid6.dtype == np.float32 and grid6.flags["C_CONTIGUOUS"]
+    jp = None
+    if J3 is not None:
+        J3 = np.ascontiguousarray(J3, dtype=np.float32)
+        jp = _ptr(J3, C.c_float)
+    for _ in range(steps):
+        lib().or_yee_advance(_ptr(grid6, C.c_float), jp, *[int(v) for v in shape], *[float(v) for v in spacing],
+                             float(dt))
+
+
+def deposit_current(s: dict, old, first: int, q: float, j_scale: float, dt: float, shape, spacing, origin,
+                    J3: np.ndarray | None = None):
+    """Esirkepov currents of particles [first, n) (old = (xo, yo, zo) arrays of
+    their start positions, or None to go back along u/gamma); returns
+    (J3 [3][nx][ny][nz] FP64, number skipped)."""
+    nx, ny, nz = (int(v) for v in shape)
+    if J3 is None:
+        J3 = np.zeros((3, nx, ny, nz))
+    ptrs = [None, None, None]
+    keep = []
+    if old is not None:
+        for c in range(3):
+            a = np.ascontiguousarray(old[c], dtype=np.float64)
+            keep.append(a)
+            ptrs[c] = _ptr(a)
+    sk = lib().or_deposit_current(C.byref(_species_struct(s)), *ptrs, int(first), float(q), float(j_scale), float(dt),
+                                  nx, ny, nz, *[float(v) for v in spacing], *[float(v) for v in origin], _ptr(J3))
+    return J3, int(sk)
+
+
+def deposit_charge(s: dict, q: float, j_scale: float, shape, spacing, origin, rho: np.ndarray | None = None):
+    nx, ny, nz = (int(v) for v in shape)
+    if rho is None:
+        rho = np.zeros((nx, ny, nz))
+    lib().or_deposit_charge(C.byref(_species_struct(s)), float(q), float(j_scale), nx, ny, nz,
+                            *[float(v) for v in spacing], *[float(v) for v in origin], _ptr(rho))
+    return rho
 
 
 def merge_spec(box_origin, spacing, shape, massive: bool, octave_min: int, n_octaves: int, sub_bins: int,

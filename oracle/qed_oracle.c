@@ -1233,3 +1233,171 @@ int64_t or_merge(const or_merge_spec *m, const or_species *src, or_species *dst,
     free(k);
     return o;
 }
+
+/* ======================================================================== *
+ * 12. Field solver and current deposition (coupling the step to a PIC loop).
+ *
+ * The paper's PIC code advances Maxwell's equations on a grid and deposits
+ * the particles' currents (Sec. 1, Sec. 3); it does not describe how.  The
+ * textbook choices are written here:
+ *  - Yee's staggered finite differences (Yee 1966) in normalised units
+ *    (c = 1): dB/dt = -curl E, dE/dt = curl B - J, on the staggering of the
+ *    field gather (Ex at (i+1/2, j, k), ..., Bz at (i+1/2, j+1/2, k)),
+ *    periodic in every direction, FP32 like the grid.  One advance: B by
+ *    dt/2, E by dt with J, B by dt/2, so E and B sit at whole steps for the
+ *    push;
+ *  - charge-conserving deposition with quadratic (TSC) shapes (Esirkepov,
+ *    Comput. Phys. Commun. 135, 144 (2001)): the change of a particle's
+ *    node charges over the step is split into W_x + W_y + W_z, and
+ *    J_x(i+1/2) - J_x(i-1/2) = -Q dx/dt W_x(i), J_x = 0 left of the stencil.
+ * Node charges of a particle of weight w and charge q: Q S_x S_y S_z with
+ * Q = q w j_scale, S the TSC weights around the nearest node of
+ * g = (x - x0) (1/dx).
+ * ======================================================================== */
+
+static inline int64_t wrap(int64_t i, int64_t n) { i %= n; return i < 0 ? i + n : i; }
+
+/* one half (h = dt/2) update of B from E */
+static void yee_b_half(float *g, int64_t nx, int64_t ny, int64_t nz, float cx, float cy, float cz)
+{
+    const int64_t N = nx * ny * nz;
+    const float *Ex = g, *Ey = g + N, *Ez = g + 2 * N;
+    float *Bx = g + 3 * N, *By = g + 4 * N, *Bz = g + 5 * N;
+    for (int64_t i = 0; i < nx; ++i)
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t k = 0; k < nz; ++k) {
+                const int64_t c = (i * ny + j) * nz + k;
+                const int64_t ip = (wrap(i + 1, nx) * ny + j) * nz + k;
+                const int64_t jp = (i * ny + wrap(j + 1, ny)) * nz + k;
+                const int64_t kp = (i * ny + j) * nz + wrap(k + 1, nz);
+                /* B -= h curl E */
+                Bx[c] = fmaf(cz, Ey[kp] - Ey[c], fmaf(-cy, Ez[jp] - Ez[c], Bx[c]));
+                By[c] = fmaf(cx, Ez[ip] - Ez[c], fmaf(-cz, Ex[kp] - Ex[c], By[c]));
+                Bz[c] = fmaf(cy, Ex[jp] - Ex[c], fmaf(-cx, Ey[ip] - Ey[c], Bz[c]));
+            }
+}
+
+/* full update of E from B and J */
+static void yee_e_full(float *g, const float *J, int64_t nx, int64_t ny, int64_t nz, float cx, float cy, float cz,
+                       float dt)
+{
+    const int64_t N = nx * ny * nz;
+    float *Ex = g, *Ey = g + N, *Ez = g + 2 * N;
+    const float *Bx = g + 3 * N, *By = g + 4 * N, *Bz = g + 5 * N;
+    for (int64_t i = 0; i < nx; ++i)
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t k = 0; k < nz; ++k) {
+                const int64_t c = (i * ny + j) * nz + k;
+                const int64_t im = (wrap(i - 1, nx) * ny + j) * nz + k;
+                const int64_t jm = (i * ny + wrap(j - 1, ny)) * nz + k;
+                const int64_t km = (i * ny + j) * nz + wrap(k - 1, nz);
+                const float jx = J ? J[c] : 0.0f, jy = J ? J[N + c] : 0.0f, jz = J ? J[2 * N + c] : 0.0f;
+                /* E += dt curl B - dt J */
+                Ex[c] = fmaf(cy, Bz[c] - Bz[jm], fmaf(-cz, By[c] - By[km], fmaf(-dt, jx, Ex[c])));
+                Ey[c] = fmaf(cz, Bx[c] - Bx[km], fmaf(-cx, Bz[c] - Bz[im], fmaf(-dt, jy, Ey[c])));
+                Ez[c] = fmaf(cx, By[c] - By[im], fmaf(-cy, Bx[c] - Bx[jm], fmaf(-dt, jz, Ez[c])));
+            }
+}
+
+void or_yee_advance(float *grid6, const float *J3, int64_t nx, int64_t ny, int64_t nz, double dx, double dy,
+                    double dz, double dt)
+{
+    const float hx = (float)(0.5 * dt / dx), hy = (float)(0.5 * dt / dy), hz = (float)(0.5 * dt / dz);
+    const float fx = (float)(dt / dx), fy = (float)(dt / dy), fz = (float)(dt / dz);
+    yee_b_half(grid6, nx, ny, nz, hx, hy, hz);
+    yee_e_full(grid6, J3, nx, ny, nz, fx, fy, fz, (float)dt);
+    yee_b_half(grid6, nx, ny, nz, hx, hy, hz);
+}
+
+/* TSC weights of grid coordinate g around its nearest node n */
+static void tsc3(double g, int64_t *n, double s[3])
+{
+    const double fn = floor(g + 0.5);
+    const double d = g - fn;
+    *n = (int64_t)fn;
+    s[0] = 0.5 * (0.5 - d) * (0.5 - d);
+    s[1] = 0.75 - d * d;
+    s[2] = 0.5 * (0.5 + d) * (0.5 + d);
+}
+
+void or_deposit_charge(const or_species *s, double q, double j_scale, int64_t nx, int64_t ny, int64_t nz,
+                       double dx, double dy, double dz, double x0, double y0, double z0, double *rho)
+{
+    const double ix = 1.0 / dx, iy = 1.0 / dy, iz = 1.0 / dz;
+    for (int64_t p = 0; p < s->n; ++p) {
+        if (isinf(s->tau[p]) && s->tau[p] > 0.0) continue;
+        int64_t n[3];
+        double S[3][3];
+        tsc3((s->x[p] - x0) * ix, &n[0], S[0]);
+        tsc3((s->y[p] - y0) * iy, &n[1], S[1]);
+        tsc3((s->z[p] - z0) * iz, &n[2], S[2]);
+        const double Q = q * s->w[p] * j_scale;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                for (int c = 0; c < 3; ++c) {
+                    const int64_t i = wrap(n[0] - 1 + a, nx), j = wrap(n[1] - 1 + b, ny), k = wrap(n[2] - 1 + c, nz);
+                    rho[(i * ny + j) * nz + k] += Q * S[0][a] * S[1][b] * S[2][c];
+                }
+    }
+}
+
+int64_t or_deposit_current(const or_species *s, const double *xo, const double *yo, const double *zo, int64_t first,
+                           double q, double j_scale, double dt, int64_t nx, int64_t ny, int64_t nz, double dx,
+                           double dy, double dz, double x0, double y0, double z0, double *J)
+{
+    const double ix = 1.0 / dx, iy = 1.0 / dy, iz = 1.0 / dz;
+    const double d[3] = { dx, dy, dz };
+    const int64_t nn[3] = { nx, ny, nz };
+    const int64_t N = nx * ny * nz;
+    int64_t skipped = 0;
+    for (int64_t p = first; p < s->n; ++p) {
+        const double xn[3] = { s->x[p], s->y[p], s->z[p] };
+        double xb[3];
+        if (xo) {
+            xb[0] = xo[p - first]; xb[1] = yo[p - first]; xb[2] = zo[p - first];
+        } else {                                        /* created this step: back along u/gamma */
+            const double u[3] = { s->ux[p], s->uy[p], s->uz[p] };
+            const double ig = 1.0 / sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            for (int c = 0; c < 3; ++c) xb[c] = xn[c] - dt * (u[c] * ig);
+        }
+        const double org[3] = { x0, y0, z0 }, inv[3] = { ix, iy, iz };
+        double S0[3][5] = { { 0 } }, S1[3][5] = { { 0 } }, D[3][5];
+        int64_t base[3];
+        int ok = 1;
+        for (int c = 0; c < 3; ++c) {
+            int64_t n0, n1;
+            double s0[3], s1[3];
+            tsc3((xb[c] - org[c]) * inv[c], &n0, s0);
+            tsc3((xn[c] - org[c]) * inv[c], &n1, s1);
+            if (n1 - n0 > 1 || n0 - n1 > 1) { ok = 0; break; }
+            base[c] = n0 - 2;
+            for (int a = 0; a < 3; ++a) {
+                S0[c][1 + a] = s0[a];
+                S1[c][(int)(n1 - n0) + 1 + a] = s1[a];
+            }
+            for (int a = 0; a < 5; ++a) D[c][a] = S1[c][a] - S0[c][a];
+        }
+        if (!ok) { ++skipped; continue; }
+        const double Q = q * s->w[p] * j_scale;
+        /* J_x: prefix along x of -Q dx/dt W_x, W_x = D_x (S_y S_z + D_y S_z/2 + S_y D_z/2 + D_y D_z/3) */
+        for (int comp = 0; comp < 3; ++comp) {
+            const int a1 = (comp + 1) % 3, a2 = (comp + 2) % 3;
+            const double f = -Q * d[comp] / dt;
+            for (int b = 0; b < 5; ++b)
+                for (int c = 0; c < 5; ++c) {
+                    const double t = S0[a1][b] * S0[a2][c] + 0.5 * D[a1][b] * S0[a2][c] + 0.5 * S0[a1][b] * D[a2][c]
+                                     + D[a1][b] * D[a2][c] / 3.0;
+                    double acc = 0.0;
+                    for (int a = 0; a < 4; ++a) {
+                        acc += f * D[comp][a] * t;
+                        int64_t idx[3];
+                        idx[comp] = wrap(base[comp] + a, nn[comp]);
+                        idx[a1] = wrap(base[a1] + b, nn[a1]);
+                        idx[a2] = wrap(base[a2] + c, nn[a2]);
+                        J[comp * N + (idx[0] * ny + idx[1]) * nz + idx[2]] += acc;
+                    }
+                }
+        }
+    }
+    return skipped;
+}

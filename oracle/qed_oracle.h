@@ -215,6 +215,22 @@ typedef struct {
 int64_t or_merge(const or_merge_spec *m, const or_species *src, or_species *dst, uint64_t seed,
                  uint64_t *uid_next);
 
+/* Field solver and current deposition (see section 12 of qed_oracle.c).
+ * Grids are [component][nx][ny][nz] (z fastest), periodic in every direction.
+ * or_yee_advance: B by dt/2, E by dt (minus dt J), B by dt/2, in FP32.
+ * or_deposit_current: Esirkepov TSC currents of particles [first, n) moving
+ * from (xo, yo, zo)[p - first] (or, if xo is NULL, from x - dt u/gamma) to
+ * their present position, added to J3 (FP64); returns the number skipped for
+ * moving more than one cell in some direction.
+ * or_deposit_charge: TSC node charges q w j_scale S_x S_y S_z added to rho. */
+void or_yee_advance(float *grid6, const float *J3, int64_t nx, int64_t ny, int64_t nz, double dx, double dy,
+                    double dz, double dt);
+int64_t or_deposit_current(const or_species *s, const double *xo, const double *yo, const double *zo, int64_t first,
+                           double q, double j_scale, double dt, int64_t nx, int64_t ny, int64_t nz, double dx,
+                           double dy, double dz, double x0, double y0, double z0, double *J3);
+void or_deposit_charge(const or_species *s, double q, double j_scale, int64_t nx, int64_t ny, int64_t nz,
+                       double dx, double dy, double dz, double x0, double y0, double z0, double *rho);
+
 #ifdef __cplusplus
 }
 #endif
