@@ -424,6 +424,49 @@ void qed_merger_free(qed_merger *m);
 qed_status qed_merge(qed_merger *m, qed_workspace *ws, const qed_merge_spec *spec, qed_species *src,
                      qed_species *dst, uint64_t seed, uint64_t *d_uid_next, void *stream);
 
+/* ------------------------------------------------------------------------ *
+ * Coupling to a particle-in-cell loop: the field solver and the currents.
+ * The paper's PIC code advances Maxwell's equations and deposits currents
+ * (Sec. 1, Sec. 3) without saying how; these are the textbook schemes.
+ * Grids are FP32, component-major [c][nx][ny][nz] (z fastest), on the Yee
+ * staggering of the field gather (Ex at (i+1/2, j, k), Bx at (i, j+1/2,
+ * k+1/2), ...; J_c at the position of E_c), periodic in every direction.
+ * The geometry comes from a qed_field of kind QED_FIELD_YEE (its grid
+ * pointer is not used by the deposition calls).
+ *
+ * qed_yee_advance: Yee's scheme in normalised units (c = 1, fields in the
+ *   units of the step): B -= (dt/2) curl E; E += dt curl B - dt J;
+ *   B -= (dt/2) curl E, so that E and B are at whole steps.  J [device]
+ *   3 n floats, or NULL for vacuum.  Each update is
+ *   fmaf(c_a, d_a, fmaf(-c_b, d_b, fmaf(-dt, J, old))) with the
+ *   coefficients rounded once to FP32, so results do not depend on the
+ *   launch.  QED_ERR_ARG if dt is not below the Courant limit
+ *   1/sqrt(1/dx^2 + 1/dy^2 + 1/dz^2).
+ * qed_deposit_current: adds to J [device, 3 n floats] the charge-conserving
+ *   current (Esirkepov, Comput. Phys. Commun. 135, 144 (2001)) of quadratic
+ *   (TSC) particles [first, *s->d_count) moving over one step dt from
+ *   (x_old, y_old, z_old)[p - first] [device, the species' precision] to
+ *   their present position; x_old = NULL takes the start as x - dt u/gamma
+ *   (particles created in the step).  first = *d_first [device], or 0 if
+ *   d_first is NULL.  A particle of weight w adds node charges
+ *   charge * w * j_scale * S_x S_y S_z (with w in physical particles,
+ *   j_scale = 1/(n_c dx dy dz) in units of c/omega_r gives J in e n_c c).
+ *   Particles whose nearest node moves by more than one cell along an axis
+ *   are skipped and added to *d_skipped [device, may be NULL].  Decayed
+ *   photons (tau = +INFINITY) are skipped silently.  Float atomics: the
+ *   order of additions, and so the last bits of J, vary between runs.
+ * qed_deposit_charge: adds the TSC node charges to rho [device, n floats].
+ * qed_save_positions: copies x, y, z of entries [0, *d_count) to x_old,
+ *   y_old, z_old [device, capacity entries of the species' precision].
+ * ------------------------------------------------------------------------ */
+qed_status qed_yee_advance(float *grid, const float *J, const qed_field *geometry, double dt, void *stream);
+qed_status qed_deposit_current(const qed_species *s, const void *x_old, const void *y_old, const void *z_old,
+                               const int64_t *d_first, double charge, double j_scale, double dt,
+                               const qed_field *geometry, float *J, uint64_t *d_skipped, void *stream);
+qed_status qed_deposit_charge(const qed_species *s, double charge, double j_scale, const qed_field *geometry,
+                              float *rho, void *stream);
+qed_status qed_save_positions(const qed_species *s, void *x_old, void *y_old, void *z_old, void *stream);
+
 /* Advance a device step counter by one (for graph-captured step sequences). */
 qed_status qed_step_advance(int64_t *d_step, void *stream);
 

@@ -129,6 +129,11 @@ _SIGS = {
     "qed_sorter_create": ([C.c_int64, _P(_vp)], C.c_int32),
     "qed_sorter_free": ([_vp], None),
     "qed_sort_by_cell": ([_vp, _vp, _P(qed_species), _P(qed_species), _P(qed_field), _vp], C.c_int32),
+    "qed_yee_advance": ([_vp, _vp, _P(qed_field), C.c_double, _vp], C.c_int32),
+    "qed_deposit_current": ([_P(qed_species), _vp, _vp, _vp, _vp, C.c_double, C.c_double, C.c_double, _P(qed_field),
+                             _vp, _vp, _vp], C.c_int32),
+    "qed_deposit_charge": ([_P(qed_species), C.c_double, C.c_double, _P(qed_field), _vp, _vp], C.c_int32),
+    "qed_save_positions": ([_P(qed_species), _vp, _vp, _vp, _vp], C.c_int32),
     "qed_merger_create": ([C.c_int64, _P(_vp)], C.c_int32),
     "qed_merger_free": ([_vp], None),
     "qed_merge": ([_vp, _vp, _P(qed_merge_spec), _P(qed_species), _P(qed_species), C.c_uint64, _vp, _vp],
@@ -303,6 +308,28 @@ def qed_sorter_free(handle):
 
 def qed_sort_by_cell(sorter, ws, src, dst, grid_field, stream=None):
     _check(lib().qed_sort_by_cell(sorter, ws, C.byref(src), C.byref(dst), C.byref(grid_field), _stream(stream)))
+
+
+def qed_yee_advance(grid_ptr, J_ptr, geometry, dt, stream=None):
+    _check(lib().qed_yee_advance(C.c_void_p(grid_ptr), C.c_void_p(J_ptr) if J_ptr else None, C.byref(geometry),
+                                 float(dt), _stream(stream)))
+
+
+def qed_deposit_current(species, old_ptrs, first_ptr, charge, j_scale, dt, geometry, J_ptr, skipped_ptr=None,
+                        stream=None):
+    xo, yo, zo = (C.c_void_p(p) for p in old_ptrs) if old_ptrs else (None, None, None)
+    _check(lib().qed_deposit_current(C.byref(species), xo, yo, zo, C.c_void_p(first_ptr) if first_ptr else None,
+                                     float(charge), float(j_scale), float(dt), C.byref(geometry), C.c_void_p(J_ptr),
+                                     C.c_void_p(skipped_ptr) if skipped_ptr else None, _stream(stream)))
+
+
+def qed_deposit_charge(species, charge, j_scale, geometry, rho_ptr, stream=None):
+    _check(lib().qed_deposit_charge(C.byref(species), float(charge), float(j_scale), C.byref(geometry),
+                                    C.c_void_p(rho_ptr), _stream(stream)))
+
+
+def qed_save_positions(species, old_ptrs, stream=None):
+    _check(lib().qed_save_positions(C.byref(species), *[C.c_void_p(p) for p in old_ptrs], _stream(stream)))
 
 
 def qed_merger_create(max_particles: int) -> C.c_void_p:

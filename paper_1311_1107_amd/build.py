@@ -27,6 +27,7 @@ SOURCES = [
     ("qed_kernels.hip", True),
     ("qed_sort.hip", True),
     ("qed_merge.hip", True),
+    ("qed_fields.hip", True),
     ("qed_api.cpp", True),
     ("qed_tables.cpp", False),
 ]

@@ -13,6 +13,7 @@
 
 #include "qed.h"
 #include "qed_kernels.h"
+#include "qed_fields.h"
 #include "qed_sort.h"
 
 namespace qedtab {
@@ -718,6 +719,85 @@ qed_status qed_merge(qed_merger *mg, qed_workspace *ws, const qed_merge_spec *sp
     a.cnt = mg->cnt;
     a.ws = ws->dev;
     HIP_TRY(qed::launch_merge(a, src->prec, (mbits + 3) / 4, (cbits + 3) / 4, ws->n_cu, (hipStream_t)stream));
+    return QED_OK;
+}
+
+// ------------------------------------------------------------ PIC coupling --
+static qed_status grid_geom(const qed_field *f, const char *who, qed::GridGeom &g) {
+    if (!f || f->kind != QED_FIELD_YEE || f->nx < 1 || f->ny < 1 || f->nz < 1 || !(f->dx > 0) || !(f->dy > 0) ||
+        !(f->dz > 0) || !std::isfinite(f->x0) || !std::isfinite(f->y0) || !std::isfinite(f->z0))
+        return fail(QED_ERR_ARG, "%s: needs a Yee geometry (sizes >= 1, spacings > 0)", who);
+    if ((double)f->nx * (double)f->ny * (double)f->nz > 9.0e15) return fail(QED_ERR_ARG, "%s: grid too large", who);
+    g.nx = f->nx; g.ny = f->ny; g.nz = f->nz;
+    g.x0 = f->x0; g.y0 = f->y0; g.z0 = f->z0;
+    g.dx = f->dx; g.dy = f->dy; g.dz = f->dz;
+    g.inv_dx = 1.0 / f->dx; g.inv_dy = 1.0 / f->dy; g.inv_dz = 1.0 / f->dz;
+    return QED_OK;
+}
+
+static int device_cus() {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) return 256;
+    return n;
+}
+
+qed_status qed_yee_advance(float *grid, const float *J, const qed_field *geometry, double dt, void *stream) {
+    qed::GridGeom g;
+    qed_status st;
+    if ((st = grid_geom(geometry, "qed_yee_advance", g))) return st;
+    if (!grid) return fail(QED_ERR_ARG, "qed_yee_advance: null grid");
+    const double lim = 1.0 / std::sqrt(1.0 / (g.dx * g.dx) + 1.0 / (g.dy * g.dy) + 1.0 / (g.dz * g.dz));
+    if (!(dt > 0.0) || !(dt < lim)) return fail(QED_ERR_ARG, "qed_yee_advance: dt must be in (0, %g)", lim);
+    HIP_TRY(qed::launch_yee_advance(grid, J, g, dt, device_cus(), (hipStream_t)stream));
+    return QED_OK;
+}
+
+qed_status qed_deposit_current(const qed_species *s, const void *x_old, const void *y_old, const void *z_old,
+                               const int64_t *d_first, double charge, double j_scale, double dt,
+                               const qed_field *geometry, float *J, uint64_t *d_skipped, void *stream) {
+    qed::DepositArgs a;
+    std::memset(&a, 0, sizeof a);
+    qed_status st;
+    if ((st = grid_geom(geometry, "qed_deposit_current", a.g))) return st;
+    if ((st = species_dev(s, false, "qed_deposit_current", a.s))) return st;
+    if (!J) return fail(QED_ERR_ARG, "qed_deposit_current: null J");
+    if ((x_old == nullptr) != (y_old == nullptr) || (x_old == nullptr) != (z_old == nullptr))
+        return fail(QED_ERR_ARG, "qed_deposit_current: give all three start arrays or none");
+    if (!(dt > 0.0) || !std::isfinite(charge) || !std::isfinite(j_scale))
+        return fail(QED_ERR_ARG, "qed_deposit_current: dt must be > 0, charge and j_scale finite");
+    a.xo = x_old; a.yo = y_old; a.zo = z_old;
+    a.d_first = d_first;
+    a.q_scale = charge * j_scale;
+    a.dt = dt;
+    a.out = J;
+    a.skipped = (unsigned long long *)d_skipped;
+    HIP_TRY(qed::launch_deposit_current(a, s->prec, device_cus(), (hipStream_t)stream));
+    return QED_OK;
+}
+
+qed_status qed_deposit_charge(const qed_species *s, double charge, double j_scale, const qed_field *geometry,
+                              float *rho, void *stream) {
+    qed::DepositArgs a;
+    std::memset(&a, 0, sizeof a);
+    qed_status st;
+    if ((st = grid_geom(geometry, "qed_deposit_charge", a.g))) return st;
+    if ((st = species_dev(s, false, "qed_deposit_charge", a.s))) return st;
+    if (!rho) return fail(QED_ERR_ARG, "qed_deposit_charge: null rho");
+    if (!std::isfinite(charge) || !std::isfinite(j_scale))
+        return fail(QED_ERR_ARG, "qed_deposit_charge: charge and j_scale must be finite");
+    a.q_scale = charge * j_scale;
+    a.out = rho;
+    HIP_TRY(qed::launch_deposit_charge(a, s->prec, device_cus(), (hipStream_t)stream));
+    return QED_OK;
+}
+
+qed_status qed_save_positions(const qed_species *s, void *x_old, void *y_old, void *z_old, void *stream) {
+    qed::SpeciesDev d;
+    qed_status st;
+    if ((st = species_dev(s, false, "qed_save_positions", d))) return st;
+    if (!x_old || !y_old || !z_old) return fail(QED_ERR_ARG, "qed_save_positions: null destination");
+    HIP_TRY(qed::launch_save_positions(d, x_old, y_old, z_old, s->prec, device_cus(), (hipStream_t)stream));
     return QED_OK;
 }
 

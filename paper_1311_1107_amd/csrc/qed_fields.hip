@@ -1,0 +1,246 @@
+// qed_fields.hip -- Yee field solver and charge-conserving current deposition,
+// the two pieces that couple the QED step to a particle-in-cell loop.
+//
+// Field solver: Yee's staggered finite differences in normalised units
+// (c = 1), dB/dt = -curl E, dE/dt = curl B - J, periodic in every direction,
+// FP32 like the grid [Ex Ey Ez Bx By Bz][nx][ny][nz] (z fastest) that the
+// field gather reads.  One advance is B by dt/2, E by dt, B by dt/2, so that
+// E and B sit at whole steps for the push.  Each update is one thread per
+// cell with the same fmaf order as the oracle, so results are bit-identical.
+//
+// Deposition: Esirkepov's charge-conserving scheme with quadratic (TSC)
+// shapes (Comput. Phys. Commun. 135, 144 (2001)).  Per particle the change of
+// its node charges over the step, on a 5 x 5 x 5 window around the starting
+// node, is split as W_x + W_y + W_z with
+//   W_x = D_x (S_y S_z + D_y S_z / 2 + S_y D_z / 2 + D_y D_z / 3)
+// (S the starting TSC weights, D the change), and J_x at the faces of the
+// window is the running sum of -Q dx/dt W_x along x.  Shapes and sums are
+// FP64; each face value is added to the FP32 current grid with a hardware
+// float atomic, so the order of the additions (and the last bits of J) vary
+// from run to run.  A particle whose nearest node moves by more than one
+// cell in some direction (a step above the Courant limit) is skipped and
+// counted.
+#include <algorithm>
+
+#include "qed_fields.h"
+
+namespace qed {
+
+__device__ __forceinline__ int64_t count_clamped(const int64_t *count, int64_t cap) {
+    const int64_t n = *count;
+    return n < 0 ? 0 : (n > cap ? cap : n);
+}
+
+__device__ __forceinline__ int64_t wrapi(int64_t i, int64_t n) {
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+__global__ void __launch_bounds__(256)
+k_yee_b_half(float *g, int64_t nx, int64_t ny, int64_t nz, float cx, float cy, float cz) {
+    const int64_t N = nx * ny * nz;
+    const float *Ex = g, *Ey = g + N, *Ez = g + 2 * N;
+    float *Bx = g + 3 * N, *By = g + 4 * N, *Bz = g + 5 * N;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = c % nz, j = (c / nz) % ny, i = c / (nz * ny);
+        const int64_t ip = c + ((i + 1 < nx) ? ny * nz : -(nx - 1) * ny * nz);
+        const int64_t jp = c + ((j + 1 < ny) ? nz : -(ny - 1) * nz);
+        const int64_t kp = c + ((k + 1 < nz) ? 1 : -(nz - 1));
+        const float ex = Ex[c], ey = Ey[c], ez = Ez[c];
+        Bx[c] = fmaf(cz, Ey[kp] - ey, fmaf(-cy, Ez[jp] - ez, Bx[c]));
+        By[c] = fmaf(cx, Ez[ip] - ez, fmaf(-cz, Ex[kp] - ex, By[c]));
+        Bz[c] = fmaf(cy, Ex[jp] - ex, fmaf(-cx, Ey[ip] - ey, Bz[c]));
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_yee_e_full(float *g, const float *J, int64_t nx, int64_t ny, int64_t nz, float cx, float cy, float cz, float dt) {
+    const int64_t N = nx * ny * nz;
+    float *Ex = g, *Ey = g + N, *Ez = g + 2 * N;
+    const float *Bx = g + 3 * N, *By = g + 4 * N, *Bz = g + 5 * N;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = c % nz, j = (c / nz) % ny, i = c / (nz * ny);
+        const int64_t im = c - ((i > 0) ? ny * nz : -(nx - 1) * ny * nz);
+        const int64_t jm = c - ((j > 0) ? nz : -(ny - 1) * nz);
+        const int64_t km = c - ((k > 0) ? 1 : -(nz - 1));
+        const float jx = J ? J[c] : 0.0f, jy = J ? J[N + c] : 0.0f, jz = J ? J[2 * N + c] : 0.0f;
+        const float bx = Bx[c], by = By[c], bz = Bz[c];
+        Ex[c] = fmaf(cy, bz - Bz[jm], fmaf(-cz, by - By[km], fmaf(-dt, jx, Ex[c])));
+        Ey[c] = fmaf(cz, bx - Bx[km], fmaf(-cx, bz - Bz[im], fmaf(-dt, jy, Ey[c])));
+        Ez[c] = fmaf(cx, by - By[im], fmaf(-cy, bx - Bx[jm], fmaf(-dt, jz, Ez[c])));
+    }
+}
+
+hipError_t launch_yee_advance(float *grid, const float *J, const GridGeom &g, double dt, int n_cu, hipStream_t s) {
+    const int64_t N = g.nx * g.ny * g.nz;
+    const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((N + 255) / 256, (int64_t)n_cu * 32));
+    const float hx = (float)(0.5 * dt / g.dx), hy = (float)(0.5 * dt / g.dy), hz = (float)(0.5 * dt / g.dz);
+    const float fx = (float)(dt / g.dx), fy = (float)(dt / g.dy), fz = (float)(dt / g.dz);
+    hipLaunchKernelGGL(k_yee_b_half, dim3(gb), dim3(256), 0, s, grid, g.nx, g.ny, g.nz, hx, hy, hz);
+    hipLaunchKernelGGL(k_yee_e_full, dim3(gb), dim3(256), 0, s, grid, J, g.nx, g.ny, g.nz, fx, fy, fz, (float)dt);
+    hipLaunchKernelGGL(k_yee_b_half, dim3(gb), dim3(256), 0, s, grid, g.nx, g.ny, g.nz, hx, hy, hz);
+    return hipGetLastError();
+}
+
+// TSC weights of grid coordinate u around its nearest node (returned)
+__device__ __forceinline__ int64_t tsc_node(double u, double s[3]) {
+    const double fn = floor(u + 0.5);
+    const double d = u - fn;
+    s[0] = 0.5 * (0.5 - d) * (0.5 - d);
+    s[1] = 0.75 - d * d;
+    s[2] = 0.5 * (0.5 + d) * (0.5 + d);
+    return (int64_t)fn;
+}
+
+__device__ __forceinline__ bool coord_ok(double u) { return u > -1.0e15 && u < 1.0e15; }
+
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_deposit_current(DepositArgs a) {
+    const int64_t n = count_clamped(a.s.count, a.s.cap);
+    const int64_t first = a.d_first ? *a.d_first : 0;
+    const R *X = (const R *)a.s.x, *Y = (const R *)a.s.y, *Z = (const R *)a.s.z;
+    const R *UX = (const R *)a.s.ux, *UY = (const R *)a.s.uy, *UZ = (const R *)a.s.uz, *Wt = (const R *)a.s.w;
+    const R *XO = (const R *)a.xo, *YO = (const R *)a.yo, *ZO = (const R *)a.zo;
+    const int64_t N = a.g.nx * a.g.ny * a.g.nz;
+    const int64_t nn[3] = {a.g.nx, a.g.ny, a.g.nz};
+    const double org[3] = {a.g.x0, a.g.y0, a.g.z0}, inv[3] = {a.g.inv_dx, a.g.inv_dy, a.g.inv_dz};
+    const double dd[3] = {a.g.dx, a.g.dy, a.g.dz};
+    uint32_t skipped = 0;
+    for (int64_t p = (first > 0 ? first : 0) + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        if (a.s.tau[p] == HUGE_VAL) continue;
+        const double xn[3] = {(double)X[p], (double)Y[p], (double)Z[p]};
+        double xb[3];
+        if (XO) {
+            xb[0] = (double)XO[p - first]; xb[1] = (double)YO[p - first]; xb[2] = (double)ZO[p - first];
+        } else {
+            const double u0 = (double)UX[p], u1 = (double)UY[p], u2 = (double)UZ[p];
+            const double ig = 1.0 / sqrt(1.0 + u0 * u0 + u1 * u1 + u2 * u2);
+            xb[0] = xn[0] - a.dt * (u0 * ig);
+            xb[1] = xn[1] - a.dt * (u1 * ig);
+            xb[2] = xn[2] - a.dt * (u2 * ig);
+        }
+        double S0[3][5], D[3][5];
+        int64_t base[3];
+        bool ok = true;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double g0 = (xb[c] - org[c]) * inv[c], g1 = (xn[c] - org[c]) * inv[c];
+            double s0[3], s1[3];
+            ok = ok && coord_ok(g0) && coord_ok(g1);
+            const int64_t n0 = tsc_node(ok ? g0 : 0.0, s0), n1 = tsc_node(ok ? g1 : 0.0, s1);
+            const int64_t sh = n1 - n0;
+            ok = ok && sh >= -1 && sh <= 1;
+            base[c] = n0 - 2;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                const int i0 = q - 1, i1 = q - 1 - (int)sh;
+                const double a0 = (i0 >= 0 && i0 < 3) ? s0[i0] : 0.0;
+                const double a1 = (i1 >= 0 && i1 < 3) ? s1[i1] : 0.0;
+                S0[c][q] = a0;
+                D[c][q] = a1 - a0;
+            }
+        }
+        if (!ok) {
+            ++skipped;
+            continue;
+        }
+        const double Q = a.q_scale * (double)Wt[p];
+#pragma unroll
+        for (int comp = 0; comp < 3; ++comp) {
+            const int a1 = (comp + 1) % 3, a2 = (comp + 2) % 3;
+            const double f = -Q * dd[comp] / a.dt;
+            float *J = a.out + comp * N;
+            for (int b = 0; b < 5; ++b)
+                for (int c = 0; c < 5; ++c) {
+                    const double t = S0[a1][b] * S0[a2][c] + 0.5 * D[a1][b] * S0[a2][c] + 0.5 * S0[a1][b] * D[a2][c]
+                                     + D[a1][b] * D[a2][c] / 3.0;
+                    if (t == 0.0) continue;
+                    double acc = 0.0;
+                    int64_t idx[3];
+                    idx[a1] = wrapi(base[a1] + b, nn[a1]);
+                    idx[a2] = wrapi(base[a2] + c, nn[a2]);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        acc += f * D[comp][q] * t;
+                        if (acc == 0.0) continue;
+                        idx[comp] = wrapi(base[comp] + q, nn[comp]);
+                        unsafeAtomicAdd(J + (idx[0] * a.g.ny + idx[1]) * a.g.nz + idx[2], (float)acc);
+                    }
+                }
+        }
+    }
+    if (a.skipped) {
+        skipped = wave_sum_u32(skipped);
+        if (lane_id() == 0 && skipped) atomicAdd(a.skipped, (unsigned long long)skipped);
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_deposit_charge(DepositArgs a) {
+    const int64_t n = count_clamped(a.s.count, a.s.cap);
+    const R *X = (const R *)a.s.x, *Y = (const R *)a.s.y, *Z = (const R *)a.s.z, *Wt = (const R *)a.s.w;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        if (a.s.tau[p] == HUGE_VAL) continue;
+        const double g[3] = {((double)X[p] - a.g.x0) * a.g.inv_dx, ((double)Y[p] - a.g.y0) * a.g.inv_dy,
+                             ((double)Z[p] - a.g.z0) * a.g.inv_dz};
+        if (!coord_ok(g[0]) || !coord_ok(g[1]) || !coord_ok(g[2])) continue;
+        double S[3][3];
+        int64_t nd[3];
+        for (int c = 0; c < 3; ++c) nd[c] = tsc_node(g[c], S[c]);
+        const double Q = a.q_scale * (double)Wt[p];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                for (int k = 0; k < 3; ++k) {
+                    const int64_t ii = wrapi(nd[0] - 1 + i, a.g.nx), jj = wrapi(nd[1] - 1 + j, a.g.ny),
+                                  kk = wrapi(nd[2] - 1 + k, a.g.nz);
+                    unsafeAtomicAdd(a.out + (ii * a.g.ny + jj) * a.g.nz + kk, (float)(Q * S[0][i] * S[1][j] * S[2][k]));
+                }
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_save_positions(SpeciesDev sp, R *xo, R *yo, R *zo) {
+    const int64_t n = count_clamped(sp.count, sp.cap);
+    const R *X = (const R *)sp.x, *Y = (const R *)sp.y, *Z = (const R *)sp.z;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        xo[p] = X[p];
+        yo[p] = Y[p];
+        zo[p] = Z[p];
+    }
+}
+
+static unsigned particle_grid(int64_t cap, int n_cu) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((cap + 255) / 256, (int64_t)n_cu * 16));
+}
+
+hipError_t launch_deposit_current(const DepositArgs &a, int prec, int n_cu, hipStream_t s) {
+    const unsigned gb = particle_grid(a.s.cap, n_cu);
+    if (prec == 0) hipLaunchKernelGGL((k_deposit_current<double>), dim3(gb), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_deposit_current<float>), dim3(gb), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_deposit_charge(const DepositArgs &a, int prec, int n_cu, hipStream_t s) {
+    const unsigned gb = particle_grid(a.s.cap, n_cu);
+    if (prec == 0) hipLaunchKernelGGL((k_deposit_charge<double>), dim3(gb), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_deposit_charge<float>), dim3(gb), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_save_positions(const SpeciesDev &sp, void *xo, void *yo, void *zo, int prec, int n_cu,
+                                 hipStream_t s) {
+    const unsigned gb = particle_grid(sp.cap, n_cu);
+    if (prec == 0)
+        hipLaunchKernelGGL((k_save_positions<double>), dim3(gb), dim3(256), 0, s, sp, (double *)xo, (double *)yo,
+                           (double *)zo);
+    else
+        hipLaunchKernelGGL((k_save_positions<float>), dim3(gb), dim3(256), 0, s, sp, (float *)xo, (float *)yo,
+                           (float *)zo);
+    return hipGetLastError();
+}
+
+}  // namespace qed
