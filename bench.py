@@ -33,7 +33,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=None)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", default="yee", choices=["yee", "plane", "batched", "cascade"])
+    p.add_argument("--workload", default="yee", choices=["yee", "coupled", "plane", "batched", "cascade"])
     p.add_argument("--electrons", type=int, default=None, help="override the electron count")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=1000, help="electrons in the oracle sample")
@@ -434,7 +434,8 @@ def main():
             out = batched_comparison(args.steps or 1000)
         print(json.dumps(out), flush=True)
         return
-    if args.workload == "yee":
+    coupled = args.workload == "coupled"
+    if args.workload in ("yee", "coupled"):
         wl = W.yee_beam(n=args.electrons or 10_000_000)
         caps = dict(photon_capacity=42 * len(wl.electrons["x"]), record_capacity=6 * len(wl.electrons["x"]),
                     pair_capacity=len(wl.electrons["x"]) // 4)
@@ -442,13 +443,17 @@ def main():
         desc = ("1e7 e- (ln gamma0 ~ N(ln 2000, 0.3^2), r <= 2 lambda, x in [20,28) lambda) vs focused pulse "
                 "a0=200 w0=3 lambda 30 fs on a 256x128x128 FP32 Yee grid, TSC gather, FP64, photons with "
                 "chi_gamma>1e-3 pushed + Breit-Wheeler pairs")
+        if coupled:
+            desc += ("; coupled: the pulse sampled once, then advanced by the Yee solver with the leptons' "
+                     "Esirkepov currents (1000 physical electrons per unit weight)")
     else:
         raise SystemExit(f"workload {args.workload}: not wired into bench.py yet")
     K = args.steps if args.steps is not None else wl.steps
     K = min(K, wl.steps)
     n0 = len(wl.electrons["x"])
 
-    run = S.Run(wl, prec=prec, compact_every=args.compact_every, sort_every=args.sort_every, **caps)
+    run = S.Run(wl, prec=prec, compact_every=args.compact_every, sort_every=args.sort_every, coupled=coupled,
+                particles_per_weight=1000.0, **caps)
     init = {k: v.clone() for k, v in run.el.a.items()}
     init_el = run.el
 
@@ -464,6 +469,9 @@ def main():
         run.uid_next.fill_(n0)
         run.tally.zero()
         run._photon_view()
+        if run.coupled:
+            run.fill_field(0)
+            run.skipped.zero_()
 
     for k in range(args.warmup):
         run.step(k)
@@ -538,17 +546,19 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      # counters were taken on the default command: 1e7 electrons, 2000 steps, sort/compact every 16
                      "traffic": (measured_traffic() if dom.startswith("qed_pair_create") and K == 2000 and n0 == 10_000_000
-                                 and args.sort_every == 16 and args.compact_every == 16 else None),
+                                 and args.sort_every == 16 and args.compact_every == 16 and not coupled else None),
                      "bytes_per_launch": dom_bytes / max(dom_n, 1), "avg_launch_ms": dom_ms / max(dom_n, 1)},
         "detail": {"lepton_steps": lepton_steps, "photon_steps": photon_steps, "kernel_ms": kernel_ms,
                    "launches": n_launch, "final_counts": counts, "emissions": tal["N_emit"], "pairs": tal["N_pair"],
                    "status": int(rc), "lepton_bytes": lep_bytes, "photon_bytes": ph_bytes},
     }
-    if args.batched_steps > 0:
+    if coupled:
+        out["detail"]["deposit_skipped"] = int(run.skipped.item())
+    if args.batched_steps > 0 and not coupled:
         del run
         torch.cuda.empty_cache()
         out["batched_vs_plain"] = batched_comparison(args.batched_steps)
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not coupled:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample, K)
     print(json.dumps(out), flush=True)
 

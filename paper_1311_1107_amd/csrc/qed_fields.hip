@@ -21,6 +21,7 @@
 // cell in some direction (a step above the Courant limit) is skipped and
 // counted.
 #include <algorithm>
+#include <climits>
 
 #include "qed_fields.h"
 
@@ -94,86 +95,172 @@ __device__ __forceinline__ int64_t tsc_node(double u, double s[3]) {
 
 __device__ __forceinline__ bool coord_ok(double u) { return u > -1.0e15 && u < 1.0e15; }
 
+__device__ __forceinline__ int wave_min_int(int v) {
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) {
+        const int w = __shfl_xor(v, d, kWave);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+
+// Per-particle stencil of the deposition: window start (node n0 - 2 per axis),
+// starting TSC weights S0 and their change D on the 5-node window.
+struct DepStencil {
+    double S0[3][5], D[3][5];
+    int64_t base[3];
+    double Q;
+};
+
+template <typename R>
+__device__ __forceinline__ bool deposit_stencil(const DepositArgs &a, int64_t p, int64_t first, DepStencil &st) {
+    const R *X = (const R *)a.s.x, *Y = (const R *)a.s.y, *Z = (const R *)a.s.z;
+    const R *XO = (const R *)a.xo, *YO = (const R *)a.yo, *ZO = (const R *)a.zo;
+    const double xn[3] = {(double)X[p], (double)Y[p], (double)Z[p]};
+    double xb[3];
+    if (XO) {
+        xb[0] = (double)XO[p - first]; xb[1] = (double)YO[p - first]; xb[2] = (double)ZO[p - first];
+    } else {
+        const R *UX = (const R *)a.s.ux, *UY = (const R *)a.s.uy, *UZ = (const R *)a.s.uz;
+        const double u0 = (double)UX[p], u1 = (double)UY[p], u2 = (double)UZ[p];
+        const double ig = 1.0 / sqrt(1.0 + u0 * u0 + u1 * u1 + u2 * u2);
+        xb[0] = xn[0] - a.dt * (u0 * ig);
+        xb[1] = xn[1] - a.dt * (u1 * ig);
+        xb[2] = xn[2] - a.dt * (u2 * ig);
+    }
+    const double org[3] = {a.g.x0, a.g.y0, a.g.z0}, inv[3] = {a.g.inv_dx, a.g.inv_dy, a.g.inv_dz};
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double g0 = (xb[c] - org[c]) * inv[c], g1 = (xn[c] - org[c]) * inv[c];
+        double s0[3], s1[3];
+        ok = ok && coord_ok(g0) && coord_ok(g1);
+        const int64_t n0 = tsc_node(ok ? g0 : 0.0, s0), n1 = tsc_node(ok ? g1 : 0.0, s1);
+        const int64_t sh = n1 - n0;
+        ok = ok && sh >= -1 && sh <= 1;
+        st.base[c] = n0 - 2;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const int i0 = q - 1, i1 = q - 1 - (int)sh;
+            const double v0 = (i0 >= 0 && i0 < 3) ? s0[i0] : 0.0;
+            const double v1 = (i1 >= 0 && i1 < 3) ? s1[i1] : 0.0;
+            st.S0[c][q] = v0;
+            st.D[c][q] = v1 - v0;
+        }
+    }
+    st.Q = a.q_scale * (double)((const R *)a.s.w)[p];
+    return ok;
+}
+
+// The face currents of one particle, handed to add(comp, i, j, k, value) with
+// window-relative node offsets (0..4); J_c is the running sum of
+// -Q d_c/dt W_c along c.
+template <typename Add>
+__device__ __forceinline__ void deposit_faces(const DepStencil &st, const double dd[3], double dt, Add add) {
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) {
+        const int a1 = (comp + 1) % 3, a2 = (comp + 2) % 3;
+        const double f = -st.Q * dd[comp] / dt;
+        for (int b = 0; b < 5; ++b)
+            for (int c = 0; c < 5; ++c) {
+                const double t = st.S0[a1][b] * st.S0[a2][c] + 0.5 * st.D[a1][b] * st.S0[a2][c] +
+                                 0.5 * st.S0[a1][b] * st.D[a2][c] + st.D[a1][b] * st.D[a2][c] / 3.0;
+                if (t == 0.0) continue;
+                double acc = 0.0;
+                int off[3];
+                off[a1] = b;
+                off[a2] = c;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    acc += f * st.D[comp][q] * t;
+                    if (acc == 0.0) continue;
+                    off[comp] = q;
+                    add(comp, off[0], off[1], off[2], acc);
+                }
+            }
+    }
+}
+
+// Waves whose 64 particles start within a box of kDepBox nodes per axis
+// (window included; particles in cell order) sum their faces in LDS first
+// and add the box to the grid once; other waves add each face directly.
+constexpr int kDepBox = 8;
+constexpr int kDepBoxN = kDepBox * kDepBox * kDepBox;
+
 template <typename R>
 __global__ void __launch_bounds__(256)
 k_deposit_current(DepositArgs a) {
+    __shared__ float s_box[kMaxWaves][3 * kDepBoxN];
     const int64_t n = count_clamped(a.s.count, a.s.cap);
-    const int64_t first = a.d_first ? *a.d_first : 0;
-    const R *X = (const R *)a.s.x, *Y = (const R *)a.s.y, *Z = (const R *)a.s.z;
-    const R *UX = (const R *)a.s.ux, *UY = (const R *)a.s.uy, *UZ = (const R *)a.s.uz, *Wt = (const R *)a.s.w;
-    const R *XO = (const R *)a.xo, *YO = (const R *)a.yo, *ZO = (const R *)a.zo;
+    const int64_t first0 = a.d_first ? *a.d_first : 0;
+    const int64_t first = first0 > 0 ? first0 : 0;
     const int64_t N = a.g.nx * a.g.ny * a.g.nz;
     const int64_t nn[3] = {a.g.nx, a.g.ny, a.g.nz};
-    const double org[3] = {a.g.x0, a.g.y0, a.g.z0}, inv[3] = {a.g.inv_dx, a.g.inv_dy, a.g.inv_dz};
     const double dd[3] = {a.g.dx, a.g.dy, a.g.dz};
+    const int lane = lane_id(), wv = threadIdx.x / kWave;
+    float *box = s_box[wv];
     uint32_t skipped = 0;
-    for (int64_t p = (first > 0 ? first : 0) + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
-         p += (int64_t)gridDim.x * blockDim.x) {
-        if (a.s.tau[p] == HUGE_VAL) continue;
-        const double xn[3] = {(double)X[p], (double)Y[p], (double)Z[p]};
-        double xb[3];
-        if (XO) {
-            xb[0] = (double)XO[p - first]; xb[1] = (double)YO[p - first]; xb[2] = (double)ZO[p - first];
-        } else {
-            const double u0 = (double)UX[p], u1 = (double)UY[p], u2 = (double)UZ[p];
-            const double ig = 1.0 / sqrt(1.0 + u0 * u0 + u1 * u1 + u2 * u2);
-            xb[0] = xn[0] - a.dt * (u0 * ig);
-            xb[1] = xn[1] - a.dt * (u1 * ig);
-            xb[2] = xn[2] - a.dt * (u2 * ig);
+    const int64_t wstride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t w0 = first + ((int64_t)blockIdx.x * (blockDim.x / kWave) + wv) * kWave; w0 < n; w0 += wstride) {
+        const int64_t p = w0 + lane;
+        const bool active = p < n && a.s.tau[p] != HUGE_VAL;
+        DepStencil st;
+        bool ok = false;
+        if (active) {
+            ok = deposit_stencil<R>(a, p, first, st);
+            if (!ok) ++skipped;
         }
-        double S0[3][5], D[3][5];
-        int64_t base[3];
-        bool ok = true;
+        const bool boxable = ok && st.base[0] > -(1 << 29) && st.base[0] < (1 << 29) && st.base[1] > -(1 << 29) &&
+                             st.base[1] < (1 << 29) && st.base[2] > -(1 << 29) && st.base[2] < (1 << 29);
+        int o[3];
+        bool fits = __ballot(boxable) != 0;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const double g0 = (xb[c] - org[c]) * inv[c], g1 = (xn[c] - org[c]) * inv[c];
-            double s0[3], s1[3];
-            ok = ok && coord_ok(g0) && coord_ok(g1);
-            const int64_t n0 = tsc_node(ok ? g0 : 0.0, s0), n1 = tsc_node(ok ? g1 : 0.0, s1);
-            const int64_t sh = n1 - n0;
-            ok = ok && sh >= -1 && sh <= 1;
-            base[c] = n0 - 2;
-#pragma unroll
-            for (int q = 0; q < 5; ++q) {
-                const int i0 = q - 1, i1 = q - 1 - (int)sh;
-                const double a0 = (i0 >= 0 && i0 < 3) ? s0[i0] : 0.0;
-                const double a1 = (i1 >= 0 && i1 < 3) ? s1[i1] : 0.0;
-                S0[c][q] = a0;
-                D[c][q] = a1 - a0;
+        for (int d = 0; d < 3; ++d) {
+            o[d] = wave_min_int(boxable ? (int)st.base[d] : INT_MAX);
+            const int hi = -wave_min_int(boxable ? -(int)st.base[d] : INT_MAX);
+            fits = fits && hi - o[d] + 5 <= kDepBox;
+        }
+        if (fits) {
+            for (int e = lane; e < 3 * kDepBoxN; e += kWave) box[e] = 0.0f;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        if (ok) {
+            if (fits && boxable) {
+                const int l0 = (int)st.base[0] - o[0], l1 = (int)st.base[1] - o[1], l2 = (int)st.base[2] - o[2];
+                deposit_faces(st, dd, a.dt, [&](int comp, int i, int j, int k, double v) {
+                    atomicAdd(box + comp * kDepBoxN + ((l0 + i) * kDepBox + (l1 + j)) * kDepBox + (l2 + k), (float)v);
+                });
+            } else {
+                deposit_faces(st, dd, a.dt, [&](int comp, int i, int j, int k, double v) {
+                    const int64_t ii = wrapi(st.base[0] + i, nn[0]), jj = wrapi(st.base[1] + j, nn[1]),
+                                  kk = wrapi(st.base[2] + k, nn[2]);
+                    unsafeAtomicAdd(a.out + comp * N + (ii * a.g.ny + jj) * a.g.nz + kk, (float)v);
+                });
             }
         }
-        if (!ok) {
-            ++skipped;
-            continue;
-        }
-        const double Q = a.q_scale * (double)Wt[p];
-#pragma unroll
-        for (int comp = 0; comp < 3; ++comp) {
-            const int a1 = (comp + 1) % 3, a2 = (comp + 2) % 3;
-            const double f = -Q * dd[comp] / a.dt;
-            float *J = a.out + comp * N;
-            for (int b = 0; b < 5; ++b)
-                for (int c = 0; c < 5; ++c) {
-                    const double t = S0[a1][b] * S0[a2][c] + 0.5 * D[a1][b] * S0[a2][c] + 0.5 * S0[a1][b] * D[a2][c]
-                                     + D[a1][b] * D[a2][c] / 3.0;
-                    if (t == 0.0) continue;
-                    double acc = 0.0;
-                    int64_t idx[3];
-                    idx[a1] = wrapi(base[a1] + b, nn[a1]);
-                    idx[a2] = wrapi(base[a2] + c, nn[a2]);
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        acc += f * D[comp][q] * t;
-                        if (acc == 0.0) continue;
-                        idx[comp] = wrapi(base[comp] + q, nn[comp]);
-                        unsafeAtomicAdd(J + (idx[0] * a.g.ny + idx[1]) * a.g.nz + idx[2], (float)acc);
-                    }
-                }
+        if (fits) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int e = lane; e < 3 * kDepBoxN; e += kWave) {
+                const float v = box[e];
+                if (v == 0.0f) continue;
+                const int comp = e / kDepBoxN, r = e % kDepBoxN;
+                const int i = r / (kDepBox * kDepBox), j = (r / kDepBox) % kDepBox, k = r % kDepBox;
+                const int64_t ii = wrapi((int64_t)o[0] + i, nn[0]), jj = wrapi((int64_t)o[1] + j, nn[1]),
+                              kk = wrapi((int64_t)o[2] + k, nn[2]);
+                unsafeAtomicAdd(a.out + comp * N + (ii * a.g.ny + jj) * a.g.nz + kk, v);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
     }
     if (a.skipped) {
         skipped = wave_sum_u32(skipped);
-        if (lane_id() == 0 && skipped) atomicAdd(a.skipped, (unsigned long long)skipped);
+        if (lane == 0 && skipped) atomicAdd(a.skipped, (unsigned long long)skipped);
     }
 }
 

@@ -14,6 +14,18 @@ Order within step n (time t = n dt):
 Between steps, merge_if_needed() merges the super-particles of a species
 that fills more than a set fraction of its buffer (qed_merge, keeping weight,
 momentum and energy).
+
+Coupled form (coupled=True, Yee field): the pulse is sampled onto the grid
+once, at step 0, and from then on the grid is advanced by the field solver
+with the leptons' currents:
+  1. the leptons' positions are saved (qed_save_positions)
+  2-3. electrons and positrons are pushed with the field at step n
+  then their charge-conserving currents over the step are deposited
+  4. photons are stepped; the pairs they create deposit the current of
+     their motion from the photon's position (qed_deposit_current, x_old
+     NULL, from the lepton counts before the photon step)
+  5. qed_yee_advance takes E and B from step n to n+1 with that current
+Weights are numbers of physical particles times particles_per_weight.
 """
 from __future__ import annotations
 
@@ -56,7 +68,7 @@ class Run:
                  chi_switch: float = 1e-3, gamma_photon_min: float = 2.0, max_events: int = 4,
                  sched: B.qed_schedule | None = None, compact_every: int = 16, sort_every: int = 0,
                  deterministic_tally: bool = True, variants: int = 0, merge: MergePolicy | None = None,
-                 device: str = "cuda"):
+                 coupled: bool = False, particles_per_weight: float = 1.0, device: str = "cuda"):
         self.wl = wl
         self.prec = prec
         self.units = B.qed_units_init(LAMBDA_M)
@@ -110,6 +122,24 @@ class Run:
                         "po": D.Species(self.po.capacity, prec, chi=True, device=device)}
             if self.ph is not None:
                 self.alt["ph"] = D.Species(self.ph.capacity, prec, chi=True, device=device)
+        # coupling to the field solver
+        self.coupled = bool(coupled)
+        if self.coupled:
+            if self.grid is None:
+                raise ValueError("the coupled form needs a Yee grid")
+            nx, ny, nz = f.shape
+            self.J = torch.zeros(3 * nx * ny * nz, dtype=torch.float32, device=device)
+            dt_ = D._dtype(prec)
+            self.x_old = {k: [torch.zeros(max(1, sp.capacity), dtype=dt_, device=device) for _ in range(3)]
+                          for k, sp in (("el", self.el), ("po", self.po))}
+            self.lep_snap = {k: torch.zeros(1, dtype=torch.int64, device=device) for k in ("el", "po")}
+            self.skipped = torch.zeros(1, dtype=torch.int64, device=device)
+            # one physical particle per unit weight: charge density unit n_c over a cell of dx dy dz (c/omega_r)^3
+            eps0, me, c, e = 8.8541878128e-12, 9.1093837015e-31, 299792458.0, 1.602176634e-19
+            omega = 2.0 * math.pi * c / LAMBDA_M
+            nc_cube = eps0 * me * c ** 3 / (e * e * omega)
+            self.j_scale = particles_per_weight / (nc_cube * f.spacing[0] * f.spacing[1] * f.spacing[2])
+            self.fill_field(0)
         # merging: second buffers (shared with the cell ordering) made on first use
         self.merge_policy = merge
         self.merger = D.Merger(max(caps)) if merge is not None else None
@@ -150,7 +180,9 @@ class Run:
         """Step n.  `timed(kind, fn)`, if given, wraps every launch (for timing)."""
         run = timed or (lambda kind, fn: fn())
         st = D.step(n * self.wl.dt, self.wl.dt, self.wl.seed, **self.step_kw)
-        if self.grid is not None:
+        if self.coupled:
+            run("save", self._save_positions)
+        elif self.grid is not None:
             run("fill", lambda: self.fill_field(n))
         if self.ph is not None:
             self.ph_snap.copy_(self.ph.count)
@@ -162,15 +194,39 @@ class Run:
         run("push_p", lambda: B.qed_push_emit(self.tables.h, self.ws.h, self.units, +1.0, self.po.struct(),
                                               self.field, pp, pr, self.tally.s, st, uid, self.sched))
         sorting = bool(self.sort_every) and (n + 1) % self.sort_every == 0
+        if self.coupled:
+            run("deposit", self._deposit_pushed)
         if self.ph is not None:
             run("pair", lambda: B.qed_pair_create(self.tables.h, self.ws.h, self.units, self.ph_step, self.field,
                                                   self.el.struct(), self.po.struct(), self.tally.s, st, uid,
                                                   self.sched))
+            if self.coupled:
+                run("deposit", self._deposit_created)
             # the cell sort drops decayed photons itself
             if self.compact_every and (n + 1) % self.compact_every == 0 and not sorting:
                 run("compact", self.compact)
+        if self.coupled:
+            run("field", lambda: B.qed_yee_advance(self.grid.data_ptr(), self.J.data_ptr(), self.field, self.wl.dt))
         if sorting:
             run("sort", self.sort)
+
+    # ------------------------------------------------------------------
+    def _save_positions(self):
+        for k in ("el", "po"):
+            sp = getattr(self, k)
+            B.qed_save_positions(sp.struct(), [t.data_ptr() for t in self.x_old[k]])
+            self.lep_snap[k].copy_(sp.count)
+
+    def _deposit_pushed(self):
+        self.J.zero_()
+        for k, q in (("el", -1.0), ("po", 1.0)):
+            B.qed_deposit_current(getattr(self, k).struct(), [t.data_ptr() for t in self.x_old[k]], None, q,
+                                  self.j_scale, self.wl.dt, self.field, self.J.data_ptr(), self.skipped.data_ptr())
+
+    def _deposit_created(self):
+        for k, q in (("el", -1.0), ("po", 1.0)):
+            B.qed_deposit_current(getattr(self, k).struct(), None, self.lep_snap[k].data_ptr(), q, self.j_scale,
+                                  self.wl.dt, self.field, self.J.data_ptr(), self.skipped.data_ptr())
 
     def merge_if_needed(self) -> list:
         """Merge every species of the policy that holds more than its threshold

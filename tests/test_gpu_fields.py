@@ -172,3 +172,42 @@ def test_save_positions_copies_live_entries():
         for c, k in enumerate("xyz"):
             v = old[c].cpu().numpy()
             assert np.array_equal(v[:1000], p[k].astype(v.dtype)) and np.all(v[1000:] == -7.0)
+
+
+def test_coupled_run_keeps_gauss_law():
+    """A coupled run (2000 electrons against a0 = 800 on a 64 x 32 x 32 grid,
+    weights of 1e9 physical electrons so that the currents matter, photons
+    and pairs on): the grid is advanced by the solver with the leptons'
+    currents, and div E - rho of the leptons stays what it was at step 0."""
+    _need_gpu()
+    from paper_1311_1107_amd import sim as S
+    from paper_1311_1107_amd import workloads as W
+    wl = W.yee_beam(n=2000, steps=60, seed=12, shape=(64, 32, 32), a0=800.0, gamma_median=4000.0,
+                    x_range_lambda=(3.0, 5.0), r_max_lambda=1.0, x_center0=12.0)
+    print("case: coupled run 2000 e- 60 steps", flush=True)
+    run = S.Run(wl, photon_capacity=200 * 2000, record_capacity=200 * 2000, pair_capacity=40 * 2000, coupled=True,
+                particles_per_weight=1e9, compact_every=4)
+    f = wl.field
+    geo = _geom(f.shape, f.spacing, f.origin)
+    N = int(np.prod(f.shape))
+
+    def gauss():
+        rho = torch.zeros(N, dtype=torch.float32, device="cuda")
+        B.qed_deposit_charge(run.el.struct(), -1.0, run.j_scale, geo, rho.data_ptr())
+        B.qed_deposit_charge(run.po.struct(), 1.0, run.j_scale, geo, rho.data_ptr())
+        torch.cuda.synchronize()
+        g = run.grid.cpu().numpy().astype(np.float64).reshape((6,) + tuple(f.shape))
+        dx, dy, dz = f.spacing
+        div = ((g[0] - np.roll(g[0], 1, 0)) / dx + (g[1] - np.roll(g[1], 1, 1)) / dy
+               + (g[2] - np.roll(g[2], 1, 2)) / dz)
+        r = rho.cpu().numpy().astype(np.float64).reshape(f.shape)
+        return div - r, np.max(np.abs(r)), np.max(np.abs(div))
+    g0, r0, d0 = gauss()
+    for n in range(wl.steps):
+        run.step(n)
+    g1, r1, d1 = gauss()
+    run.ws.status()
+    t = run.tally.reduce()
+    assert t["N_emit"] > 100 and int(run.skipped.item()) == 0
+    assert r1 > 1e-3 * d1                 # the charges are not negligible next to the field
+    assert np.max(np.abs(g1 - g0)) <= 1e-4 * max(r1, d1)
