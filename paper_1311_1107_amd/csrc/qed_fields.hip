@@ -109,6 +109,7 @@ __device__ __forceinline__ int wave_min_int(int v) {
 struct DepStencil {
     double S0[3][5], D[3][5];
     int64_t base[3];
+    int lo[3], hi[3];                // first window node of the support, last face with current
     double Q;
 };
 
@@ -139,6 +140,10 @@ __device__ __forceinline__ bool deposit_stencil(const DepositArgs &a, int64_t p,
         const int64_t sh = n1 - n0;
         ok = ok && sh >= -1 && sh <= 1;
         st.base[c] = n0 - 2;
+        // weights live on window nodes [lo, lo + 3]: lo = 1 + min(sh, 0); current flows
+        // through faces lo .. hi, hi = 2 + max(sh, 0) (face q lies between nodes q and q + 1)
+        st.lo[c] = sh < 0 ? 0 : 1;
+        st.hi[c] = sh > 0 ? 3 : 2;
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
             const int i0 = q - 1, i1 = q - 1 - (int)sh;
@@ -154,27 +159,43 @@ __device__ __forceinline__ bool deposit_stencil(const DepositArgs &a, int64_t p,
 
 // The face currents of one particle, handed to add(comp, i, j, k, value) with
 // window-relative node offsets (0..4); J_c is the running sum of
-// -Q d_c/dt W_c along c.
+// -Q d_c/dt W_c along c.  Only the particle's support is visited: along each
+// axis the start and end weights are nonzero on the 4 window nodes from
+// lo = 1 + min(shift, 0) on, and the running sum along c vanishes before the
+// first and from the last of them on (the changes sum to zero; the rounding
+// residue of that sum is dropped), so 3 x 4 x 4 x 3 static slots cover it.
 template <typename Add>
 __device__ __forceinline__ void deposit_faces(const DepStencil &st, const double dd[3], double dt, Add add) {
+    double S[3][4], Dl[3][4];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const bool s1 = st.lo[d] != 0;       // support starts at window node 1
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            S[d][m] = s1 ? st.S0[d][m + 1] : st.S0[d][m];
+            Dl[d][m] = s1 ? st.D[d][m + 1] : st.D[d][m];
+        }
+    }
 #pragma unroll
     for (int comp = 0; comp < 3; ++comp) {
         const int a1 = (comp + 1) % 3, a2 = (comp + 2) % 3;
         const double f = -st.Q * dd[comp] / dt;
-        for (int b = 0; b < 5; ++b)
-            for (int c = 0; c < 5; ++c) {
-                const double t = st.S0[a1][b] * st.S0[a2][c] + 0.5 * st.D[a1][b] * st.S0[a2][c] +
-                                 0.5 * st.S0[a1][b] * st.D[a2][c] + st.D[a1][b] * st.D[a2][c] / 3.0;
-                if (t == 0.0) continue;
+        const int nf = st.hi[comp] - st.lo[comp] + 1;      // faces carrying current: 2 or 3
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double t = S[a1][b] * S[a2][c] + 0.5 * Dl[a1][b] * S[a2][c] + 0.5 * S[a1][b] * Dl[a2][c]
+                                 + Dl[a1][b] * Dl[a2][c] / 3.0;
                 double acc = 0.0;
                 int off[3];
-                off[a1] = b;
-                off[a2] = c;
+                off[a1] = st.lo[a1] + b;
+                off[a2] = st.lo[a2] + c;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    acc += f * st.D[comp][q] * t;
-                    if (acc == 0.0) continue;
-                    off[comp] = q;
+                for (int q = 0; q < 3; ++q) {
+                    acc += f * Dl[comp][q] * t;
+                    if (q >= nf || acc == 0.0) continue;
+                    off[comp] = st.lo[comp] + q;
                     add(comp, off[0], off[1], off[2], acc);
                 }
             }
