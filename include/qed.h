@@ -159,7 +159,25 @@ typedef struct {
     const float *grid;        /* [device] 6*nx*ny*nz floats                     */
     int64_t nx, ny, nz;
     double dx, dy, dz, x0, y0, z0;
+    const float *bound;       /* [device] or NULL: field bounds from qed_field_bound  */
+    int64_t bound_block;      /* cells per block edge of that table                */
 } qed_field;
+
+/* Bounds of a Yee field for the photon step.  For each block of block^3
+ * cells (b = (bi nby + bj) nbz + bk, nb* = ceil(n* / block)) writes
+ * bound[2 b] and bound[2 b + 1]: sqrt of the sum over the E (then B)
+ * components of the largest |component| over the nodes the gather of a
+ * particle in the block can touch (the block's nodes and two more on every
+ * side), scaled up by 1 + 2^-20.  A particle outside the grid belongs to the
+ * block of its nearest cell.  With f->bound = bound and f->bound_block =
+ * block, the photon step skips the field gather of a wave whose photons all
+ * have |k| (|E|_b + |B|_b) / E_s (1.01) below the pair table's chi_min: the
+ * quantum parameter of Eq. 1 is at most |k| (|E| + |B|) / E_s, so their pair
+ * rate is exactly zero with or without the gather and the results do not
+ * change.  The table describes the grid at the time of the call; recompute
+ * it whenever the grid changes.  bound [device] holds 2 nbx nby nbz floats;
+ * 1 <= block <= 64; QED_ERR_ARG for a non-Yee field or a bad block. */
+qed_status qed_field_bound(const qed_field *f, int32_t block, float *bound, void *stream);
 
 /* Separable pulse onto the Yee grid: grid[c][i][j][k] =
  * (float)((a0 * tperp[c][j*nz+k]) * tpar[c][i]), tperp [device] 6*ny*nz,
@@ -218,7 +236,8 @@ enum { QED_VAR_SOKOLOV_G = 1, QED_VAR_PAIR_MOMENTUM = 2 };
  * count: 0 emissions, 1 pushed, 2 recorded, 3 tallied only, 4 below
  *   threshold, 5 max_events cap hit, 6 chi above table, 7 Sokolov steps,
  *   8 Monte Carlo steps, 9 pairs, 10 photon steps, 11 non-finite, 12 lost
- *   to capacity.
+ *   to capacity, 13 photon steps that skipped the field gather (field
+ *   bounds, see qed_field_bound).
  * ------------------------------------------------------------------------ */
 #define QED_N_ENERGY 8
 #define QED_N_COUNT 16

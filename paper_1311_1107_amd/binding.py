@@ -23,7 +23,7 @@ QED_N_ENERGY, QED_N_COUNT = 8, 16
 
 ENERGY_NAMES = ["work", "erad", "epush", "erec", "edrop", "esub", "epair", "_e7"]
 COUNT_NAMES = ["emit", "push", "rec", "drop", "sub", "cap", "range", "sokolov", "mc",
-               "pair", "phstep", "nan", "overflow", "_c13", "_c14", "_c15"]
+               "pair", "phstep", "nan", "overflow", "nogather", "_c14", "_c15"]
 
 
 class QedError(RuntimeError):
@@ -58,7 +58,8 @@ class qed_field(C.Structure):
                 ("a0", C.c_double), ("n_periods", C.c_double), ("grid", _vp),
                 ("nx", C.c_int64), ("ny", C.c_int64), ("nz", C.c_int64),
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
-                ("x0", C.c_double), ("y0", C.c_double), ("z0", C.c_double)]
+                ("x0", C.c_double), ("y0", C.c_double), ("z0", C.c_double),
+                ("bound", _vp), ("bound_block", C.c_int64)]
 
 
 QED_VAR_SOKOLOV_G, QED_VAR_PAIR_MOMENTUM = 1, 2
@@ -129,6 +130,7 @@ _SIGS = {
     "qed_sorter_create": ([C.c_int64, _P(_vp)], C.c_int32),
     "qed_sorter_free": ([_vp], None),
     "qed_sort_by_cell": ([_vp, _vp, _P(qed_species), _P(qed_species), _P(qed_field), _vp], C.c_int32),
+    "qed_field_bound": ([_P(qed_field), C.c_int32, _vp, _vp], C.c_int32),
     "qed_yee_advance": ([_vp, _vp, _P(qed_field), C.c_double, _vp], C.c_int32),
     "qed_deposit_current": ([_P(qed_species), _vp, _vp, _vp, _vp, C.c_double, C.c_double, C.c_double, _P(qed_field),
                              _vp, _vp, _vp], C.c_int32),
@@ -308,6 +310,10 @@ def qed_sorter_free(handle):
 
 def qed_sort_by_cell(sorter, ws, src, dst, grid_field, stream=None):
     _check(lib().qed_sort_by_cell(sorter, ws, C.byref(src), C.byref(dst), C.byref(grid_field), _stream(stream)))
+
+
+def qed_field_bound(field, block, bound_ptr, stream=None):
+    _check(lib().qed_field_bound(C.byref(field), int(block), C.c_void_p(bound_ptr), _stream(stream)))
 
 
 def qed_yee_advance(grid_ptr, J_ptr, geometry, dt, stream=None):

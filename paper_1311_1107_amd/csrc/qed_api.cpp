@@ -335,6 +335,13 @@ qed_status field_dev(const qed_field *f, int prec, qed::FieldDev &d, int &fk) {
         d.grid = f->grid; d.nx = f->nx; d.ny = f->ny; d.nz = f->nz;
         d.inv_dx = 1.0 / f->dx; d.inv_dy = 1.0 / f->dy; d.inv_dz = 1.0 / f->dz;
         d.x0 = f->x0; d.y0 = f->y0; d.z0 = f->z0;
+        if (f->bound) {
+            if (f->bound_block < 1 || f->bound_block > 64)
+                return fail(QED_ERR_ARG, "field: bound_block must be in 1..64 with a bound table");
+            d.bound = f->bound;
+            d.bb = f->bound_block;
+            d.nbx = (f->nx + d.bb - 1) / d.bb; d.nby = (f->ny + d.bb - 1) / d.bb; d.nbz = (f->nz + d.bb - 1) / d.bb;
+        }
         fk = qed::FIELD_YEE;
     } else {
         return fail(QED_ERR_ARG, "field: unknown kind %d", f->kind);
@@ -719,6 +726,14 @@ qed_status qed_merge(qed_merger *mg, qed_workspace *ws, const qed_merge_spec *sp
     a.cnt = mg->cnt;
     a.ws = ws->dev;
     HIP_TRY(qed::launch_merge(a, src->prec, (mbits + 3) / 4, (cbits + 3) / 4, ws->n_cu, (hipStream_t)stream));
+    return QED_OK;
+}
+
+qed_status qed_field_bound(const qed_field *f, int32_t block, float *bound, void *stream) {
+    if (!f || f->kind != QED_FIELD_YEE || !f->grid || f->nx < 1 || f->ny < 1 || f->nz < 1)
+        return fail(QED_ERR_ARG, "qed_field_bound: needs a Yee field with a grid");
+    if (block < 1 || block > 64 || !bound) return fail(QED_ERR_ARG, "qed_field_bound: block in 1..64 and a table");
+    HIP_TRY(qed::launch_field_bound(f->grid, f->nx, f->ny, f->nz, block, bound, (hipStream_t)stream));
     return QED_OK;
 }
 

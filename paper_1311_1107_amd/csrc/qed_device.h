@@ -20,7 +20,7 @@ enum { RAD_NONE = 0, RAD_SOKOLOV = 1, RAD_MC = 2, RAD_HYBRID = 3 };
 
 // count tallies (integer, accumulated per block across tiles)
 enum { C_EMIT = 0, C_PUSH, C_REC, C_DROP, C_SUB, C_CAP, C_RANGE, C_SOKOLOV, C_MC,
-       C_PAIR, C_PHSTEP, C_NAN, C_LOST, N_COUNT_USED };
+       C_PAIR, C_PHSTEP, C_NAN, C_LOST, C_NOGATHER, N_COUNT_USED };
 // energy tallies (FP64, per tile slot)
 enum { E_WORK = 0, E_RAD, E_PUSH, E_REC, E_DROP, E_SUB, E_PAIR, N_ENERGY_USED };
 

@@ -30,6 +30,8 @@ struct FieldDev {
     const float *grid;
     int64_t nx, ny, nz;
     double inv_dx, inv_dy, inv_dz, x0, y0, z0;
+    const float *bound;              // Yee: per-block |E|, |B| bounds (photon-step cull) or NULL
+    int64_t bb, nbx, nby, nbz;       // cells per block edge, blocks per axis
     int n_bunches;                   // bunched plane waves
     const int64_t *offsets;
     const double *a0s, *nper;
@@ -137,6 +139,8 @@ hipError_t launch_pair_append(const PairArgs &a, int prec, int fk, dim3 grid, di
 hipError_t launch_compact(const CompactArgs &a, int prec, dim3 grid, dim3 block, hipStream_t s);
 hipError_t launch_init_tau(const uint64_t *uid, double *tau, const int64_t *count, uint64_t seed,
                            int n_blocks, hipStream_t s);
+hipError_t launch_field_bound(const float *grid, int64_t nx, int64_t ny, int64_t nz, int64_t block, float *bound,
+                              hipStream_t s);
 hipError_t launch_yee_fill(float *grid, int64_t nx, int64_t ny, int64_t nz, double a0,
                            const double *tperp, const double *tpar, int n_blocks, hipStream_t s);
 hipError_t launch_step_advance(int64_t *d_step, hipStream_t s);

@@ -845,7 +845,32 @@ k_pair_create(PairArgs a) {
         }
         const bool live = i < n && tau != HUGE_VAL;
         R E[3], B[3];
-        if constexpr (FK == FIELD_YEE) yee_gather_wave<R>(a.f, live, x, y, z, E, B, s_box + (tid / kWave) * kWBFloats);
+        if constexpr (FK == FIELD_YEE) {
+            // a wave whose photons all have a pair rate of exactly zero whatever the
+            // field (chi below the table, from the block bounds) skips the gather
+            bool low = true;
+            if (a.f.bound && live) {
+                const double gc[3] = {((double)x - a.f.x0) * a.f.inv_dx, ((double)y - a.f.y0) * a.f.inv_dy,
+                                      ((double)z - a.f.z0) * a.f.inv_dz};
+                const int64_t nc[3] = {a.f.nx, a.f.ny, a.f.nz};
+                int64_t bix[3];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const double cl = gc[d] > 0.0 ? (gc[d] < (double)(nc[d] - 1) ? gc[d] : (double)(nc[d] - 1)) : 0.0;
+                    bix[d] = (int64_t)cl / a.f.bb;        // NaN positions land in block 0: the field is ignored anyway
+                }
+                const float *bd = a.f.bound + 2 * ((bix[0] * a.f.nby + bix[1]) * a.f.nbz + bix[2]);
+                const double kd = sqrt((double)kx * (double)kx + (double)ky * (double)ky + (double)kz * (double)kz);
+                low = kd * ((double)bd[0] + (double)bd[1]) * a.c.es_inv * 1.01 < tb.p_chi_min;
+            }
+            if (a.f.bound && __ballot(!low) == 0ull) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) { E[d] = R(0); B[d] = R(0); }
+                if (live) cnt[C_NOGATHER]++;
+            } else {
+                yee_gather_wave<R>(a.f, live, x, y, z, E, B, s_box + (tid / kWave) * kWBFloats);
+            }
+        }
         if (live) {
             if constexpr (FK != FIELD_YEE) field_at<R, FK>(a.f, t, x, y, z, a.f.a0, a.f.Phi, E, B);
             const R kk = Math<R>::sqrt_(kx * kx + ky * ky + kz * kz);
@@ -1060,6 +1085,45 @@ __global__ void k_yee_fill(float *grid, int64_t nx, int64_t ny, int64_t nz, doub
         const int64_t i = r / plane, jk = r - i * plane;
         grid[idx] = (float)((a0 * tperp[c * plane + jk]) * tpar[c * nx + i]);
     }
+}
+
+// Per-block field bounds: thread (block, E or B) takes the largest |component|
+// of each of its three components over the block's nodes and two more on
+// every side, and stores sqrt of the sum of their squares (rounded up).
+__global__ void __launch_bounds__(256)
+k_field_bound(const float *grid, int64_t nx, int64_t ny, int64_t nz, int64_t bb, int64_t nbx, int64_t nby,
+              int64_t nbz, float *bound) {
+    const int64_t nb = nbx * nby * nbz, ncell = nx * ny * nz;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < 2 * nb; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = t >> 1;
+        const int fb = (int)(t & 1);
+        const int64_t bk = b % nbz, bj = (b / nbz) % nby, bi = b / (nbz * nby);
+        const int64_t i0 = bi * bb - 2 < 0 ? 0 : bi * bb - 2, i1 = bi * bb + bb + 2 > nx ? nx : bi * bb + bb + 2;
+        const int64_t j0 = bj * bb - 2 < 0 ? 0 : bj * bb - 2, j1 = bj * bb + bb + 2 > ny ? ny : bj * bb + bb + 2;
+        const int64_t k0 = bk * bb - 2 < 0 ? 0 : bk * bb - 2, k1 = bk * bb + bb + 2 > nz ? nz : bk * bb + bb + 2;
+        double s2 = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            const float *g = grid + (int64_t)(3 * fb + c) * ncell;
+            float m = 0.0f;
+            for (int64_t i = i0; i < i1; ++i)
+                for (int64_t j = j0; j < j1; ++j) {
+                    const float *r = g + (i * ny + j) * nz;
+                    for (int64_t k = k0; k < k1; ++k) m = fmaxf(m, fabsf(r[k]));
+                }
+            s2 += (double)m * (double)m;
+        }
+        // NaN anywhere in the region leaves the bound infinite (no cull)
+        bound[t] = isfinite(s2) ? (float)(sqrt(s2) * (1.0 + 0x1p-20)) : HUGE_VALF;
+    }
+}
+
+hipError_t launch_field_bound(const float *grid, int64_t nx, int64_t ny, int64_t nz, int64_t block, float *bound,
+                              hipStream_t s) {
+    const int64_t nbx = (nx + block - 1) / block, nby = (ny + block - 1) / block, nbz = (nz + block - 1) / block;
+    const int64_t n = 2 * nbx * nby * nbz;
+    const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65535));
+    hipLaunchKernelGGL(k_field_bound, dim3(g), dim3(256), 0, s, grid, nx, ny, nz, block, nbx, nby, nbz, bound);
+    return hipGetLastError();
 }
 
 __global__ void k_step_advance(int64_t *d_step) {

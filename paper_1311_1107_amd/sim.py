@@ -68,7 +68,8 @@ class Run:
                  chi_switch: float = 1e-3, gamma_photon_min: float = 2.0, max_events: int = 4,
                  sched: B.qed_schedule | None = None, compact_every: int = 16, sort_every: int = 0,
                  deterministic_tally: bool = True, variants: int = 0, merge: MergePolicy | None = None,
-                 coupled: bool = False, particles_per_weight: float = 1.0, device: str = "cuda"):
+                 coupled: bool = False, particles_per_weight: float = 1.0, field_bound_block: int = 0,
+                 device: str = "cuda"):
         self.wl = wl
         self.prec = prec
         self.units = B.qed_units_init(LAMBDA_M)
@@ -112,6 +113,14 @@ class Run:
             self.tperp = torch.from_numpy(np.ascontiguousarray(f.tperp)).to(device)
             self.tpar = torch.from_numpy(np.ascontiguousarray(f.tpar)).to(device)
             self.field = D.yee(self.grid, f.shape, f.spacing, f.origin)
+            # per-block field bounds let the photon step skip the gather of waves in which no
+            # pair can form (opt-in: on the Yee workload too few waves qualify to pay for it)
+            self.bound_block = int(field_bound_block)
+            if self.bound_block:
+                nb = [(n + self.bound_block - 1) // self.bound_block for n in f.shape]
+                self.bound = torch.zeros(2 * nb[0] * nb[1] * nb[2], dtype=torch.float32, device=device)
+                self.field.bound = self.bound.data_ptr()
+                self.field.bound_block = self.bound_block
         else:
             raise TypeError("unknown field description")
         # cell ordering (Yee field only): a second buffer per species, swapped after each sort
@@ -175,6 +184,12 @@ class Run:
             nx, ny, nz = f.shape
             tp = self.tpar[n].reshape(-1)
             B.qed_yee_fill_separable(self.grid.data_ptr(), nx, ny, nz, f.a0, self.tperp.data_ptr(), tp.data_ptr())
+            self.field_bound()
+
+    def field_bound(self):
+        """Recompute the per-block field bounds (after every change of the grid)."""
+        if self.grid is not None and self.bound_block:
+            B.qed_field_bound(self.field, self.bound_block, self.bound.data_ptr())
 
     def step(self, n: int, timed=None):
         """Step n.  `timed(kind, fn)`, if given, wraps every launch (for timing)."""
@@ -206,7 +221,8 @@ class Run:
             if self.compact_every and (n + 1) % self.compact_every == 0 and not sorting:
                 run("compact", self.compact)
         if self.coupled:
-            run("field", lambda: B.qed_yee_advance(self.grid.data_ptr(), self.J.data_ptr(), self.field, self.wl.dt))
+            run("field", lambda: (B.qed_yee_advance(self.grid.data_ptr(), self.J.data_ptr(), self.field, self.wl.dt),
+                                  self.field_bound()))
         if sorting:
             run("sort", self.sort)
 

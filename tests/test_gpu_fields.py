@@ -211,3 +211,84 @@ def test_coupled_run_keeps_gauss_law():
     assert t["N_emit"] > 100 and int(run.skipped.item()) == 0
     assert r1 > 1e-3 * d1                 # the charges are not negligible next to the field
     assert np.max(np.abs(g1 - g0)) <= 1e-4 * max(r1, d1)
+
+
+def test_field_bound_table():
+    """qed_field_bound: per 4^3-cell block, sqrt(sum over components of the
+    largest |component|^2) over the block's nodes and two more each side,
+    never below the exact value."""
+    _need_gpu()
+    r = np.random.default_rng(5)
+    shape, bb = (19, 10, 13), 4
+    g = r.normal(size=(6,) + shape).astype(np.float32)
+    g[:, 5:9, 2:6, :] *= 50.0
+    gd = torch.from_numpy(g.copy()).cuda()
+    f = D.yee(gd, shape, (0.5, 0.5, 0.5), (0.0, 0.0, 0.0))
+    nb = [(n + bb - 1) // bb for n in shape]
+    bound = torch.zeros(2 * int(np.prod(nb)), dtype=torch.float32, device="cuda")
+    B.qed_field_bound(f, bb, bound.data_ptr())
+    torch.cuda.synchronize()
+    got = bound.cpu().numpy().reshape(nb + [2])
+    for bi in range(nb[0]):
+        for bj in range(nb[1]):
+            for bk in range(nb[2]):
+                sl = tuple(slice(max(0, b * bb - 2), min(n, b * bb + bb + 2)) for b, n in zip((bi, bj, bk), shape))
+                for fb in range(2):
+                    m = [np.max(np.abs(g[3 * fb + c][sl])).astype(np.float64) for c in range(3)]
+                    want = np.sqrt(sum(v * v for v in m))
+                    assert want <= got[bi, bj, bk, fb] <= want * (1 + 1e-5)
+    with pytest.raises(B.QedError):
+        B.qed_field_bound(f, 0, bound.data_ptr())
+
+
+def test_photon_step_cull_changes_nothing():
+    """One photon step on the Yee grid with and without the per-block field
+    bounds, from identical state: photons spread over a box whose x < L/2
+    half holds no field (there every wave skips the gather) and whose other
+    half holds the a0 = 800 pulse (pairs form).  Photons, pairs, ids and
+    tallies are bit-identical; only the count of skipped gathers differs."""
+    _need_gpu()
+    from paper_1311_1107_amd import sim as S
+    from paper_1311_1107_amd import workloads as W
+    print("case: photon-step cull on/off, one step of 200k photons", flush=True)
+    r = np.random.default_rng(17)
+    n = 200_000
+    res = []
+    for bb in (2, 0):
+        wl = W.yee_beam(n=2000, steps=260, seed=12, shape=(64, 32, 32), a0=800.0, gamma_median=4000.0,
+                        x_range_lambda=(3.0, 5.0), r_max_lambda=1.0, x_center0=12.0)
+        run = S.Run(wl, photon_capacity=n, record_capacity=1000, pair_capacity=4 * n, field_bound_block=bb)
+        f = wl.field
+        nx, ny, nz = f.shape
+        run.fill_field(120)
+        run.grid.view(6, nx, ny, nz)[:, : nx // 2] = 0.0
+        run.field_bound()
+        rr = np.random.default_rng(17)
+        lo, ext = np.array(f.origin), np.array(f.shape) * np.array(f.spacing)
+        pos = lo + rr.uniform(0.05, 0.95, (n, 3)) * ext
+        cell = np.floor((pos - lo) / np.array(f.spacing)).astype(np.int64)
+        order = np.lexsort((cell[:, 2], cell[:, 1], cell[:, 0]))
+        pos = pos[order]
+        kk = 10.0 ** rr.uniform(0.5, 3.5, n)
+        d = np.array([-1.0, 0.0, 0.0]) + 0.05 * rr.normal(size=(n, 3))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        k = d * kk[:, None]
+        run.ph.upload({"x": pos[:, 0], "y": pos[:, 1], "z": pos[:, 2], "ux": k[:, 0], "uy": k[:, 1], "uz": k[:, 2],
+                       "w": np.ones(n), "chi": np.zeros(n), "tau": rr.exponential(1.0, n) * 0.02,
+                       "uid": np.arange(10 ** 6, 10 ** 6 + n, dtype=np.uint64)})
+        run.uid_next.fill_(10 ** 7)
+        st = D.step(120 * wl.dt, wl.dt, wl.seed, **run.step_kw)
+        run.ph_snap.copy_(run.ph.count)
+        B.qed_pair_create(run.tables.h, run.ws.h, run.units, run.ph_step, run.field, run.el.struct(),
+                          run.po.struct(), run.tally.s, st, run.uid_next.data_ptr(), run.sched)
+        torch.cuda.synchronize()
+        run.ws.status()
+        res.append({"ph": run.ph.download(), "el": run.el.download(), "po": run.po.download(),
+                    "tally": run.tally.reduce(), "uid": int(run.uid_next.item())})
+    a, b = res
+    assert a["tally"].pop("N_nogather") > n // 4 and b["tally"].pop("N_nogather") == 0
+    assert a["tally"] == b["tally"] and a["uid"] == b["uid"]
+    assert a["tally"]["N_pair"] > 100
+    for sp in ("ph", "el", "po"):
+        for key in a[sp]:
+            assert np.array_equal(a[sp][key], b[sp][key]), (sp, key)
