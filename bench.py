@@ -43,6 +43,9 @@ def parse():
     p.add_argument("--no-merge", action="store_true",
                    help="cascade: stop at the first full buffer instead of merging super-particles")
     p.add_argument("--sort-every", type=int, default=16, help="cell-order the particles every k steps (Yee)")
+    p.add_argument("--bound-block", type=int, default=0,
+                   help="Yee: per-block field bounds (block edge in cells) so that photon waves with no possible "
+                        "pair skip the gather; 0 = off")
     p.add_argument("--batched-steps", type=int, default=1000,
                    help="steps of the FP32-batched vs FP64-plain comparison (0 skips it)")
     return p.parse_args()
@@ -453,7 +456,7 @@ def main():
     n0 = len(wl.electrons["x"])
 
     run = S.Run(wl, prec=prec, compact_every=args.compact_every, sort_every=args.sort_every, coupled=coupled,
-                particles_per_weight=1000.0, **caps)
+                particles_per_weight=1000.0, field_bound_block=args.bound_block, **caps)
     init = {k: v.clone() for k, v in run.el.a.items()}
     init_el = run.el
 
@@ -541,16 +544,18 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "electrons": n0, "grid": list(wl.field.shape) if hasattr(wl.field, "shape") else None,
                    "steps_timed": K, "dt": wl.dt, "compact_every": args.compact_every,
-                   "sort_every": args.sort_every},
+                   "sort_every": args.sort_every, "bound_block": args.bound_block},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      # counters were taken on the default command: 1e7 electrons, 2000 steps, sort/compact every 16
                      "traffic": (measured_traffic() if dom.startswith("qed_pair_create") and K == 2000 and n0 == 10_000_000
-                                 and args.sort_every == 16 and args.compact_every == 16 and not coupled else None),
+                                 and args.sort_every == 16 and args.compact_every == 16 and not coupled
+                                 and args.bound_block == 0 else None),
                      "bytes_per_launch": dom_bytes / max(dom_n, 1), "avg_launch_ms": dom_ms / max(dom_n, 1)},
         "detail": {"lepton_steps": lepton_steps, "photon_steps": photon_steps, "kernel_ms": kernel_ms,
                    "launches": n_launch, "final_counts": counts, "emissions": tal["N_emit"], "pairs": tal["N_pair"],
-                   "status": int(rc), "lepton_bytes": lep_bytes, "photon_bytes": ph_bytes},
+                   "status": int(rc), "lepton_bytes": lep_bytes, "photon_bytes": ph_bytes,
+                   "photon_steps_without_gather": tal.get("N_nogather", 0)},
     }
     if coupled:
         out["detail"]["deposit_skipped"] = int(run.skipped.item())

@@ -371,6 +371,14 @@ qed_status qed_sorter_create(int64_t max_particles, qed_sorter **out);
 void qed_sorter_free(qed_sorter *s);
 qed_status qed_sort_by_cell(qed_sorter *s, qed_workspace *ws, qed_species *src, qed_species *dst,
                             const qed_field *grid, void *stream);
+/* The same order with each cell's particles grouped by energy band:
+ * key = cell key * bands + b, b = min(bands - 1, floor(log2 |u|^2 / 6)) (0 for
+ * |u| < 8), taken from the exponent of |u|^2 = fma(uz, uz, fma(uy, uy, ux ux))
+ * in FP64: band edges at |u| = 8, 64, 512, ...  bands is 1 (qed_sort_by_cell),
+ * 2, 4 or 8.  Photons of similar energy then share waves, which lets the
+ * photon step skip whole waves' gathers (qed_field_bound). */
+qed_status qed_sort_by_cell_bands(qed_sorter *s, qed_workspace *ws, qed_species *src, qed_species *dst,
+                                  const qed_field *grid, int32_t bands, void *stream);
 
 /* ------------------------------------------------------------------------ *
  * Log-binned energy spectrum of a species (the photon and lepton spectra the

@@ -150,6 +150,8 @@ def lib():
                                      C.POINTER(Step), _u64p, _dp, C.POINTER(C.c_int64)]
         L.or_pair_create.restype = C.c_int
         L.or_sort_by_cell.argtypes = [C.POINTER(Species), C.c_int64, C.c_int64, C.c_int64, d, d, d, d, d, d]
+        L.or_sort_by_cell_bands.argtypes = [C.POINTER(Species), C.c_int64, C.c_int64, C.c_int64, d, d, d, d, d, d,
+                                            C.c_int32]
         L.or_yee_advance.argtypes = [_fp, _fp, C.c_int64, C.c_int64, C.c_int64, d, d, d, d]
         L.or_deposit_current.argtypes = [C.POINTER(Species), _dp, _dp, _dp, C.c_int64, d, d, d, C.c_int64, C.c_int64,
                                          C.c_int64, d, d, d, d, d, d, _dp]
@@ -462,10 +464,10 @@ def pair_create(tabs: BoundTables, lambda_m, ph: dict, field: Field, elec: dict,
     return rc
 
 
-def sort_by_cell(s: dict, shape, spacing, origin):
+def sort_by_cell(s: dict, shape, spacing, origin, bands: int = 1):
     st = _species_struct(s)
-    lib().or_sort_by_cell(C.byref(st), *[int(v) for v in shape], *[float(v) for v in spacing],
-                          *[float(v) for v in origin])
+    lib().or_sort_by_cell_bands(C.byref(st), *[int(v) for v in shape], *[float(v) for v in spacing],
+                                *[float(v) for v in origin], int(bands))
 
 
 def yee_advance(grid6: np.ndarray, J3: np.ndarray | None, shape, spacing, dt: float, steps: int = 1):

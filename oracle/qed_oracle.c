@@ -992,6 +992,22 @@ static int cmp_keyidx(const void *a, const void *b)
 void or_sort_by_cell(or_species *s, int64_t nx, int64_t ny, int64_t nz, double dx, double dy, double dz,
                      double x0, double y0, double z0)
 {
+    or_sort_by_cell_bands(s, nx, ny, nz, dx, dy, dz, x0, y0, z0, 1);
+}
+
+/* energy band of |u|: floor(log2 |u|^2 / 6) clamped to [0, bands), from the exponent of |u|^2 */
+static uint64_t energy_band(double ux, double uy, double uz, int32_t bands)
+{
+    double u2 = fma(uz, uz, fma(uy, uy, ux * ux));
+    int e = 0;
+    if (u2 > 0.0 && isfinite(u2)) frexp(u2, &e);
+    int b = (e - 1) >= 0 ? (e - 1) / 6 : 0;
+    return (uint64_t)(b < bands - 1 ? b : bands - 1);
+}
+
+void or_sort_by_cell_bands(or_species *s, int64_t nx, int64_t ny, int64_t nz, double dx, double dy, double dz,
+                           double x0, double y0, double z0, int32_t bands)
+{
     int64_t n = s->n;
     if (n < 2) return;
     double idx_ = 1.0 / dx, idy = 1.0 / dy, idz = 1.0 / dz;
@@ -1005,6 +1021,7 @@ void or_sort_by_cell(or_species *s, int64_t nx, int64_t ny, int64_t nz, double d
             if (fi < (double)nx && fj < (double)ny && fk < (double)nz)
                 key = (uint64_t)((((int64_t)fi * ny) + (int64_t)fj) * nz + (int64_t)fk);
         }
+        if (bands > 1) key = key * (uint64_t)bands + energy_band(s->ux[i], s->uy[i], s->uz[i], bands);
         ki[i].key = key;
         ki[i].idx = i;
     }

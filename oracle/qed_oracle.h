@@ -196,6 +196,10 @@ int or_pair_create(const or_tables *tab, const or_units *u,
  * particles outside the grid last. */
 void or_sort_by_cell(or_species *s, int64_t nx, int64_t ny, int64_t nz, double dx, double dy, double dz,
                      double x0, double y0, double z0);
+/* The same with key = cell key * bands + energy band of |u|, the band
+ * floor(log2 |u|^2 / 6) clamped to [0, bands) (edges at |u| = 8, 64, 512). */
+void or_sort_by_cell_bands(or_species *s, int64_t nx, int64_t ny, int64_t nz, double dx, double dy, double dz,
+                           double x0, double y0, double z0, int32_t bands);
 
 /* Merging of super-particles (coalescence; the paper fixes only that energy
  * and momentum are kept).  Two-particle merge per group of (cell, energy bin,

@@ -130,6 +130,8 @@ _SIGS = {
     "qed_sorter_create": ([C.c_int64, _P(_vp)], C.c_int32),
     "qed_sorter_free": ([_vp], None),
     "qed_sort_by_cell": ([_vp, _vp, _P(qed_species), _P(qed_species), _P(qed_field), _vp], C.c_int32),
+    "qed_sort_by_cell_bands": ([_vp, _vp, _P(qed_species), _P(qed_species), _P(qed_field), C.c_int32, _vp],
+                               C.c_int32),
     "qed_field_bound": ([_P(qed_field), C.c_int32, _vp, _vp], C.c_int32),
     "qed_yee_advance": ([_vp, _vp, _P(qed_field), C.c_double, _vp], C.c_int32),
     "qed_deposit_current": ([_P(qed_species), _vp, _vp, _vp, _vp, C.c_double, C.c_double, C.c_double, _P(qed_field),
@@ -308,8 +310,12 @@ def qed_sorter_free(handle):
     lib().qed_sorter_free(handle)
 
 
-def qed_sort_by_cell(sorter, ws, src, dst, grid_field, stream=None):
-    _check(lib().qed_sort_by_cell(sorter, ws, C.byref(src), C.byref(dst), C.byref(grid_field), _stream(stream)))
+def qed_sort_by_cell(sorter, ws, src, dst, grid_field, stream=None, bands=1):
+    if bands == 1:
+        _check(lib().qed_sort_by_cell(sorter, ws, C.byref(src), C.byref(dst), C.byref(grid_field), _stream(stream)))
+    else:
+        _check(lib().qed_sort_by_cell_bands(sorter, ws, C.byref(src), C.byref(dst), C.byref(grid_field), int(bands),
+                                            _stream(stream)))
 
 
 def qed_field_bound(field, block, bound_ptr, stream=None):

@@ -612,6 +612,13 @@ void qed_sorter_free(qed_sorter *s) {
 
 qed_status qed_sort_by_cell(qed_sorter *so, qed_workspace *ws, qed_species *src, qed_species *dst,
                             const qed_field *grid, void *stream) {
+    return qed_sort_by_cell_bands(so, ws, src, dst, grid, 1, stream);
+}
+
+qed_status qed_sort_by_cell_bands(qed_sorter *so, qed_workspace *ws, qed_species *src, qed_species *dst,
+                                  const qed_field *grid, int32_t bands, void *stream) {
+    if (bands != 1 && bands != 2 && bands != 4 && bands != 8)
+        return fail(QED_ERR_ARG, "qed_sort_by_cell: bands must be 1, 2, 4 or 8");
     if (!so || !ws || !src || !dst || !grid) return fail(QED_ERR_ARG, "qed_sort_by_cell: null argument");
     if (grid->kind != QED_FIELD_YEE || grid->nx < 1 || grid->ny < 1 || grid->nz < 1 || !(grid->dx > 0) ||
         !(grid->dy > 0) || !(grid->dz > 0))
@@ -629,10 +636,14 @@ qed_status qed_sort_by_cell(qed_sorter *so, qed_workspace *ws, qed_species *src,
     if ((src->chi == nullptr) != (dst->chi == nullptr)) return fail(QED_ERR_ARG, "qed_sort_by_cell: chi arrays differ");
     if (src->x == dst->x || src->tau == dst->tau || src->d_count == dst->d_count)
         return fail(QED_ERR_ARG, "qed_sort_by_cell: src and dst must be distinct buffers");
+    // keys 0 .. (ncell + 1) bands - 1 (ncell: outside) < key_dead = 2^bits - 1
+    const int64_t top = (ncell + 1) * bands - 1;
+    if (top >= (int64_t)0xfffffffe) return fail(QED_ERR_ARG, "qed_sort_by_cell: too many cells for the bands");
     int bits = 1;
-    while (((int64_t)1 << bits) - 1 <= ncell) ++bits;      // keys 0..ncell (outside) < key_dead = 2^bits - 1
+    while (((int64_t)1 << bits) - 1 <= top) ++bits;
     a.key_out = (uint32_t)ncell;
     a.key_dead = (uint32_t)(((uint64_t)1 << bits) - 1);
+    a.bands = bands;
     const int passes = (bits + 3) / 4;
     a.x0 = grid->x0; a.y0 = grid->y0; a.z0 = grid->z0;
     a.inv_dx = 1.0 / grid->dx; a.inv_dy = 1.0 / grid->dy; a.inv_dz = 1.0 / grid->dz;

@@ -847,23 +847,50 @@ k_pair_create(PairArgs a) {
         R E[3], B[3];
         if constexpr (FK == FIELD_YEE) {
             // a wave whose photons all have a pair rate of exactly zero whatever the
-            // field (chi below the table, from the block bounds) skips the gather
-            bool low = true;
-            if (a.f.bound && live) {
-                const double gc[3] = {((double)x - a.f.x0) * a.f.inv_dx, ((double)y - a.f.y0) * a.f.inv_dy,
-                                      ((double)z - a.f.z0) * a.f.inv_dz};
-                const int64_t nc[3] = {a.f.nx, a.f.ny, a.f.nz};
-                int64_t bix[3];
+            // field skips the gather: chi_gamma <= |k| (|E| + |B|) / E_s, bounded over
+            // the blocks of cells the wave spans with the largest |k| of the wave
+            bool cull = false;
+            if (a.f.bound) {
+                if (__ballot(live) == 0ull) {
+                    cull = true;                                  // nothing to gather
+                } else {
+                    const double gc[3] = {((double)x - a.f.x0) * a.f.inv_dx, ((double)y - a.f.y0) * a.f.inv_dy,
+                                          ((double)z - a.f.z0) * a.f.inv_dz};
+                    const int64_t nc[3] = {a.f.nx, a.f.ny, a.f.nz};
+                    int blo[3], nbk[3];
+                    int64_t nblk = 1;
 #pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    const double cl = gc[d] > 0.0 ? (gc[d] < (double)(nc[d] - 1) ? gc[d] : (double)(nc[d] - 1)) : 0.0;
-                    bix[d] = (int64_t)cl / a.f.bb;        // NaN positions land in block 0: the field is ignored anyway
+                    for (int d = 0; d < 3; ++d) {
+                        // NaN positions land in cell 0: their pair rate is zero whatever the field
+                        const double cl =
+                            gc[d] > 0.0 ? (gc[d] < (double)(nc[d] - 1) ? gc[d] : (double)(nc[d] - 1)) : 0.0;
+                        const int b = (int)((int64_t)cl / a.f.bb);
+                        blo[d] = wave_min_i32(live ? b : INT_MAX);
+                        const int bhi = -wave_min_i32(live ? -b : INT_MAX);
+                        nbk[d] = bhi - blo[d] + 1;               // >= 1: some lane is live
+                        nblk *= nbk[d];
+                    }
+                    if (nblk <= kWave) {
+                        const double kd = live ? sqrt((double)kx * (double)kx + (double)ky * (double)ky +
+                                                      (double)kz * (double)kz) : 0.0;
+                        double kmax = kd, fmax_ = 0.0;
+                        const int lane = lane_id();
+                        if (lane < (int)nblk) {
+                            const int bk = blo[2] + lane % nbk[2], bj = blo[1] + (lane / nbk[2]) % nbk[1],
+                                      bi = blo[0] + lane / (nbk[2] * nbk[1]);
+                            const float *bd = a.f.bound + 2 * (((int64_t)bi * a.f.nby + bj) * a.f.nbz + bk);
+                            fmax_ = (double)bd[0] + (double)bd[1];
+                        }
+#pragma unroll
+                        for (int o = kWave / 2; o > 0; o >>= 1) {
+                            kmax = fmax(kmax, __shfl_xor(kmax, o, kWave));
+                            fmax_ = fmax(fmax_, __shfl_xor(fmax_, o, kWave));
+                        }
+                        cull = kmax * fmax_ * a.c.es_inv * 1.01 < tb.p_chi_min;
+                    }
                 }
-                const float *bd = a.f.bound + 2 * ((bix[0] * a.f.nby + bix[1]) * a.f.nbz + bix[2]);
-                const double kd = sqrt((double)kx * (double)kx + (double)ky * (double)ky + (double)kz * (double)kz);
-                low = kd * ((double)bd[0] + (double)bd[1]) * a.c.es_inv * 1.01 < tb.p_chi_min;
             }
-            if (a.f.bound && __ballot(!low) == 0ull) {
+            if (cull) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) { E[d] = R(0); B[d] = R(0); }
                 if (live) cnt[C_NOGATHER]++;

@@ -11,7 +11,8 @@ struct SortArgs {
     SpeciesDev src, dst;
     double x0, y0, z0, inv_dx, inv_dy, inv_dz;
     int64_t nx, ny, nz;
-    uint32_t key_out, key_dead;     // keys of particles outside the grid and of decayed photons
+    uint32_t key_out, key_dead;     // cell keys of particles outside the grid; key of decayed photons
+    int bands;                       // energy bands within a cell (1, 2, 4 or 8)
     uint32_t *key0, *key1, *idx0, *idx1, *idx_final;
     uint32_t *hist, *hoff;
     unsigned long long *live;

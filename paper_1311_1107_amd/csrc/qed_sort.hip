@@ -48,6 +48,17 @@ k_sort_keys(SortArgs a) {
                 if (fi < (double)a.nx && fj < (double)a.ny && fk < (double)a.nz)
                     key = (uint32_t)(((int64_t)fi * a.ny + (int64_t)fj) * a.nz + (int64_t)fk);
             }
+            if (a.bands > 1) {
+                // band of |u|: floor(log2 |u|^2 / 6) in [0, bands), from the exponent of |u|^2
+                const double ux = (double)((const R *)a.src.ux)[i], uy = (double)((const R *)a.src.uy)[i],
+                             uz = (double)((const R *)a.src.uz)[i];
+                const double u2 = fma(uz, uz, fma(uy, uy, ux * ux));
+                int e = 0;
+                if (u2 > 0.0 && isfinite(u2)) (void)frexp(u2, &e);
+                int b = (e - 1) >= 0 ? (e - 1) / 6 : 0;
+                b = b < a.bands - 1 ? b : a.bands - 1;
+                key = key * (uint32_t)a.bands + (uint32_t)b;
+            }
         }
         a.key0[i] = key;
         a.idx0[i] = (uint32_t)i;

@@ -158,8 +158,8 @@ class Sorter:
         self.max_particles = int(max_particles)
         self.h = B.qed_sorter_create(self.max_particles)
 
-    def sort(self, ws: "Workspace", src: Species, dst: Species, grid_field: B.qed_field):
-        B.qed_sort_by_cell(self.h, ws.h, src.struct(), dst.struct(), grid_field)
+    def sort(self, ws: "Workspace", src: Species, dst: Species, grid_field: B.qed_field, bands: int = 1):
+        B.qed_sort_by_cell(self.h, ws.h, src.struct(), dst.struct(), grid_field, bands=bands)
 
     def __del__(self):
         h, self.h = getattr(self, "h", None), None

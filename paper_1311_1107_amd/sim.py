@@ -166,13 +166,17 @@ class Run:
             self.ph_step.d_count = self.ph_snap.data_ptr()
 
     def sort(self):
-        """Stable cell order of every species (drops decayed photons)."""
+        """Stable cell order of every species (drops decayed photons); photons by (cell,
+        energy band) when the field bounds are on."""
         for name in ("el", "po", "ph"):
             src = getattr(self, name)
             if src is None:
                 continue
             dst = self.alt[name]
-            self.sorter.sort(self.ws, src, dst, self.field)
+            # with field bounds, photons of one cell are grouped by energy band so that whole
+            # waves can skip the gather
+            bands = 4 if (name == "ph" and self.bound_block) else 1
+            self.sorter.sort(self.ws, src, dst, self.field, bands=bands)
             setattr(self, name, dst)
             self.alt[name] = src
         self._photon_view()

@@ -282,6 +282,42 @@ def test_sort_by_cell_matches_oracle(prec, n):
     ws.status()
 
 
+@pytest.mark.parametrize("prec,bands", [(B.QED_F64, 4), (B.QED_F32, 8), (B.QED_F64, 2)])
+def test_sort_with_energy_bands_matches_oracle(prec, bands):
+    """qed_sort_by_cell_bands: the cell order with each cell's particles
+    grouped by energy band of |u| (momenta log-uniform over 1e-1 .. 3e4), a
+    bit-exact permutation against the oracle's banded sort."""
+    _need_gpu()
+    n = 3 * 4096 + 123
+    print(f"case: banded sort prec={prec} bands={bands} n={n}", flush=True)
+    p = _sort_particles(n, seed=77 + bands, prec=prec)
+    r = np.random.default_rng(bands)
+    mag = 10.0 ** r.uniform(-1.0, 4.5, n)
+    ft = np.float64 if prec == B.QED_F64 else np.float32
+    for k in ("ux", "uy", "uz"):
+        p[k] = (p[k] * mag).astype(ft).astype(np.float64)
+    cap = n + 5
+    src = D.Species(cap, prec)
+    src.upload(p)
+    dst = D.Species(cap, prec)
+    ws = D.Workspace(cap)
+    so = D.Sorter(cap)
+    grid = torch.zeros(6, dtype=torch.float32, device="cuda")
+    f = D.yee(grid, SORT_SHAPE, SORT_SPACING, SORT_ORIGIN)
+    so.sort(ws, src, dst, f, bands=bands)
+    torch.cuda.synchronize()
+    got = dst.download()
+    live = np.isfinite(p["tau"])
+    o = O.species_from({k: v[live] for k, v in p.items()})
+    O.sort_by_cell(o, SORT_SHAPE, SORT_SPACING, SORT_ORIGIN, bands=bands)
+    want = O.view(o)
+    assert len(got["x"]) == int(live.sum())
+    for k in ("uid", "n_ev", "tau", "x", "y", "z", "ux", "uy", "uz", "w", "chi"):
+        assert np.array_equal(got[k].astype(want[k].dtype), want[k]), k
+    with pytest.raises(B.QedError):
+        so.sort(ws, src, dst, f, bands=3)
+
+
 def test_sort_rejects_bad_arguments():
     _need_gpu()
     src = D.Species(100)

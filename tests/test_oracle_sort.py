@@ -75,3 +75,30 @@ def test_sort_is_idempotent():
     O.sort_by_cell(s, SHAPE, SPACING, ORIGIN)
     for k, v in O.view(s).items():
         assert np.array_equal(v, once[k]), k
+
+
+@pytest.mark.parametrize("bands", [2, 4, 8])
+def test_sort_with_energy_bands_matches_stable_argsort(bands):
+    """key = cell key * bands + band, band = floor(log2 |u|^2 / 6) clamped to
+    [0, bands) (edges at |u| = 8, 64, 512, ...); momenta drawn away from the
+    edges so that the band is the same in any rounding."""
+    n = 900
+    p = _particles(n, seed=40 + bands)
+    r = np.random.default_rng(bands)
+    mag = 10.0 ** r.uniform(-1.0, 4.5, n)
+    edges = 8.0 ** np.arange(1, 6)
+    near = np.min(np.abs(mag[:, None] / edges[None, :] - 1.0), axis=1) < 1e-6
+    mag[near] *= 1.01
+    d = r.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    for c, k in enumerate(("ux", "uy", "uz")):
+        p[k] = d[:, c] * mag
+    s = O.species_from(p)
+    O.sort_by_cell(s, SHAPE, SPACING, ORIGIN, bands=bands)
+    got = O.view(s)
+    band = np.array([min(bands - 1, max(0, int(np.floor(np.log2(m * m) / 6.0)))) for m in mag])
+    keys = _keys(p["x"], p["y"], p["z"]) * bands + band
+    order = np.argsort(keys, kind="stable")
+    for k in ("x", "ux", "uid", "n_ev", "tau"):
+        assert np.array_equal(got[k], p[k][order]), k
+    assert len(set(band.tolist())) == min(bands, 5)  # every band up to |u| ~ 3e4 is used
