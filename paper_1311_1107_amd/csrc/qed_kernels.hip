@@ -798,7 +798,7 @@ k_push_append(PushArgs a) {
 // the decay of marked photons, writes the pair and sets tau = +inf (removed
 // later by k_compact).
 // ------------------------------------------------------------------------
-template <typename R, int FK>
+template <typename R, int FK, bool kCull>
 __global__ void __launch_bounds__(256)
 k_pair_create(PairArgs a) {
     __shared__ R s_lp[kMaxChiNodes];
@@ -844,13 +844,15 @@ k_pair_create(PairArgs a) {
             }
         }
         const bool live = i < n && tau != HUGE_VAL;
+        // |k| = gamma_gamma, with one rounding order whatever the kernel variant
+        const R kk = Math<R>::sqrt_(fma(kz, kz, fma(ky, ky, kx * kx)));
         R E[3], B[3];
         if constexpr (FK == FIELD_YEE) {
             // a wave whose photons all have a pair rate of exactly zero whatever the
             // field skips the gather: chi_gamma <= |k| (|E| + |B|) / E_s, bounded over
             // the blocks of cells the wave spans with the largest |k| of the wave
             bool cull = false;
-            if (a.f.bound) {
+            if (kCull) {
                 if (__ballot(live) == 0ull) {
                     cull = true;                                  // nothing to gather
                 } else {
@@ -871,8 +873,7 @@ k_pair_create(PairArgs a) {
                         nblk *= nbk[d];
                     }
                     if (nblk <= kWave) {
-                        const double kd = live ? sqrt((double)kx * (double)kx + (double)ky * (double)ky +
-                                                      (double)kz * (double)kz) : 0.0;
+                        const double kd = live ? (double)kk : 0.0;
                         double kmax = kd, fmax_ = 0.0;
                         const int lane = lane_id();
                         if (lane < (int)nblk) {
@@ -900,7 +901,6 @@ k_pair_create(PairArgs a) {
         }
         if (live) {
             if constexpr (FK != FIELD_YEE) field_at<R, FK>(a.f, t, x, y, z, a.f.a0, a.f.Phi, E, B);
-            const R kk = Math<R>::sqrt_(kx * kx + ky * ky + kz * kz);
             const R chig = chi_of<R>(es_inv, kk, kx, ky, kz, E, B);
             cnt[C_PHSTEP]++;
             R Wp = R(0);
@@ -971,7 +971,7 @@ k_pair_append(PairArgs a) {
                 const R wgt = ((const R *)a.ph.w)[i];
                 R E[3], B[3];
                 field_at<R, FK>(a.f, t, x, y, z, a.f.a0, a.f.Phi, E, B);
-                const R kk = Math<R>::sqrt_(kx * kx + ky * ky + kz * kz);
+                const R kk = Math<R>::sqrt_(fma(kz, kz, fma(ky, ky, kx * kx)));     // as in the physics pass
                 const R chig = chi_of<R>(es_inv, kk, kx, ky, kz, E, B);
                 const R khx = kx / kk, khy = ky / kk, khz = kz / kk;
                 const U64x4 o = philox4x64_10(a.ph.uid[i], (uint64_t)a.ph.n_ev[i], (uint64_t)RNG_PAIR, 0ull,
@@ -1189,9 +1189,13 @@ hipError_t launch_push_append(const PushArgs &a, int prec, dim3 grid, dim3 block
 template <typename R>
 hipError_t launch_pair(const PairArgs &a, int fk, dim3 grid, dim3 block, hipStream_t s) {
     switch (fk) {
-    case FIELD_UNIFORM: hipLaunchKernelGGL((k_pair_create<R, FIELD_UNIFORM>), grid, block, 0, s, a); break;
-    case FIELD_PLANE: hipLaunchKernelGGL((k_pair_create<R, FIELD_PLANE>), grid, block, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_pair_create<R, FIELD_YEE>), grid, block, 0, s, a); break;
+    case FIELD_UNIFORM: hipLaunchKernelGGL((k_pair_create<R, FIELD_UNIFORM, false>), grid, block, 0, s, a); break;
+    case FIELD_PLANE: hipLaunchKernelGGL((k_pair_create<R, FIELD_PLANE, false>), grid, block, 0, s, a); break;
+    default:
+        // the field-bound cull is a separate instantiation, so that the plain gather keeps its registers
+        if (a.f.bound) hipLaunchKernelGGL((k_pair_create<R, FIELD_YEE, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_pair_create<R, FIELD_YEE, false>), grid, block, 0, s, a);
+        break;
     }
     return hipGetLastError();
 }
