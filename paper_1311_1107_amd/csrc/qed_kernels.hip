@@ -373,8 +373,10 @@ struct Emitted {
 
 // Physics pass of the lepton step.  Writes each particle's new state, and for
 // particles that store photons an emission record for the append pass.
+// FP32 analytic-field steps run three waves per SIMD (168 VGPRs, a few spills):
+// 7 % faster on the batched bunches than two waves with 180 VGPRs
 template <typename R, int FK>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, (sizeof(R) == 4 && FK != FIELD_YEE) ? 3 : 1)
 k_push_emit(PushArgs a) {
     __shared__ R s_lh[kMaxChiNodes];
     __shared__ float s_box[FK == FIELD_YEE && sizeof(R) == 4 ? kMaxWaves * kWBFloats : 1];
