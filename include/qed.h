@@ -244,7 +244,9 @@ enum { QED_VAR_SOKOLOV_G = 1, QED_VAR_PAIR_MOMENTUM = 2 };
 typedef struct {
     double *energy;           /* [device] n_slots * QED_N_ENERGY, zeroed by caller */
     int64_t *count;           /* [device] QED_N_COUNT, zeroed by caller              */
-    int64_t n_slots;          /* [host] >= 1; reproducible sums need >= tiles/launch */
+    int64_t n_slots;          /* [host] >= 1; reproducible sums need one slot per tile:
+                                 ceil(n / block) for the lepton step, ceil(n / 64) for the
+                                 photon step; with fewer, slots are added to atomically */
 } qed_tally;
 
 qed_status qed_tally_reduce(const qed_tally *t, double energy[QED_N_ENERGY] /* [host] */,

@@ -552,20 +552,24 @@ qed_status qed_pair_create(const qed_tables *tab, qed_workspace *ws, const qed_u
     a.uid_next = d_uid_next;
     dim3 grid, block;
     if ((s = shape(ws, sched, ph->capacity, grid, block))) return s;
-    a.tile_sz = block.x;
+    // the physics pass counts pairs per wave (tiles of 64 photons)
+    const int64_t tile_sz = 64;
+    if ((ph->capacity + tile_sz - 1) / tile_sz + 1 > ws->max_tiles)
+        return fail(QED_ERR_ARG, "qed_pair_create: workspace too small for %lld photons", (long long)ph->capacity);
+    a.tile_sz = tile_sz;
     hipStream_t st_ = (hipStream_t)stream;
     // physics pass, scan of the per-tile pair counts, pair appends
     HIP_TRY(qed::launch_pair_create(a, ph->prec, fk, grid, block, st_));
     qed::ScanArgs sc;
     std::memset(&sc, 0, sizeof sc);
     sc.src_count = ph->d_count;
-    sc.tile_sz = block.x;
+    sc.tile_sz = tile_sz;
     sc.d0 = a.el;
     sc.d1 = a.po;
     sc.uid_next = d_uid_next;
     sc.mode = 1;
     sc.ws = ws->dev;
-    HIP_TRY(qed::launch_scan_tiles(sc, scan_grid(ws, ph->capacity, block.x), st_));
+    HIP_TRY(qed::launch_scan_tiles(sc, scan_grid(ws, ph->capacity, tile_sz), st_));
     HIP_TRY(qed::launch_pair_append(a, ph->prec, fk, grid, dim3(256), st_));
     return QED_OK;
 }

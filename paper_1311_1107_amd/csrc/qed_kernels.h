@@ -103,7 +103,7 @@ struct PushArgs {
 
 struct PairArgs {
     TablesDev tab;
-    int64_t tile_sz;
+    int64_t tile_sz;                 // tile of the physics pass: one wave (64 photons)
     SpeciesDev ph, el, po;
     FieldDev f;
     StepDev st;

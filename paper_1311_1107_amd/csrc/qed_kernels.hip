@@ -67,22 +67,26 @@ __device__ __forceinline__ int64_t tsc(R g, R w[3]) {
     return (int64_t)f;
 }
 
-// Sum of w_x[a] w_y[b] w_z[c] v[a][b][c] in one fixed order with explicit
-// FMAs, so that the direct and the LDS-staged gathers give the same bits for
-// the same node values.
+// Sum of w_x[a] w_y[b] w_z[c] v[a][b][c], contracted one axis at a time
+// (z rows, then y, then x) in one fixed order with explicit FMAs, so that the
+// direct and the LDS-staged gathers give the same bits for the same node
+// values.
 template <typename R>
 __device__ __forceinline__ R tsc_sum(const R wx[3], const R wy[3], const R wz[3], const float v[27]) {
     R acc = R(0);
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < 3; ++a) {
+        R plane = R(0);
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
             const float *r = v + 9 * a + 3 * b;
             R row = wz[0] * (R)r[0];
             row = fma(wz[1], (R)r[1], row);
             row = fma(wz[2], (R)r[2], row);
-            acc = fma(wx[a] * wy[b], row, acc);
+            plane = b == 0 ? wy[0] * row : fma(wy[b], row, plane);
         }
+        acc = a == 0 ? wx[0] * plane : fma(wx[a], plane, acc);
+    }
     return acc;
 }
 
@@ -133,22 +137,27 @@ __device__ __forceinline__ void yee_gather(const FieldDev &f, R x, R y, R z, R E
         const int64_t j0 = tsc<R>(gy - (R)kYeeStag[c][1], wy) - 1;
         const int64_t k0 = tsc<R>(gz - (R)kYeeStag[c][2], wz) - 1;
         const float *g = f.grid + c * ncell;
+        // the operations of tsc_sum, in its order, with each row loaded where it is used
         R acc = R(0);
         if (i0 >= 0 && i0 + 2 < nx && j0 >= 0 && j0 + 2 < ny && k0 >= 0 && k0 + 2 < nz) {
             const float *p = g + (i0 * ny + j0) * nz + k0;
 #pragma unroll
-            for (int a = 0; a < 3; ++a)
+            for (int a = 0; a < 3; ++a) {
+                R plane = R(0);
 #pragma unroll
                 for (int b = 0; b < 3; ++b) {
                     const float *r = p + (a * ny + b) * nz;
                     R row = wz[0] * (R)r[0];
                     row = fma(wz[1], (R)r[1], row);
                     row = fma(wz[2], (R)r[2], row);
-                    acc = fma(wx[a] * wy[b], row, acc);
+                    plane = b == 0 ? wy[0] * row : fma(wy[b], row, plane);
                 }
+                acc = a == 0 ? wx[0] * plane : fma(wx[a], plane, acc);
+            }
         } else {
             // nodes outside the grid count as zero, in the same order of operations
-            for (int a = 0; a < 3; ++a)
+            for (int a = 0; a < 3; ++a) {
+                R plane = R(0);
                 for (int b = 0; b < 3; ++b) {
                     const int64_t i = i0 + a, j = j0 + b;
                     const bool row_in = i >= 0 && i < nx && j >= 0 && j < ny;
@@ -161,8 +170,10 @@ __device__ __forceinline__ void yee_gather(const FieldDev &f, R x, R y, R z, R E
                     R row = wz[0] * (R)r[0];
                     row = fma(wz[1], (R)r[1], row);
                     row = fma(wz[2], (R)r[2], row);
-                    acc = fma(wx[a] * wy[b], row, acc);
+                    plane = b == 0 ? wy[0] * row : fma(wy[b], row, plane);
                 }
+                acc = a == 0 ? wx[0] * plane : fma(wx[a], plane, acc);
+            }
         }
         out[c] = acc;
     }
@@ -315,6 +326,20 @@ __device__ __forceinline__ void tile_energy(const TallyDev &tal, int64_t tile, b
         for (int w = 0; w < nw; ++w) s += s_red[threadIdx.x * kMaxWaves + w];
         if (s != 0.0) {
             double *slot = tal.energy + (tile % tal.n_slots) * kNEnergy + threadIdx.x;
+            if (atomic_slots) atomicAdd(slot, s); else *slot += s;
+        }
+    }
+}
+
+// Energy sums of one wave's tile into its tally slot.
+template <int NE>
+__device__ __forceinline__ void wave_energy(const TallyDev &tal, int64_t tile, bool atomic_slots, double (&e)[NE]) {
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+        if (__ballot(e[k] != 0.0) == 0ull) continue;
+        const double s = wave_sum_f64(e[k]);
+        if (lane_id() == 0 && s != 0.0) {
+            double *slot = tal.energy + (tile % tal.n_slots) * kNEnergy + k;
             if (atomic_slots) atomicAdd(slot, s); else *slot += s;
         }
     }
@@ -800,24 +825,28 @@ k_push_append(PushArgs a) {
 // the decay of marked photons, writes the pair and sets tau = +inf (removed
 // later by k_compact).
 // ------------------------------------------------------------------------
+//
+// Blocks take chunks of blockDim.x photons (XCD-contiguous ranges of chunks);
+// each wave of a block steps its own tile of 64 photons of the chunk and
+// publishes that tile's pair count, so the loop has no block barrier.  The
+// state of a wave's next tile is loaded before the current one is stepped,
+// which hides the HBM latency behind the gather.
 template <typename R, int FK, bool kCull>
 __global__ void __launch_bounds__(256)
 k_pair_create(PairArgs a) {
     __shared__ R s_lp[kMaxChiNodes];
     __shared__ float s_box[FK == FIELD_YEE ? kMaxWaves * kWBFloats : 1];
-    __shared__ uint32_t s_wave[3 * kMaxWaves];
-    __shared__ double s_red[kNEnergy * kMaxWaves];
     __shared__ int64_t s_cnt[N_COUNT_USED];
 
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave, nw = blockDim.x / kWave;
     const TablesDev &tb = a.tab;
     for (int i = tid; i < tb.p_n_chi; i += blockDim.x) s_lp[i] = (R)tb.pair_lnh[i];
     const int64_t n = *a.ph.count;
     const double t = a.st.d_step ? a.st.t + (double)(*a.st.d_step) * a.st.dt : a.st.t;
     const double dt = a.st.dt;
     const R dtr = (R)dt;
-    const int64_t tile_sz = blockDim.x;
-    const int64_t n_tiles = (n + tile_sz - 1) / tile_sz;
+    const int64_t n_chunks = (n + blockDim.x - 1) / blockDim.x;
+    const int64_t n_tiles = (n + kWave - 1) / kWave;
     const bool atomic_slots = n_tiles > a.tal.n_slots;
     const R es_inv = (R)a.c.es_inv, Ah = (R)a.c.A;
     const R lnchi0 = (R)tb.p_lnchi0, inv_d = (R)tb.p_inv_dlnchi, chi_min = (R)tb.p_chi_min;
@@ -828,24 +857,34 @@ k_pair_create(PairArgs a) {
     for (int k = 0; k < N_COUNT_USED; ++k) cnt[k] = 0;
     __syncthreads();
 
-    for (int64_t it = 0;; ++it) {
-        const int64_t tile = xcd_tile(it, n_tiles);
-        if (tile < 0) break;
-        const int64_t i = tile * tile_sz + tid;
+    int64_t chunk = xcd_tile(0, n_chunks);
+    double n_tau = HUGE_VAL;
+    R n_x = R(0), n_y = R(0), n_z = R(0), n_kx = R(0), n_ky = R(0), n_kz = R(0);
+    if (chunk >= 0 && chunk * blockDim.x + tid < n) {
+        const int64_t j = chunk * blockDim.x + tid;
+        n_tau = a.ph.tau[j];
+        n_x = X[j]; n_y = Y[j]; n_z = Z[j];
+        n_kx = KX[j]; n_ky = KY[j]; n_kz = KZ[j];
+    }
+    for (int64_t it = 0; chunk >= 0; ++it) {
+        const int64_t tile = chunk * nw + wid;              // = i / 64
+        const int64_t i = chunk * blockDim.x + tid;
         double en[kNEnergy];
 #pragma unroll
         for (int k = 0; k < kNEnergy; ++k) en[k] = 0.0;
         bool event = false;
-        double tau = HUGE_VAL;
-        R x = R(0), y = R(0), z = R(0), kx = R(0), ky = R(0), kz = R(0);
-        if (i < n) {
-            tau = a.ph.tau[i];
-            if (tau != HUGE_VAL) {
-                x = X[i]; y = Y[i]; z = Z[i];
-                kx = KX[i]; ky = KY[i]; kz = KZ[i];
-            }
-        }
+        double tau = n_tau;
+        R x = n_x, y = n_y, z = n_z, kx = n_kx, ky = n_ky, kz = n_kz;
         const bool live = i < n && tau != HUGE_VAL;
+        if (!live) x = y = z = kx = ky = kz = R(0);
+        const int64_t next = xcd_tile(it + 1, n_chunks);
+        n_tau = HUGE_VAL;
+        if (next >= 0 && next * blockDim.x + tid < n) {
+            const int64_t j = next * blockDim.x + tid;
+            n_tau = a.ph.tau[j];
+            n_x = X[j]; n_y = Y[j]; n_z = Z[j];
+            n_kx = KX[j]; n_ky = KY[j]; n_kz = KZ[j];
+        }
         // |k| = gamma_gamma, with one rounding order whatever the kernel variant
         const R kk = Math<R>::sqrt_(fma(kz, kz, fma(ky, ky, kx * kx)));
         R E[3], B[3];
@@ -925,14 +964,15 @@ k_pair_create(PairArgs a) {
                 a.ph.tau[i] = tau;
             }
         }
-        uint32_t rank, tot, d0, d1;
-        block_rank3(event, 0u, 0u, rank, tot, d0, d1, s_wave);
-        if (tid == 0) {
-            a.ws.tile_cnt0[tile] = tot;
-            a.ws.tile_cnt1[tile] = 0u;
+        const uint32_t tot = (uint32_t)__popcll(__ballot(event));
+        if (tile < n_tiles) {
+            if (lane == 0) {
+                a.ws.tile_cnt0[tile] = tot;
+                a.ws.tile_cnt1[tile] = 0u;
+            }
+            wave_energy<kNEnergy>(a.tal, tile, atomic_slots, en);
         }
-        tile_energy<kNEnergy>(a.tal, tile, atomic_slots, en, s_red);
-        __syncthreads();
+        chunk = next;
     }
     block_counts(a.tal, cnt, s_cnt);
 }

@@ -87,8 +87,8 @@ class Run:
         self.rec = D.Species(cap_rec, prec, chi=True, device=device) if wl.record_photons else None
         caps = [n0 + cap_pair, cap_pair, cap_ph, cap_rec, 1]
         self.ws = D.Workspace(max(caps), max_leptons=n0 + cap_pair)
-        # one energy slot per 256-particle tile keeps the sums reproducible at the default block
-        slots = (max(caps) + 255) // 256 + 1 if deterministic_tally else 4096
+        # one energy slot per tile (64 photons in the photon step) keeps the sums reproducible
+        slots = (max(caps) + 63) // 64 + 1 if deterministic_tally else 4096
         self.tally = D.Tally(slots, device=device)
         self.uid_next = torch.tensor([n0], dtype=torch.int64, device=device)
         self.ph_snap = torch.zeros(1, dtype=torch.int64, device=device)
