@@ -238,21 +238,32 @@ __device__ __forceinline__ void yee_gather_wave(const FieldDev &f, bool act, R x
         else E[0] = E[1] = E[2] = B[0] = B[1] = B[2] = R(0);
         return;
     }
-    // stage the box: node e = (p kWBY + q) kWBZ + r
+    // stage the box: node e = (p kWBY + q) kWBZ + r; every load of the lane is
+    // issued before the first LDS write
+    constexpr int kU = (kWBVol + kWave - 1) / kWave;
+    bool span[kU], in[kU];
+    int64_t off[kU];
 #pragma unroll
-    for (int u = 0; u < (kWBVol + kWave - 1) / kWave; ++u) {
+    for (int u = 0; u < kU; ++u) {
         const int e = lane_id() + u * kWave;
         const int p = e / (kWBY * kWBZ), q = (e / kWBZ) % kWBY, r = e % kWBZ;
-        // only the nodes the wave's stencils span are loaded (the rest are never read)
-        if (e < kWBVol && p < ext[0] && q < ext[1] && r < ext[2]) {
-            const int64_t i = o[0] + p, j = o[1] + q, k = o[2] + r;
-            const bool in = i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz;
-            const int64_t off = in ? (i * ny + j) * nz + k : 0;
-            float v[6];
+        // only the nodes the wave's stencils span are stored (the rest are never read)
+        span[u] = e < kWBVol && p < ext[0] && q < ext[1] && r < ext[2];
+        const int64_t i = o[0] + p, j = o[1] + q, k = o[2] + r;
+        in[u] = span[u] && i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz;
+        off[u] = in[u] ? (i * ny + j) * nz + k : 0;
+    }
+    float v[kU][6];
 #pragma unroll
-            for (int c = 0; c < 6; ++c) v[c] = in ? f.grid[c * ncell + off] : 0.0f;
+    for (int u = 0; u < kU; ++u)
 #pragma unroll
-            for (int c = 0; c < 6; ++c) box[c * kWBVol + e] = v[c];
+        for (int c = 0; c < 6; ++c) v[u][c] = in[u] ? f.grid[c * ncell + off[u]] : 0.0f;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+        const int e = lane_id() + u * kWave;
+        if (span[u]) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) box[c * kWBVol + e] = v[u][c];
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
