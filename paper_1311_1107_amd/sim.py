@@ -277,6 +277,59 @@ class Run:
             self._photon_view()
         return done
 
+    # ------------------------------------------------------------------
+    # Checkpoint and restart.  What carries over from one step to the next is
+    # saved: the live particles of every species with their ids, event counters
+    # and optical depths, the id counter, the tallies and, in the coupled form,
+    # the grid.  A run built again from the same workload and options and
+    # loaded from the file continues bit-identically: draws are keyed by id and
+    # event counter, and the step schedule (compaction, cell order) by step.
+    _SPECIES = ("el", "po", "ph", "rec")
+
+    def save(self, path: str, next_step: int):
+        """Write a checkpoint (numpy .npz) to continue from step `next_step`."""
+        torch.cuda.synchronize()
+        out = {"next_step": np.array(next_step, dtype=np.int64),
+               "uid_next": self.uid_next.cpu().numpy(),
+               "tally_energy": self.tally.energy.cpu().numpy(),
+               "tally_count": self.tally.count.cpu().numpy()}
+        for name in self._SPECIES:
+            sp = getattr(self, name)
+            if sp is None:
+                continue
+            for k, v in sp.download().items():
+                out[f"{name}.{k}"] = v
+        if self.coupled:
+            out["grid"] = self.grid.cpu().numpy()
+            out["skipped"] = self.skipped.cpu().numpy()
+        np.savez(path, **out)
+
+    def load(self, path: str) -> int:
+        """Restore a checkpoint written by save() into this run (built with the
+        same workload and options); returns the step to continue from."""
+        with np.load(path, allow_pickle=False) as z:
+            for name in self._SPECIES:
+                sp = getattr(self, name)
+                keys = [k for k in z.files if k.startswith(name + ".")]
+                if sp is None:
+                    if keys:
+                        raise ValueError(f"checkpoint holds species {name!r}, which this run does not")
+                    continue
+                arrays = {k.split(".", 1)[1]: z[k] for k in keys}
+                sp.upload(arrays, len(arrays["x"]))
+            if self.tally.energy.numel() != z["tally_energy"].size:
+                raise ValueError("checkpoint tally has a different number of slots")
+            self.uid_next.copy_(torch.from_numpy(z["uid_next"]))
+            self.tally.energy.copy_(torch.from_numpy(z["tally_energy"]))
+            self.tally.count.copy_(torch.from_numpy(z["tally_count"]))
+            if self.coupled:
+                self.grid.copy_(torch.from_numpy(z["grid"]))
+                self.skipped.copy_(torch.from_numpy(z["skipped"]))
+                self.field_bound()
+            nxt = int(z["next_step"])
+        torch.cuda.synchronize()
+        return nxt
+
     def compact(self):
         if self.ph is not None:
             B.qed_compact(self.ws.h, self.ph.struct(), self.sched)
