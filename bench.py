@@ -42,7 +42,9 @@ def parse():
     p.add_argument("--compact-every", type=int, default=16)
     p.add_argument("--no-merge", action="store_true",
                    help="cascade: stop at the first full buffer instead of merging super-particles")
-    p.add_argument("--sort-every", type=int, default=16, help="cell-order the particles every k steps (Yee)")
+    p.add_argument("--sort-every", type=int, default=16, help="cell-order the leptons every k steps (Yee)")
+    p.add_argument("--photon-sort-every", type=int, default=None,
+                   help="cell-order the photons every k steps (Yee; default: as the leptons)")
     p.add_argument("--bound-block", type=int, default=0,
                    help="Yee: per-block field bounds (block edge in cells) so that photon waves with no possible "
                         "pair skip the gather; 0 = off")
@@ -455,7 +457,8 @@ def main():
     K = min(K, wl.steps)
     n0 = len(wl.electrons["x"])
 
-    run = S.Run(wl, prec=prec, compact_every=args.compact_every, sort_every=args.sort_every, coupled=coupled,
+    run = S.Run(wl, prec=prec, compact_every=args.compact_every, sort_every=args.sort_every,
+                photon_sort_every=args.photon_sort_every, coupled=coupled,
                 particles_per_weight=1000.0, field_bound_block=args.bound_block, **caps)
     init = {k: v.clone() for k, v in run.el.a.items()}
     init_el = run.el
@@ -544,12 +547,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "electrons": n0, "grid": list(wl.field.shape) if hasattr(wl.field, "shape") else None,
                    "steps_timed": K, "dt": wl.dt, "compact_every": args.compact_every,
-                   "sort_every": args.sort_every, "bound_block": args.bound_block},
+                   "sort_every": args.sort_every, "photon_sort_every": run.photon_sort_every,
+                   "bound_block": args.bound_block},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      # counters were taken on the default command: 1e7 electrons, 2000 steps, sort/compact every 16
                      "traffic": (measured_traffic() if dom.startswith("qed_pair_create") and K == 2000 and n0 == 10_000_000
-                                 and args.sort_every == 16 and args.compact_every == 16 and not coupled
+                                 and args.sort_every == 16 and run.photon_sort_every == 16
+                                 and args.compact_every == 16 and not coupled
                                  and args.bound_block == 0 else None),
                      "bytes_per_launch": dom_bytes / max(dom_n, 1), "avg_launch_ms": dom_ms / max(dom_n, 1)},
         "detail": {"lepton_steps": lepton_steps, "photon_steps": photon_steps, "kernel_ms": kernel_ms,

@@ -9,8 +9,9 @@ Order within step n (time t = n dt):
      (qed_pair_create); photons emitted in 2-3 are stored at level n+1 and
      are first advanced at step n+1, as are the pairs created in 4
   5. every `compact_every` steps, decayed photons are removed (qed_compact)
-  6. (Yee field) every `sort_every` steps, every species is put in stable cell
-     order (qed_sort_by_cell), which also drops decayed photons
+  6. (Yee field) every `sort_every` steps the leptons, and every
+     `photon_sort_every` steps the photons, are put in stable cell order
+     (qed_sort_by_cell), which also drops decayed photons
 Between steps, merge_if_needed() merges the super-particles of a species
 that fills more than a set fraction of its buffer (qed_merge, keeping weight,
 momentum and energy).
@@ -67,6 +68,7 @@ class Run:
                  pair_capacity: int | None = None, rad_model: int = B.QED_RAD_HYBRID,
                  chi_switch: float = 1e-3, gamma_photon_min: float = 2.0, max_events: int = 4,
                  sched: B.qed_schedule | None = None, compact_every: int = 16, sort_every: int = 0,
+                 photon_sort_every: int | None = None,
                  deterministic_tally: bool = True, variants: int = 0, merge: MergePolicy | None = None,
                  coupled: bool = False, particles_per_weight: float = 1.0, field_bound_block: int = 0,
                  device: str = "cuda"):
@@ -125,7 +127,11 @@ class Run:
             raise TypeError("unknown field description")
         # cell ordering (Yee field only): a second buffer per species, swapped after each sort
         self.sort_every = sort_every if self.grid is not None else 0
-        if self.sort_every:
+        # photons move together at c, and those emitted in one step are appended in the
+        # cell order of their parents, so their order decays more slowly than the leptons'
+        pse = sort_every if photon_sort_every is None else photon_sort_every
+        self.photon_sort_every = pse if (self.grid is not None and self.ph is not None) else 0
+        if self.sort_every or self.photon_sort_every:
             self.sorter = D.Sorter(max(caps))
             self.alt = {"el": D.Species(self.el.capacity, prec, chi=True, device=device),
                         "po": D.Species(self.po.capacity, prec, chi=True, device=device)}
@@ -153,7 +159,7 @@ class Run:
         self.merge_policy = merge
         self.merger = D.Merger(max(caps)) if merge is not None else None
         self.merges = []
-        if not self.sort_every:
+        if not (self.sort_every or self.photon_sort_every):
             self.alt = {}
         self._photon_view()
 
@@ -165,12 +171,12 @@ class Run:
             C.memmove(C.addressof(self.ph_step), C.addressof(s), C.sizeof(s))
             self.ph_step.d_count = self.ph_snap.data_ptr()
 
-    def sort(self):
-        """Stable cell order of every species (drops decayed photons); photons by (cell,
-        energy band) when the field bounds are on."""
+    def sort(self, leptons: bool = True, photons: bool = True):
+        """Stable cell order of the leptons and/or the photons (drops decayed photons);
+        photons by (cell, energy band) when the field bounds are on."""
         for name in ("el", "po", "ph"):
             src = getattr(self, name)
-            if src is None:
+            if src is None or not (photons if name == "ph" else leptons):
                 continue
             dst = self.alt[name]
             # with field bounds, photons of one cell are grouped by energy band so that whole
@@ -212,7 +218,8 @@ class Run:
                                               self.field, pp, pr, self.tally.s, st, uid, self.sched))
         run("push_p", lambda: B.qed_push_emit(self.tables.h, self.ws.h, self.units, +1.0, self.po.struct(),
                                               self.field, pp, pr, self.tally.s, st, uid, self.sched))
-        sorting = bool(self.sort_every) and (n + 1) % self.sort_every == 0
+        sort_lep = bool(self.sort_every) and (n + 1) % self.sort_every == 0
+        sort_ph = bool(self.photon_sort_every) and (n + 1) % self.photon_sort_every == 0
         if self.coupled:
             run("deposit", self._deposit_pushed)
         if self.ph is not None:
@@ -222,13 +229,13 @@ class Run:
             if self.coupled:
                 run("deposit", self._deposit_created)
             # the cell sort drops decayed photons itself
-            if self.compact_every and (n + 1) % self.compact_every == 0 and not sorting:
+            if self.compact_every and (n + 1) % self.compact_every == 0 and not sort_ph:
                 run("compact", self.compact)
         if self.coupled:
             run("field", lambda: (B.qed_yee_advance(self.grid.data_ptr(), self.J.data_ptr(), self.field, self.wl.dt),
                                   self.field_bound()))
-        if sorting:
-            run("sort", self.sort)
+        if sort_lep or sort_ph:
+            run("sort", lambda: self.sort(leptons=sort_lep, photons=sort_ph))
 
     # ------------------------------------------------------------------
     def _save_positions(self):
