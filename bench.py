@@ -36,7 +36,7 @@ def parse():
     p.add_argument("--workload", default="yee", choices=["yee", "coupled", "plane", "batched", "cascade"])
     p.add_argument("--electrons", type=int, default=None, help="override the electron count")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-sample", type=int, default=1000, help="electrons in the oracle sample")
+    p.add_argument("--cpu-sample", type=int, default=1500, help="electrons in the oracle sample")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run a 1 GiB device copy first (reference for the traffic counters)")
     p.add_argument("--compact-every", type=int, default=16)
@@ -75,6 +75,24 @@ def measured_traffic():
     if vals.get("kernel_source_sha256") != h.hexdigest() or "traffic_bytes_per_call" not in vals:
         return None
     return float(vals["traffic_bytes_per_call"])
+
+
+def device_copy_gbs(reps: int = 10) -> float:
+    """Bandwidth of a plain 1 GiB device-to-device copy (read + write bytes / time)."""
+    import torch
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * (1 << 30) / (ms * 1e-3) / 1e9
 
 
 def cpu_baseline(wl, n_sample: int, steps: int):
@@ -568,6 +586,10 @@ def main():
         del run
         torch.cuda.empty_cache()
         out["batched_vs_plain"] = batched_comparison(args.batched_steps)
+    # measured copy bandwidth on this GPU (after the timed region), for the ratio to it
+    copy_gbs = device_copy_gbs()
+    out["roofline"]["copy_GBs"] = copy_gbs
+    out["roofline"]["frac_of_copy"] = achieved / copy_gbs if copy_gbs > 0 else None
     if not args.no_cpu_baseline and not coupled:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample, K)
     print(json.dumps(out), flush=True)
