@@ -178,10 +178,16 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t &total) 
     return x - v;
 }
 
+// Sum over the wave, on every lane: row sums through DPP (quad permutations,
+// row rotations), then the four rows.  The wave must be fully active.
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
-#pragma unroll
-    for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
-    return v;
+    int x = (int)v;
+    x += __builtin_amdgcn_update_dpp(x, x, 0xb1, 0xf, 0xf, false);    // quad_perm 1,0,3,2
+    x += __builtin_amdgcn_update_dpp(x, x, 0x4e, 0xf, 0xf, false);    // quad_perm 2,3,0,1
+    x += __builtin_amdgcn_update_dpp(x, x, 0x124, 0xf, 0xf, false);   // row_ror 4
+    x += __builtin_amdgcn_update_dpp(x, x, 0x128, 0xf, 0xf, false);   // row_ror 8
+    return (uint32_t)__builtin_amdgcn_readlane(x, 0) + (uint32_t)__builtin_amdgcn_readlane(x, 16) +
+           (uint32_t)__builtin_amdgcn_readlane(x, 32) + (uint32_t)__builtin_amdgcn_readlane(x, 48);
 }
 
 __device__ __forceinline__ double wave_sum_f64(double v) {

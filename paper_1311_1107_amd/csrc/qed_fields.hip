@@ -96,12 +96,15 @@ __device__ __forceinline__ int64_t tsc_node(double u, double s[3]) {
 __device__ __forceinline__ bool coord_ok(double u) { return u > -1.0e15 && u < 1.0e15; }
 
 __device__ __forceinline__ int wave_min_int(int v) {
-#pragma unroll
-    for (int d = kWave / 2; d > 0; d >>= 1) {
-        const int w = __shfl_xor(v, d, kWave);
-        v = w < v ? w : v;
-    }
-    return v;
+    // row minima through DPP (quad permutations, row rotations), then the four
+    // rows; the wave must be fully active
+    auto mn = [](int a, int b) { return a < b ? a : b; };
+    v = mn(v, __builtin_amdgcn_update_dpp(v, v, 0xb1, 0xf, 0xf, false));    // quad_perm 1,0,3,2
+    v = mn(v, __builtin_amdgcn_update_dpp(v, v, 0x4e, 0xf, 0xf, false));    // quad_perm 2,3,0,1
+    v = mn(v, __builtin_amdgcn_update_dpp(v, v, 0x124, 0xf, 0xf, false));   // row_ror 4
+    v = mn(v, __builtin_amdgcn_update_dpp(v, v, 0x128, 0xf, 0xf, false));   // row_ror 8
+    return mn(mn(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+              mn(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 
 // Per-particle stencil of the deposition: window start (node n0 - 2 per axis),

@@ -196,13 +196,17 @@ constexpr int kWBX = 6, kWBY = 5, kWBZ = 5;
 constexpr int kWBVol = kWBX * kWBY * kWBZ;
 constexpr int kWBFloats = 6 * kWBVol;
 
+// Minimum over the wave, on every lane: row minima through DPP (quad
+// permutations, row rotations), then the four rows.  The wave must be fully
+// active.
 __device__ __forceinline__ int wave_min_i32(int v) {
-#pragma unroll
-    for (int d = kWave / 2; d > 0; d >>= 1) {
-        const int o = __shfl_xor(v, d, kWave);
-        v = o < v ? o : v;
-    }
-    return v;
+    auto mn = [](int a, int b) { return a < b ? a : b; };
+    v = mn(v, __builtin_amdgcn_update_dpp(v, v, 0xb1, 0xf, 0xf, false));    // quad_perm 1,0,3,2
+    v = mn(v, __builtin_amdgcn_update_dpp(v, v, 0x4e, 0xf, 0xf, false));    // quad_perm 2,3,0,1
+    v = mn(v, __builtin_amdgcn_update_dpp(v, v, 0x124, 0xf, 0xf, false));   // row_ror 4
+    v = mn(v, __builtin_amdgcn_update_dpp(v, v, 0x128, 0xf, 0xf, false));   // row_ror 8
+    return mn(mn(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+              mn(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 
 // Called by all lanes of the wave; act marks lanes that need the field.
