@@ -5,6 +5,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <type_traits>
 #include <stdint.h>
 
 namespace qed {
@@ -188,6 +189,29 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
     x += __builtin_amdgcn_update_dpp(x, x, 0x128, 0xf, 0xf, false);   // row_ror 8
     return (uint32_t)__builtin_amdgcn_readlane(x, 0) + (uint32_t)__builtin_amdgcn_readlane(x, 16) +
            (uint32_t)__builtin_amdgcn_readlane(x, 32) + (uint32_t)__builtin_amdgcn_readlane(x, 48);
+}
+
+// Sum over the wave of a double, on every lane, in a fixed tree order: row
+// sums through DPP on both halves of the value, then the four rows in order.
+// The wave must be fully active.
+__device__ __forceinline__ double wave_sum_f64_dpp(double v) {
+    auto step = [](double x, auto ctrl) {
+        const uint64_t b = __builtin_bit_cast(uint64_t, x);
+        const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, decltype(ctrl)::value, 0xf, 0xf, false);
+        const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), decltype(ctrl)::value, 0xf, 0xf, false);
+        return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+    };
+    v += step(v, std::integral_constant<int, 0xb1>{});    // quad_perm 1,0,3,2
+    v += step(v, std::integral_constant<int, 0x4e>{});    // quad_perm 2,3,0,1
+    v += step(v, std::integral_constant<int, 0x124>{});   // row_ror 4
+    v += step(v, std::integral_constant<int, 0x128>{});   // row_ror 8
+    auto lane_value = [](double x, int l) {
+        const uint64_t b = __builtin_bit_cast(uint64_t, x);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)b, l);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(b >> 32), l);
+        return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+    };
+    return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 
 __device__ __forceinline__ double wave_sum_f64(double v) {

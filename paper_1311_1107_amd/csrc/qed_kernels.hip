@@ -332,7 +332,7 @@ __device__ __forceinline__ void tile_energy(const TallyDev &tal, int64_t tile, b
 #pragma unroll
     for (int k = 0; k < NE; ++k) {
         double v = e[k];
-        if (__ballot(v != 0.0)) v = wave_sum_f64(v); else v = 0.0;
+        if (__ballot(v != 0.0)) v = wave_sum_f64_dpp(v); else v = 0.0;
         if (lane == 0) s_red[k * kMaxWaves + wid] = v;
     }
     __syncthreads();
@@ -352,7 +352,7 @@ __device__ __forceinline__ void wave_energy(const TallyDev &tal, int64_t tile, b
 #pragma unroll
     for (int k = 0; k < NE; ++k) {
         if (__ballot(e[k] != 0.0) == 0ull) continue;
-        const double s = wave_sum_f64(e[k]);
+        const double s = wave_sum_f64_dpp(e[k]);
         if (lane_id() == 0 && s != 0.0) {
             double *slot = tal.energy + (tile % tal.n_slots) * kNEnergy + k;
             if (atomic_slots) atomicAdd(slot, s); else *slot += s;
