@@ -501,9 +501,11 @@ k_push_emit(PushArgs a) {
             // Boris: half electric kick, magnetic rotation, half kick
             const R umx = ux + hq * E[0], umy = uy + hq * E[1], umz = uz + hq * E[2];
             const R gm = Math<R>::sqrt_(R(1) + (umx * umx + umy * umy + umz * umz));
-            const R tx = hq * B[0] / gm, ty = hq * B[1] / gm, tz = hq * B[2] / gm;
+            const R hg = hq / gm;
+            const R tx = hg * B[0], ty = hg * B[1], tz = hg * B[2];
             const R t2 = tx * tx + ty * ty + tz * tz;
-            const R sx = R(2) * tx / (R(1) + t2), sy = R(2) * ty / (R(1) + t2), sz = R(2) * tz / (R(1) + t2);
+            const R s2 = R(2) / (R(1) + t2);
+            const R sx = s2 * tx, sy = s2 * ty, sz = s2 * tz;
             const R px = umx + (umy * tz - umz * ty);
             const R py = umy + (umz * tx - umx * tz);
             const R pz = umz + (umx * ty - umy * tx);
@@ -524,7 +526,8 @@ k_push_emit(PushArgs a) {
             if (rad == RAD_SOKOLOV || (rad == RAD_HYBRID && (double)chi < a.st.chi_switch)) {
                 // Sokolov scheme (Eq. 4) with P_rad of Eq. 5
                 cnt[C_SOKOLOV]++;
-                const R vx = uLx / gL, vy = uLy / gL, vz = uLz / gL;
+                const R igL = R(1) / gL;
+                const R vx = uLx * igL, vy = uLy * igL, vz = uLz * igL;
                 const R fx = q * (E[0] + (vy * B[2] - vz * B[1]));
                 const R fy = q * (E[1] + (vz * B[0] - vx * B[2]));
                 const R fz = q * (E[2] + (vx * B[1] - vy * B[0]));
@@ -536,21 +539,22 @@ k_push_emit(PushArgs a) {
                 }
                 // variant: delta_v with the quantum-reduced tau_0 g(chi)
                 const R tq = (a.st.variants & VAR_SOKOLOV_G) ? tau0 * g : tau0;
-                const R den = R(1) + tq * vf;
-                dvx = tq * (fx - vx * vf) / den;
-                dvy = tq * (fy - vy * vf) / den;
-                dvz = tq * (fz - vz * vf) / den;
+                const R tden = tq / (R(1) + tq * vf);
+                dvx = tden * (fx - vx * vf);
+                dvy = tden * (fy - vy * vf);
+                dvz = tden * (fz - vz * vf);
                 const R P = (R(2) / R(3)) * Ah * chi * chi * g;
                 const R bx = dvy * B[2] - dvz * B[1], by = dvz * B[0] - dvx * B[2], bz = dvx * B[1] - dvy * B[0];
-                unx = uLx + dtr * (q * bx - P * uLx / gL);
-                uny = uLy + dtr * (q * by - P * uLy / gL);
-                unz = uLz + dtr * (q * bz - P * uLz / gL);
+                const R Pg = P * igL;
+                unx = uLx + dtr * (q * bx - Pg * uLx);
+                uny = uLy + dtr * (q * by - Pg * uLy);
+                unz = uLz + dtr * (q * bz - Pg * uLz);
                 en[E_RAD] = (double)wgt * (double)P * dt;
             } else if (rad == RAD_MC || rad == RAD_HYBRID) {
                 // optical-depth Monte Carlo, Eqs. 6-8
                 cnt[C_MC]++;
                 R p = Math<R>::sqrt_(uLx * uLx + uLy * uLy + uLz * uLz);
-                if (p > R(0)) { uhx = uLx / p; uhy = uLy / p; uhz = uLz / p; }
+                if (p > R(0)) { const R ip = R(1) / p; uhx = uLx * ip; uhy = uLy * ip; uhz = uLz * ip; }
                 R gam = gL, ce = chi;
                 R W = R(0);
                 if (p > R(0) && ce > R(0)) {
@@ -609,9 +613,10 @@ k_push_emit(PushArgs a) {
                 a.lep.tau[i] = tau;
             }
             const R gn = Math<R>::sqrt_(R(1) + (unx * unx + uny * uny + unz * unz));
-            X[i] = x + dtr * (unx / gn + dvx);
-            Y[i] = y + dtr * (uny / gn + dvy);
-            Z[i] = z + dtr * (unz / gn + dvz);
+            const R ign = R(1) / gn;
+            X[i] = x + dtr * (unx * ign + dvx);
+            Y[i] = y + dtr * (uny * ign + dvy);
+            Z[i] = z + dtr * (unz * ign + dvz);
             UX[i] = unx; UY[i] = uny; UZ[i] = unz;
         }
 
@@ -960,10 +965,11 @@ k_pair_create(PairArgs a) {
             const R chig = chi_of<R>(es_inv, kk, kx, ky, kz, E, B);
             cnt[C_PHSTEP]++;
             R Wp = R(0);
+            const R ik = R(1) / kk;
             if (kk > R(2) && chig >= chi_min) {
                 bool above = false;
                 const R l = lerp_rate<R>(s_lp, tb.p_n_chi, lnchi0, inv_d, Math<R>::log_(chig), above);
-                Wp = Ah * Math<R>::exp_(l - R(8) / (R(3) * chig)) / kk;
+                Wp = Ah * Math<R>::exp_(l - R(8) / (R(3) * chig)) * ik;
                 if (above) cnt[C_RANGE]++;
             }
             tau -= (double)Wp * dt;
@@ -973,9 +979,9 @@ k_pair_create(PairArgs a) {
                 en[E_PAIR] = (double)((const R *)a.ph.w)[i] * (double)kk;
                 a.ph.tau[i] = -HUGE_VAL;
             } else {
-                X[i] = x + dtr * (kx / kk);
-                Y[i] = y + dtr * (ky / kk);
-                Z[i] = z + dtr * (kz / kk);
+                X[i] = x + dtr * (kx * ik);
+                Y[i] = y + dtr * (ky * ik);
+                Z[i] = z + dtr * (kz * ik);
                 a.ph.tau[i] = tau;
             }
         }
