@@ -338,6 +338,27 @@ def test_sort_rejects_bad_arguments():
         D.Sorter(10).sort(ws, src, D.Species(100), f)
 
 
+def test_photon_step_rejects_a_workspace_too_small_for_its_tiles(gpu_oracle_tables):
+    """The photon step counts pairs per wave (tiles of 64 photons): a workspace
+    made for fewer photons than the species holds is refused before any launch."""
+    _need_gpu()
+    units = B.qed_units_init(W.LAMBDA_M)
+    ws = D.Workspace(1000)
+    ph, el, po = D.Species(2000), D.Species(100), D.Species(100)
+    tal = D.Tally(64)
+    uid = torch.zeros(1, dtype=torch.int64, device="cuda")
+    with pytest.raises(B.QedError) as e:
+        B.qed_pair_create(gpu_oracle_tables.h, ws.h, units, ph.struct(), D.uniform(), el.struct(), po.struct(),
+                          tal.s, D.step(0.0, W.DT, 1), uid.data_ptr())
+    assert e.value.code == B.QED_ERR_ARG and "workspace too small" in str(e.value)
+    # a workspace of the species' size is accepted (no photons: nothing happens)
+    ws2 = D.Workspace(2000)
+    B.qed_pair_create(gpu_oracle_tables.h, ws2.h, units, ph.struct(), D.uniform(), el.struct(), po.struct(),
+                      tal.s, D.step(0.0, W.DT, 1), uid.data_ptr())
+    torch.cuda.synchronize()
+    ws2.status()
+
+
 # --------------------------------------------------------- batched form ----
 def _bunch_setup(seed=4, n_bunches=6):
     e, off, a0s, g0s = W.bunches(n_bunches=n_bunches, seed=seed, lo=2.0, hi=3.3)
