@@ -246,26 +246,33 @@ k_radix_scatter(const uint32_t *kin, const uint32_t *iin, uint32_t *kout, uint32
     }
 }
 
-// gather the live particles into the destination, in sorted order
+// gather the live particles into the destination, in sorted order; each
+// thread keeps four gathers in flight
 template <typename R>
 __global__ void __launch_bounds__(256)
 k_sort_permute(SortArgs a) {
     const int64_t live = (int64_t)*a.live;
     const uint32_t *idx = a.idx_final;
     const bool chi = a.src.chi != nullptr && a.dst.chi != nullptr;
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < live; j += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = idx[j];
-        ((R *)a.dst.x)[j] = ((const R *)a.src.x)[i];
-        ((R *)a.dst.y)[j] = ((const R *)a.src.y)[i];
-        ((R *)a.dst.z)[j] = ((const R *)a.src.z)[i];
-        ((R *)a.dst.ux)[j] = ((const R *)a.src.ux)[i];
-        ((R *)a.dst.uy)[j] = ((const R *)a.src.uy)[i];
-        ((R *)a.dst.uz)[j] = ((const R *)a.src.uz)[i];
-        ((R *)a.dst.w)[j] = ((const R *)a.src.w)[i];
-        if (chi) ((R *)a.dst.chi)[j] = ((const R *)a.src.chi)[i];
-        a.dst.tau[j] = a.src.tau[i];
-        a.dst.uid[j] = a.src.uid[i];
-        a.dst.n_ev[j] = a.src.n_ev[i];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j0 < live; j0 += 4 * stride) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t j = j0 + u * stride;
+            if (j >= live) break;
+            const int64_t i = idx[j];
+            ((R *)a.dst.x)[j] = ((const R *)a.src.x)[i];
+            ((R *)a.dst.y)[j] = ((const R *)a.src.y)[i];
+            ((R *)a.dst.z)[j] = ((const R *)a.src.z)[i];
+            ((R *)a.dst.ux)[j] = ((const R *)a.src.ux)[i];
+            ((R *)a.dst.uy)[j] = ((const R *)a.src.uy)[i];
+            ((R *)a.dst.uz)[j] = ((const R *)a.src.uz)[i];
+            ((R *)a.dst.w)[j] = ((const R *)a.src.w)[i];
+            if (chi) ((R *)a.dst.chi)[j] = ((const R *)a.src.chi)[i];
+            a.dst.tau[j] = a.src.tau[i];
+            a.dst.uid[j] = a.src.uid[i];
+            a.dst.n_ev[j] = a.src.n_ev[i];
+        }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) *a.dst.count = live;
 }
