@@ -1089,12 +1089,13 @@ k_pair_append(PairArgs a) {
 template <typename R>
 __global__ void __launch_bounds__(256)
 k_compact(CompactArgs a) {
+    constexpr int kItems = 4;                          // tiles of kItems x blockDim.x photons
     __shared__ uint64_t s_ticket;
-    __shared__ uint32_t s_wave[2 * kMaxWaves];
+    __shared__ uint32_t s_wc[kItems * kMaxWaves];      // alive photons per (item row, wave)
     __shared__ uint32_t s_pref;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave, nw = blockDim.x / kWave;
     const int64_t n = *a.s.count;
-    const int64_t tile_sz = blockDim.x;
+    const int64_t tile_sz = (int64_t)blockDim.x * kItems;
     const int64_t n_tiles = (n + tile_sz - 1) / tile_sz;
     R *X = (R *)a.s.x, *Y = (R *)a.s.y, *Z = (R *)a.s.z;
     R *UX = (R *)a.s.ux, *UY = (R *)a.s.uy, *UZ = (R *)a.s.uz, *Wt = (R *)a.s.w, *CH = (R *)a.s.chi;
@@ -1117,40 +1118,69 @@ k_compact(CompactArgs a) {
             }
             break;
         }
-        const int64_t i = tile * tile_sz + tid;
-        bool alive = false;
-        R x = R(0), y = R(0), z = R(0), ux = R(0), uy = R(0), uz = R(0), w = R(0), ch = R(0);
-        double tau = 0.0;
-        uint64_t uid = 0;
-        uint32_t nev = 0;
-        if (i < n) {
-            tau = a.s.tau[i];
-            alive = tau != HUGE_VAL;
-            if (alive) {
-                x = X[i]; y = Y[i]; z = Z[i]; ux = UX[i]; uy = UY[i]; uz = UZ[i]; w = Wt[i];
-                if (CH) ch = CH[i];
-                uid = a.s.uid[i];
-                nev = a.s.n_ev[i];
+        // photon u * blockDim.x + tid of the tile: coalesced rows, kept in index order
+        const int64_t base = tile * tile_sz;
+        bool alive[kItems];
+        R x[kItems], y[kItems], z[kItems], ux[kItems], uy[kItems], uz[kItems], w[kItems], ch[kItems];
+        double tau[kItems];
+        uint64_t uid[kItems];
+        uint32_t nev[kItems];
+#pragma unroll
+        for (int u = 0; u < kItems; ++u) {
+            const int64_t i = base + (int64_t)u * blockDim.x + tid;
+            alive[u] = false;
+            x[u] = y[u] = z[u] = ux[u] = uy[u] = uz[u] = w[u] = ch[u] = R(0);
+            tau[u] = 0.0; uid[u] = 0; nev[u] = 0;
+            if (i < n) {
+                tau[u] = a.s.tau[i];
+                alive[u] = tau[u] != HUGE_VAL;
+                if (alive[u]) {
+                    x[u] = X[i]; y[u] = Y[i]; z[u] = Z[i]; ux[u] = UX[i]; uy[u] = UY[i]; uz[u] = UZ[i]; w[u] = Wt[i];
+                    if (CH) ch[u] = CH[i];
+                    uid[u] = a.s.uid[i];
+                    nev[u] = a.s.n_ev[i];
+                }
             }
         }
         // all loads of this tile complete before its count becomes visible
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        uint32_t e, tot;
-        block_scan_flag(alive, e, tot, s_wave);
+        uint64_t m[kItems];
+#pragma unroll
+        for (int u = 0; u < kItems; ++u) {
+            m[u] = __ballot(alive[u]);
+            if (lane == 0) s_wc[u * kMaxWaves + wid] = (uint32_t)__popcll(m[u]);
+        }
+        __syncthreads();
+        // rank of photon (u, tid): alive photons in earlier rows, then in earlier waves of row u
+        uint32_t before[kItems], tot = 0;
+#pragma unroll
+        for (int u = 0; u < kItems; ++u) {
+            uint32_t r = tot;
+            for (int v = 0; v < nw; ++v) {
+                const uint32_t c = s_wc[u * kMaxWaves + v];
+                if (v < wid) r += c;
+                tot += c;
+            }
+            before[u] = r + __builtin_amdgcn_mbcnt_hi((uint32_t)(m[u] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m[u], 0u));
+        }
         if (tid < kWave) {
             uint32_t p0, p1;
             lookback2(a.ws.lb, tile, epoch, tot, 0u, p0, p1);
             if (tid == 0) s_pref = p0;
         }
         __syncthreads();
-        if (alive) {
-            const int64_t j = (int64_t)(s_pref + e);
-            if (j != i) {
-                X[j] = x; Y[j] = y; Z[j] = z; UX[j] = ux; UY[j] = uy; UZ[j] = uz; Wt[j] = w;
-                if (CH) CH[j] = ch;
-                a.s.uid[j] = uid;
-                a.s.n_ev[j] = nev;
-                a.s.tau[j] = tau;
+#pragma unroll
+        for (int u = 0; u < kItems; ++u) {
+            const int64_t i = base + (int64_t)u * blockDim.x + tid;
+            if (alive[u]) {
+                const int64_t j = (int64_t)(s_pref + before[u]);
+                if (j != i) {
+                    X[j] = x[u]; Y[j] = y[u]; Z[j] = z[u]; UX[j] = ux[u]; UY[j] = uy[u]; UZ[j] = uz[u]; Wt[j] = w[u];
+                    if (CH) CH[j] = ch[u];
+                    a.s.uid[j] = uid[u];
+                    a.s.n_ev[j] = nev[u];
+                    a.s.tau[j] = tau[u];
+                }
             }
         }
         __syncthreads();
