@@ -1005,10 +1005,10 @@ k_pair_append(PairArgs a) {
     __shared__ uint32_t s_wave[3 * kMaxWaves];
     __shared__ uint32_t s_list[256];
     __shared__ int64_t s_cnt[N_COUNT_USED];
-    const int tid = threadIdx.x;
+    const int wid = threadIdx.x / kWave, nw = blockDim.x / kWave, lane = lane_id();
     const TablesDev &tb = a.tab;
     const int64_t n = *a.ph.count;
-    const int64_t tile_sz = a.tile_sz;
+    const int64_t tile_sz = a.tile_sz;                 // kWave: one wave per physics tile
     const int64_t n_tiles = (n + tile_sz - 1) / tile_sz;
     const int64_t n_chunks = (n_tiles + blockDim.x - 1) / blockDim.x;
     const LaunchInfo info = *a.ws.info;
@@ -1021,13 +1021,15 @@ k_pair_append(PairArgs a) {
 #pragma unroll
     for (int k = 0; k < N_COUNT_USED; ++k) cnt[k] = 0;
     for (int64_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+        // tiles are one wave (64 photons) in the physics pass: each wave takes its
+        // own listed tiles and ranks their pairs with a ballot, with no block barrier
         const uint32_t m = list_tiles(a.ws.tile_cnt0, c, n_tiles, s_list, s_wave);
-        for (uint32_t qi = 0; qi < m; ++qi) {
+        for (uint32_t qi = (uint32_t)wid; qi < m; qi += (uint32_t)nw) {
             const int64_t tile = c * blockDim.x + s_list[qi];
-            const int64_t i = tile * tile_sz + tid;
-            const bool ev = tid < tile_sz && i < n && a.ph.tau[i] == -HUGE_VAL;
-            uint32_t e, tot;
-            block_scan_flag(ev, e, tot, s_wave);
+            const int64_t i = tile * tile_sz + lane;
+            const bool ev = i < n && a.ph.tau[i] == -HUGE_VAL;
+            uint32_t tot;
+            const uint32_t e = ballot_excl(ev, tot);
             if (ev) {
                 const R x = ((const R *)a.ph.x)[i], y = ((const R *)a.ph.y)[i], z = ((const R *)a.ph.z)[i];
                 const R kx = ((const R *)a.ph.ux)[i], ky = ((const R *)a.ph.uy)[i], kz = ((const R *)a.ph.uz)[i];
@@ -1074,8 +1076,8 @@ k_pair_append(PairArgs a) {
                 }
                 a.ph.tau[i] = HUGE_VAL;
             }
-            __syncthreads();
         }
+        __syncthreads();       // s_list is rewritten for the next chunk only after every wave is done
     }
     block_counts(a.tal, cnt, s_cnt);
 }
