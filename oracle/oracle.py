@@ -32,14 +32,23 @@ C_NAMES = ["emit", "push", "rec", "drop", "sub", "cap", "range", "sokolov", "mc"
            "pair", "phstep", "nan", "overflow", "_c13", "_c14", "_c15"]
 
 
+# QED_ORACLE_SANITIZE=1 selects a build with AddressSanitizer and
+# UndefinedBehaviorSanitizer (the process must preload gcc's libasan).
+SANITIZE = os.environ.get("QED_ORACLE_SANITIZE") == "1"
+if SANITIZE:
+    LIB = os.path.join(HERE, "libqed_oracle_san.so")
+
+
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (plain C11, FP64, no FMA contraction)."""
     if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= max(
             os.path.getmtime(SRC), os.path.getmtime(HDR)):
         return LIB
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-fopenmp",
-           "-ffp-contract=off", "-fno-fast-math", "-o", tmp, SRC, "-lm"]
+    opt = (["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+            "-fno-sanitize-recover=undefined"] if SANITIZE else ["-O2"])
+    cmd = ["gcc", "-std=c11"] + opt + ["-fPIC", "-shared", "-fopenmp",
+                                       "-ffp-contract=off", "-fno-fast-math", "-o", tmp, SRC, "-lm"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB
