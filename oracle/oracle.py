@@ -73,7 +73,7 @@ _u32p = C.POINTER(C.c_uint32)
 
 class Tables(C.Structure):
     _fields_ = [("e_n_chi", C.c_int32), ("e_n_q", C.c_int32),
-                ("e_lnchi0", C.c_double), ("e_inv_dlnchi", C.c_double),
+                ("e_chi_min", C.c_double), ("e_lnchi0", C.c_double), ("e_inv_dlnchi", C.c_double),
                 ("e_logit_max", C.c_double), ("e_inv_dt", C.c_double),
                 ("ln_hrad", _dp), ("ln_g", _dp), ("emit_q", _dp),
                 ("p_n_chi", C.c_int32), ("p_n_q", C.c_int32),

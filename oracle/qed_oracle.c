@@ -450,6 +450,7 @@ void or_tables_bind(or_tables *t, const or_table_spec *emit, const or_table_spec
                     const double *pair_lnh, const double *pair_q)
 {
     t->e_n_chi = emit->n_chi; t->e_n_q = emit->n_q;
+    t->e_chi_min = emit->chi_min;
     t->e_lnchi0 = log(emit->chi_min);
     t->e_inv_dlnchi = (emit->n_chi - 1) / (log(emit->chi_max) - log(emit->chi_min));
     t->e_logit_max = emit->logit_max;
@@ -464,9 +465,11 @@ void or_tables_bind(or_tables *t, const or_table_spec *emit, const or_table_spec
     t->pair_lnh = pair_lnh; t->pair_q = pair_q;
 }
 
-/* Linear interpolation in (ln chi, ln h).  Outside the node range the end
- * segment is extended (READING: the paper gives no table range); lookups above
- * the last node are reported through *out_of_range. */
+/* Linear interpolation in (ln chi, ln h).  Above the last node the end
+ * segment is extended (READING: the paper gives no table range) and the
+ * lookup is reported through *out_of_range.  Below the first node the
+ * emission lookups follow their small-chi laws instead (see or_lookup_h_rad
+ * and or_lookup_g). */
 static double lerp_rate(const double *tab, int n, double lnchi0, double inv_d,
                         double chi, int *oor)
 {
@@ -479,15 +482,26 @@ static double lerp_rate(const double *tab, int n, double lnchi0, double inv_d,
     return tab[i] + w * (tab[i + 1] - tab[i]);
 }
 
+/* READING (below the table): as chi -> 0 the photon-number rate of Eq. 2
+ * becomes the classical one, proportional to chi (h_rad -> 5 chi/(2 sqrt 3)).
+ * Below the first node h_rad is taken proportional to chi and equal to the
+ * node value there, so the lookup is continuous and keeps the classical law. */
 double or_lookup_h_rad(const or_tables *t, double chi, int *oor)
 {
     if (!(chi > 0.0)) return 0.0;
+    if (chi < t->e_chi_min) return exp(t->ln_hrad[0]) * (chi / t->e_chi_min);
     return exp(lerp_rate(t->ln_hrad, t->e_n_chi, t->e_lnchi0, t->e_inv_dlnchi, chi, oor));
 }
 
+/* READING (below the table): Eq. 5 must give the classical Larmor power as
+ * chi -> 0, i.e. g -> 1, with g = 1 - (55 sqrt 3/16) chi + O(chi^2).  Below
+ * the first node ln g is taken proportional to chi and equal to the node
+ * value there: ln g(chi) = ln g(chi_min) chi/chi_min, which tends to 0 with
+ * the first-order slope of the expansion. */
 double or_lookup_g(const or_tables *t, double chi)
 {
     if (!(chi > 0.0)) return 1.0;
+    if (chi < t->e_chi_min) return exp(t->ln_g[0] * (chi / t->e_chi_min));
     return exp(lerp_rate(t->ln_g, t->e_n_chi, t->e_lnchi0, t->e_inv_dlnchi, chi, NULL));
 }
 

@@ -84,7 +84,7 @@ int or_tables_compute(const or_table_spec *emit, const or_table_spec *pair,
 typedef struct {
     /* emission side */
     int32_t e_n_chi, e_n_q;
-    double e_lnchi0, e_inv_dlnchi, e_logit_max, e_inv_dt;
+    double e_chi_min, e_lnchi0, e_inv_dlnchi, e_logit_max, e_inv_dt;
     const double *ln_hrad, *ln_g, *emit_q;
     /* pair side */
     int32_t p_n_chi, p_n_q;
