@@ -278,14 +278,19 @@ typedef struct {
 qed_status qed_sync_status(qed_workspace *ws, qed_status_report *out /* [host] */,
                            int32_t clear, void *stream);
 
-/* Launch shape of the persistent kernels: threads per block (64..1024,
- * multiple of 64), particles per thread (1, 2 or 4), and blocks per compute
- * unit.  Zero fields take the library defaults. */
+/* Launch shape of the persistent kernels: threads per block (64, 128, 192
+ * or 256), particles per thread (1), blocks per compute unit (1..64) and an
+ * optional cap on the persistent grid (max_blocks >= 8, rounded down to a
+ * multiple of 8; 0 = no cap).  The grid is min(CUs x blocks_per_cu, tiles of
+ * the species' capacity, max_blocks), rounded to a multiple of 8; each block
+ * then walks as many tiles as the live count needs, so a small cap makes
+ * every block loop over many tiles.  Zero fields take the library defaults
+ * (256, 1, 8, no cap).  Results do not depend on the schedule. */
 typedef struct {
     int32_t block;
     int32_t items_per_thread;
     int32_t blocks_per_cu;
-    int32_t reserved;
+    int32_t max_blocks;
 } qed_schedule;
 
 /* ------------------------------------------------------------------------ *

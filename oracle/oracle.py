@@ -107,7 +107,8 @@ class Step(C.Structure):
     _fields_ = [("t", C.c_double), ("dt", C.c_double), ("seed", C.c_uint64),
                 ("rad_model", C.c_int32), ("chi_switch", C.c_double),
                 ("gamma_photon_min", C.c_double), ("chi_photon_push_min", C.c_double),
-                ("max_events", C.c_int32), ("no_recoil", C.c_int32), ("variants", C.c_int32)]
+                ("max_events", C.c_int32), ("no_recoil", C.c_int32), ("variants", C.c_int32),
+                ("rate_scale", C.c_double)]
 
 
 _lib = None
@@ -425,9 +426,9 @@ VAR_SOKOLOV_G, VAR_PAIR_MOMENTUM = 1, 2
 
 
 def make_step(t, dt, seed, rad_model=RAD_HYBRID, chi_switch=1e-3, gamma_photon_min=2.0,
-              chi_photon_push_min=1e-3, max_events=4, no_recoil=0, variants=0) -> Step:
+              chi_photon_push_min=1e-3, max_events=4, no_recoil=0, variants=0, rate_scale=1.0) -> Step:
     return Step(t, dt, seed, rad_model, chi_switch, gamma_photon_min, chi_photon_push_min,
-                max_events, no_recoil, variants)
+                max_events, no_recoil, variants, rate_scale)
 
 
 class Tally:

@@ -740,7 +740,11 @@ int or_push_emit(const or_tables *tab, const or_units *un, double q,
                  const or_step *st, uint64_t *uid_next,
                  double *tally, int64_t *count)
 {
-    const double dt = st->dt, Es = un->Es_hat, A = un->A_hat, tau0 = un->tau0_hat;
+    const double dt = st->dt, Es = un->Es_hat, tau0 = un->tau0_hat;
+    /* the rate prefactor of Eq. 6, times the test switch rate_scale (exactly
+     * A when it is 1, the default) */
+    const double A = un->A_hat * (st->rate_scale > 0.0 ? st->rate_scale : 1.0);
+    const double A_sok = un->A_hat;
     int overflow = 0;
     for (int64_t i = 0; i < L->n; ++i) {
         double x[3] = { L->x[i], L->y[i], L->z[i] };
@@ -790,7 +794,7 @@ int or_push_emit(const or_tables *tab, const or_units *un, double q,
             double tq = (st->variants & OR_VAR_SOKOLOV_G) ? tau0 * gq : tau0;
             double den = 1.0 + tq * vf;
             for (int c = 0; c < 3; ++c) dv[c] = tq * (fl[c] - v[c] * vf) / den;
-            double P = (2.0 / 3.0) * A * chi * chi * gq;
+            double P = (2.0 / 3.0) * A_sok * chi * chi * gq;
             double dvB[3] = { dv[1] * B[2] - dv[2] * B[1],
                               dv[2] * B[0] - dv[0] * B[2],
                               dv[0] * B[1] - dv[1] * B[0] };
@@ -904,7 +908,7 @@ int or_pair_create(const or_tables *tab, const or_units *un,
                    const or_step *st, uint64_t *uid_next,
                    double *tally, int64_t *count)
 {
-    const double dt = st->dt, A = un->A_hat;
+    const double dt = st->dt, A = un->A_hat * (st->rate_scale > 0.0 ? st->rate_scale : 1.0);
     int overflow = 0;
     int64_t keep = 0;
     int64_t n_step = n_limit < P->n ? n_limit : P->n;

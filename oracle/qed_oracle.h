@@ -144,6 +144,9 @@ typedef struct {
     int32_t max_events;         /* emissions per particle and step            */
     int32_t no_recoil;          /* test switch: emit without recoil           */
     int32_t variants;           /* alternative readings, OR of OR_VAR_*       */
+    double rate_scale;          /* test switch: emission and pair rates times
+                                   this (0 = 1), to find event decisions that
+                                   lie within a relative margin of the rate   */
 } or_step;
 
 /* Alternative readings: the Sokolov delta_v of Eq. 4 with tau_0 g(chi)

@@ -89,7 +89,7 @@ class qed_status_report(C.Structure):
 
 class qed_schedule(C.Structure):
     _fields_ = [("block", C.c_int32), ("items_per_thread", C.c_int32),
-                ("blocks_per_cu", C.c_int32), ("reserved", C.c_int32)]
+                ("blocks_per_cu", C.c_int32), ("max_blocks", C.c_int32)]
 
 
 class qed_bunches(C.Structure):

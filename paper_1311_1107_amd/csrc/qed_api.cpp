@@ -162,6 +162,9 @@ qed_status qed_tables_load(const qed_table_spec *emit, const qed_table_spec *pai
     d.ln_hrad_f = t->d32 + t->off[0]; d.ln_g_f = t->d32 + t->off[1]; d.emit_q_f = t->d32 + t->off[2];
     d.pair_lnh_f = t->d32 + t->off[3]; d.pair_q_f = t->d32 + t->off[4];
     d.e_n_chi = emit->n_chi; d.e_n_q = emit->n_q; d.p_n_chi = pair->n_chi; d.p_n_q = pair->n_q;
+    d.e_chi_min = emit->chi_min;
+    d.e_inv_chi_min = 1.0 / emit->chi_min;
+    d.e_h0 = std::exp(ln_hrad[0]);
     d.e_lnchi0 = std::log(emit->chi_min);
     d.e_inv_dlnchi = (emit->n_chi - 1) / (std::log(emit->chi_max) - std::log(emit->chi_min));
     d.e_logit_max = emit->logit_max;
@@ -378,19 +381,22 @@ qed_status consts_dev(const qed_units *u, double q, qed::ConstsDev &c) {
 // Launch shape of the physics passes: a persistent grid whose size is a
 // multiple of 8 (one share per XCD).
 qed_status shape(const qed_workspace *w, const qed_schedule *s, int64_t capacity, dim3 &grid, dim3 &block) {
-    int b = 256, ipt = 1, bpc = 8;
+    int b = 256, ipt = 1, bpc = 8, cap = 0;
     if (s) {
         if (s->block) b = s->block;
         if (s->items_per_thread) ipt = s->items_per_thread;
         if (s->blocks_per_cu) bpc = s->blocks_per_cu;
+        cap = s->max_blocks;
     }
     if (b < 64 || b > 256 || b % 64) return fail(QED_ERR_ARG, "schedule: block must be 64, 128, 192 or 256");
     if (ipt != 1) return fail(QED_ERR_ARG, "schedule: items_per_thread must be 1");
     if (bpc < 1 || bpc > 64) return fail(QED_ERR_ARG, "schedule: blocks_per_cu must be 1..64");
+    if (cap != 0 && cap < 8) return fail(QED_ERR_ARG, "schedule: max_blocks must be 0 or at least 8");
     const int64_t tiles = (capacity + b - 1) / b;
     if (tiles + 1 > w->max_tiles) return fail(QED_ERR_ARG, "workspace too small for %lld particles", (long long)capacity);
     int64_t g = (int64_t)w->n_cu * bpc;
     g = std::min<int64_t>(g, ((tiles + 7) / 8) * 8);
+    if (cap) g = std::min<int64_t>(g, cap);
     g = std::max<int64_t>(8, (g / 8) * 8);
     grid = dim3((unsigned)g);
     block = dim3((unsigned)b);

@@ -81,6 +81,7 @@ struct TablesDev {
     const double *ln_hrad, *ln_g, *emit_q, *pair_lnh, *pair_q;
     const float *ln_hrad_f, *ln_g_f, *emit_q_f, *pair_lnh_f, *pair_q_f;
     int e_n_chi, e_n_q, p_n_chi, p_n_q;
+    double e_chi_min, e_inv_chi_min, e_h0;   // first emission node, 1/chi there, h_rad there
     double e_lnchi0, e_inv_dlnchi, e_logit_max, e_inv_dt;
     double p_chi_min, p_lnchi0, p_inv_dlnchi, p_logit_max, p_inv_dt;
 };
@@ -112,6 +113,26 @@ __device__ __forceinline__ R lerp_rate(const R *lds, int n, R lnchi0, R inv_d, R
     const R w = u - (R)i;
     const R a = lds[i], b = lds[i + 1];
     return a + w * (b - a);
+}
+
+// Emission rate h_rad of Eq. 2 at chi_e from the table staged in LDS.  Below
+// the first node the rate follows the classical law, proportional to chi,
+// equal to the node value there; *above is set beyond the last node.
+template <typename R>
+__device__ __forceinline__ R h_rad_at(const R *s_lh, const TablesDev &tb, R lnchi0, R inv_d, R chi, bool &above) {
+    if (chi < (R)tb.e_chi_min) return (R)tb.e_h0 * (chi * (R)tb.e_inv_chi_min);
+    return Math<R>::exp_(lerp_rate<R>(s_lh, tb.e_n_chi, lnchi0, inv_d, Math<R>::log_(chi), above));
+}
+
+// g(chi_e) = P_rad / P_classical of Eq. 5 from the table staged in LDS.  Below
+// the first node ln g is proportional to chi (the first-order law
+// g = 1 - (55 sqrt 3/16) chi), equal to the node value there, so that g -> 1
+// and P_rad tends to the classical Larmor power.
+template <typename R>
+__device__ __forceinline__ R g_at(const R *s_lg, const TablesDev &tb, R lnchi0, R inv_d, R chi) {
+    if (chi < (R)tb.e_chi_min) return Math<R>::exp_(s_lg[0] * (chi * (R)tb.e_inv_chi_min));
+    bool above = false;
+    return Math<R>::exp_(lerp_rate<R>(s_lg, tb.e_n_chi, lnchi0, inv_d, Math<R>::log_(chi), above));
 }
 
 // Bilinear lookup in (ln chi, logit r) of a quantile table in global memory

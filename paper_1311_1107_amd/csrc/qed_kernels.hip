@@ -532,11 +532,7 @@ k_push_emit(PushArgs a) {
                 const R fy = q * (E[1] + (vz * B[0] - vx * B[2]));
                 const R fz = q * (E[2] + (vx * B[1] - vy * B[0]));
                 const R vf = vx * fx + vy * fy + vz * fz;
-                R g = R(1);
-                if (chi > R(0)) {
-                    bool above = false;
-                    g = Math<R>::exp_(lerp_rate<R>(s_lg, tb.e_n_chi, lnchi0, inv_d, Math<R>::log_(chi), above));
-                }
+                const R g = chi > R(0) ? g_at<R>(s_lg, tb, lnchi0, inv_d, chi) : R(1);
                 // variant: delta_v with the quantum-reduced tau_0 g(chi)
                 const R tq = (a.st.variants & VAR_SOKOLOV_G) ? tau0 * g : tau0;
                 const R tden = tq / (R(1) + tq * vf);
@@ -559,7 +555,7 @@ k_push_emit(PushArgs a) {
                 R W = R(0);
                 if (p > R(0) && ce > R(0)) {
                     bool above = false;
-                    W = Ah * Math<R>::exp_(lerp_rate<R>(s_lh, tb.e_n_chi, lnchi0, inv_d, Math<R>::log_(ce), above)) / gam;
+                    W = Ah * h_rad_at<R>(s_lh, tb, lnchi0, inv_d, ce, above) / gam;
                     if (above) cnt[C_RANGE]++;
                 }
                 double tau = a.lep.tau[i];
@@ -601,7 +597,7 @@ k_push_emit(PushArgs a) {
                         W = R(0);
                         if (p > R(0) && ce > R(0)) {
                             bool above = false;
-                            W = Ah * Math<R>::exp_(lerp_rate<R>(s_lh, tb.e_n_chi, lnchi0, inv_d, Math<R>::log_(ce), above)) / gam;
+                            W = Ah * h_rad_at<R>(s_lh, tb, lnchi0, inv_d, ce, above) / gam;
                             if (above) cnt[C_RANGE]++;
                         }
                     }

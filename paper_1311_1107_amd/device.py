@@ -233,5 +233,5 @@ def step(t, dt, seed, rad_model=B.QED_RAD_HYBRID, chi_switch=1e-3, gamma_photon_
     return s
 
 
-def schedule(block=256, items_per_thread=1, blocks_per_cu=8) -> B.qed_schedule:
-    return B.qed_schedule(block, items_per_thread, blocks_per_cu, 0)
+def schedule(block=256, items_per_thread=1, blocks_per_cu=8, max_blocks=0) -> B.qed_schedule:
+    return B.qed_schedule(block, items_per_thread, blocks_per_cu, max_blocks)
