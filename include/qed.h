@@ -307,6 +307,26 @@ qed_status qed_push_emit(const qed_tables *tab, qed_workspace *ws, const qed_uni
                          const qed_step *st, uint64_t *d_uid_next /* [device] */,
                          const qed_schedule *sched, void *stream);
 
+/* The same step as qed_push_emit for callers that cannot allocate (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * no qed_workspace; the look-back words, per-tile counts and emission
+ * records live in a static device array of the library (about 16.4 MB,
+ * held on each GPU the library runs on until the process ends), and the call
+ * makes no allocation.  lep->capacity must not exceed 131072 (QED_ERR_ARG
+ * otherwise).  d_status [device] is 6 words the caller zeroes once: the call
+ * ORs its status flags into d_status[0] (bit 0 capacity, bit 1 non-finite)
+ * and raises d_status[1..4] (needed counts: photons pushed, photons
+ * recorded) and d_status[5] to the largest value seen, as qed_sync_status
+ * reports them for a workspace.  Every call on one GPU shares the array:
+ * calls must be ordered (one stream, or synchronised), since overlapping
+ * calls on one GPU race.  The first call on a device sets the array up and
+ * synchronises that device, so it must not be made under graph capture. */
+qed_status qed_push_emit_static(const qed_tables *tab, const qed_units *u, double charge,
+                                qed_species *lep, const qed_field *f, qed_species *ph_push,
+                                qed_species *ph_rec, qed_tally *tally, const qed_step *st,
+                                uint64_t *d_uid_next /* [device] */, uint64_t *d_status /* [device] */,
+                                const qed_schedule *sched, void *stream);
+
 /* One step of pushed photons (Sec. 3 with Eq. 3): chi_gamma, optical depth
  * against the pair rate, decay into an e- e+ pair at the photon's position
  * (chi_- from the pair CDF, chi_+ = chi_gamma - chi_-, energies

@@ -115,6 +115,9 @@ _SIGS = {
     "qed_push_emit": ([_vp, _vp, _P(qed_units), C.c_double, _P(qed_species), _P(qed_field),
                        _P(qed_species), _P(qed_species), _P(qed_tally), _P(qed_step), _vp,
                        _P(qed_schedule), _vp], C.c_int32),
+    "qed_push_emit_static": ([_vp, _P(qed_units), C.c_double, _P(qed_species), _P(qed_field),
+                              _P(qed_species), _P(qed_species), _P(qed_tally), _P(qed_step), _vp, _vp,
+                              _P(qed_schedule), _vp], C.c_int32),
     "qed_pair_create": ([_vp, _vp, _P(qed_units), _P(qed_species), _P(qed_field), _P(qed_species),
                          _P(qed_species), _P(qed_tally), _P(qed_step), _vp, _P(qed_schedule), _vp], C.c_int32),
     "qed_compact": ([_vp, _P(qed_species), _P(qed_schedule), _vp], C.c_int32),
@@ -252,6 +255,14 @@ def qed_push_emit(tables, ws, units, charge, lep, field, ph_push, ph_rec, tally,
     _check(lib().qed_push_emit(tables, ws, C.byref(units), float(charge), C.byref(lep), C.byref(field),
                                _ref(ph_push), _ref(ph_rec), C.byref(tally), C.byref(step),
                                C.c_void_p(uid_next_ptr), _ref(sched), _stream(stream)))
+
+
+def qed_push_emit_static(tables, units, charge, lep, field, ph_push, ph_rec, tally, step, uid_next_ptr,
+                         status_ptr, sched=None, stream=None):
+    _check(lib().qed_push_emit_static(tables, C.byref(units), float(charge), C.byref(lep), C.byref(field),
+                                      _ref(ph_push), _ref(ph_rec), C.byref(tally), C.byref(step),
+                                      C.c_void_p(uid_next_ptr), C.c_void_p(status_ptr), _ref(sched),
+                                      _stream(stream)))
 
 
 def qed_push_emit_batched(tables, ws, units, charge, lep, bunches, ph_push, ph_rec, tally, step, uid_next_ptr,

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -380,7 +381,19 @@ qed_status consts_dev(const qed_units *u, double q, qed::ConstsDev &c) {
 
 // Launch shape of the physics passes: a persistent grid whose size is a
 // multiple of 8 (one share per XCD).
-qed_status shape(const qed_workspace *w, const qed_schedule *s, int64_t capacity, dim3 &grid, dim3 &block) {
+// What the launches need to know of a workspace: the device view, the CU
+// count for the grid and the limits of its per-tile arrays and staging.
+struct WsInfo {
+    qed::WsDev dev;
+    int n_cu;
+    int64_t max_tiles, max_leptons;
+};
+
+WsInfo info_of(const qed_workspace *w) {
+    return WsInfo{w->dev, w->n_cu, w->max_tiles, w->max_leptons};
+}
+
+qed_status shape(const WsInfo &w, const qed_schedule *s, int64_t capacity, dim3 &grid, dim3 &block) {
     int b = 256, ipt = 1, bpc = 8, cap = 0;
     if (s) {
         if (s->block) b = s->block;
@@ -393,8 +406,8 @@ qed_status shape(const qed_workspace *w, const qed_schedule *s, int64_t capacity
     if (bpc < 1 || bpc > 64) return fail(QED_ERR_ARG, "schedule: blocks_per_cu must be 1..64");
     if (cap != 0 && cap < 8) return fail(QED_ERR_ARG, "schedule: max_blocks must be 0 or at least 8");
     const int64_t tiles = (capacity + b - 1) / b;
-    if (tiles + 1 > w->max_tiles) return fail(QED_ERR_ARG, "workspace too small for %lld particles", (long long)capacity);
-    int64_t g = (int64_t)w->n_cu * bpc;
+    if (tiles + 1 > w.max_tiles) return fail(QED_ERR_ARG, "workspace too small for %lld particles", (long long)capacity);
+    int64_t g = (int64_t)w.n_cu * bpc;
     g = std::min<int64_t>(g, ((tiles + 7) / 8) * 8);
     if (cap) g = std::min<int64_t>(g, cap);
     g = std::max<int64_t>(8, (g / 8) * 8);
@@ -404,10 +417,10 @@ qed_status shape(const qed_workspace *w, const qed_schedule *s, int64_t capacity
 }
 
 // Grid of the scan pass: one block per 4096 tile counts, at most one per CU.
-dim3 scan_grid(const qed_workspace *w, int64_t capacity, int64_t tile_sz) {
+dim3 scan_grid(const WsInfo &w, int64_t capacity, int64_t tile_sz) {
     const int64_t tiles = (capacity + tile_sz - 1) / tile_sz;
     const int64_t blocks = (tiles + 4095) / 4096;
-    return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks, w->n_cu)));
+    return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks, w.n_cu)));
 }
 
 }  // namespace
@@ -464,11 +477,11 @@ qed_status qed_step_advance(int64_t *d_step, void *stream) {
     return QED_OK;
 }
 
-static qed_status push_common(const qed_tables *tab, qed_workspace *ws, const qed_units *u, double charge,
+static qed_status push_common(const qed_tables *tab, const WsInfo &ws, const qed_units *u, double charge,
                               qed_species *lep, qed::FieldDev &fd, int fk, qed_species *pp, qed_species *pr,
                               qed_tally *tally, const qed_step *st, uint64_t *uid_next, const qed_schedule *sched,
                               void *stream) {
-    if (!tab || !ws || !lep || !uid_next) return fail(QED_ERR_ARG, "qed_push_emit: null argument");
+    if (!tab || !lep || !uid_next) return fail(QED_ERR_ARG, "qed_push_emit: null argument");
     if (charge != -1.0 && charge != 1.0) return fail(QED_ERR_ARG, "qed_push_emit: charge must be -1 or +1");
     qed::PushArgs a;
     std::memset(&a, 0, sizeof a);
@@ -483,11 +496,11 @@ static qed_status push_common(const qed_tables *tab, qed_workspace *ws, const qe
     if ((s = consts_dev(u, charge, a.c))) return s;
     a.tab = tab->dev;
     a.f = fd;
-    a.ws = ws->dev;
+    a.ws = ws.dev;
     a.uid_next = uid_next;
-    if (lep->capacity > ws->max_leptons)
+    if (lep->capacity > ws.max_leptons)
         return fail(QED_ERR_ARG, "qed_push_emit: %lld leptons exceed the workspace's max_leptons %lld",
-                    (long long)lep->capacity, (long long)ws->max_leptons);
+                    (long long)lep->capacity, (long long)ws.max_leptons);
     dim3 grid, block;
     if ((s = shape(ws, sched, lep->capacity, grid, block))) return s;
     a.tile_sz = block.x;
@@ -502,7 +515,7 @@ static qed_status push_common(const qed_tables *tab, qed_workspace *ws, const qe
     sc.d1 = a.pr;
     sc.uid_next = uid_next;
     sc.mode = 0;
-    sc.ws = ws->dev;
+    sc.ws = ws.dev;
     HIP_TRY(qed::launch_scan_tiles(sc, scan_grid(ws, lep->capacity, block.x), st_));
     HIP_TRY(qed::launch_push_append(a, lep->prec, grid, dim3(256), st_));
     return QED_OK;
@@ -517,7 +530,8 @@ qed_status qed_push_emit(const qed_tables *tab, qed_workspace *ws, const qed_uni
     int fk = 0;
     qed_status s = field_dev(f, lep->prec, fd, fk);
     if (s) return s;
-    return push_common(tab, ws, u, charge, lep, fd, fk, ph_push, ph_rec, tally, st, d_uid_next, sched, stream);
+    if (!ws) return fail(QED_ERR_ARG, "qed_push_emit: null workspace");
+    return push_common(tab, info_of(ws), u, charge, lep, fd, fk, ph_push, ph_rec, tally, st, d_uid_next, sched, stream);
 }
 
 qed_status qed_push_emit_batched(const qed_tables *tab, qed_workspace *ws, const qed_units *u, double charge,
@@ -533,8 +547,146 @@ qed_status qed_push_emit_batched(const qed_tables *tab, qed_workspace *ws, const
     fd.offsets = b->offsets;
     fd.a0s = b->a0;
     fd.nper = b->n_periods;
-    return push_common(tab, ws, u, charge, lep, fd, qed::FIELD_BUNCHED, ph_push, ph_rec, tally, st, d_uid_next,
-                       sched, stream);
+    if (!ws) return fail(QED_ERR_ARG, "qed_push_emit_batched: null workspace");
+    return push_common(tab, info_of(ws), u, charge, lep, fd, qed::FIELD_BUNCHED, ph_push, ph_rec, tally, st,
+                       d_uid_next, sched, stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------- static scratch -------
+// qed_push_emit_static keeps the lepton step's scratch (look-back words,
+// per-tile counts and prefixes, emission records, ticket and status) in one
+// file-scope device array instead of a qed_workspace, for callers that cannot
+// allocate.  Each device holds its own copy until the process ends.  Host
+// code never uses the array's name for its memory: the address comes from
+// hipGetSymbolAddress, once per device.
+namespace {
+
+constexpr int64_t kStaticMaxLeptons = 131072;                      // per call
+constexpr int64_t kStaticTiles = kStaticMaxLeptons / 64 + 1;      // tiles of 64 at the smallest block
+constexpr int64_t kStaticSlots = ((kStaticMaxLeptons + 255) / 256 + 1) * 256;
+
+constexpr size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t kOffTicket = 0;
+constexpr size_t kOffStatus = 256;
+constexpr size_t kOffInfo = 512;
+constexpr size_t kOffLb = 768;
+constexpr size_t kOffTiles = kOffLb + align256(sizeof(uint64_t) * 4 * kStaticTiles);
+constexpr size_t kOffNrec = kOffTiles + align256(sizeof(uint32_t) * 4 * kStaticTiles);
+constexpr size_t kOffMeta = kOffNrec + align256(sizeof(uint32_t) * kStaticTiles);
+constexpr size_t kOffRec = kOffMeta + align256(sizeof(uint32_t) * kStaticSlots);
+constexpr size_t kStaticBytes = kOffRec + align256(sizeof(double) * qed::kRecReals * kStaticSlots);
+
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+unsigned char *g_static_ptr[kMaxDevices];      // device address of `scratch`, per device
+int g_static_ncu[kMaxDevices];
+
+// First use on a device: zero the status and the look-back words and put the
+// ticket at epoch 1 (zeroed look-back words, epoch 0, never match).  Runs
+// only while the ticket is still zero, so running it again (a replayed
+// graph) changes nothing.
+__global__ void __launch_bounds__(1024) k_static_init(unsigned char *base) {
+    __shared__ int s_fresh;
+    uint64_t *ticket = (uint64_t *)(base + kOffTicket);
+    if (threadIdx.x == 0) s_fresh = *ticket == 0ull;
+    __syncthreads();
+    if (!s_fresh) return;
+    unsigned long long *st = (unsigned long long *)(base + kOffStatus);
+    uint64_t *lb = (uint64_t *)(base + kOffLb);
+    for (int64_t i = threadIdx.x; i < 4 * kStaticTiles; i += blockDim.x) lb[i] = 0ull;
+    if (threadIdx.x < 8) st[threadIdx.x] = 0ull;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        *ticket = 1ull << 32;
+    }
+}
+
+// The call's device status into the caller's words (flags OR'ed, needed
+// counts raised to the largest), then the static status cleared.
+__global__ void k_static_status(unsigned char *base, unsigned long long *out) {
+    unsigned long long *st = (unsigned long long *)(base + kOffStatus);
+    const int k = threadIdx.x;
+    if (k < 6) {
+        const unsigned long long v = st[k];
+        if (k == 0) out[0] |= v;
+        else if (v > out[k]) out[k] = v;
+        st[k] = 0ull;
+    }
+}
+
+qed_status static_scratch(int device, unsigned char **ptr, int *n_cu) {
+    if (device < 0 || device >= kMaxDevices) return fail(QED_ERR_ARG, "qed_push_emit_static: device %d beyond %d", device, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[device]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(QED_ERR_HIP, "qed_push_emit_static: no address for the static scratch");
+        HIP_TRY(hipDeviceGetAttribute(&g_static_ncu[device], hipDeviceAttributeMultiprocessorCount, device));
+        hipLaunchKernelGGL(k_static_init, dim3(1), dim3(1024), 0, (hipStream_t)0, (unsigned char *)p);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipDeviceSynchronize());
+        g_static_ptr[device] = (unsigned char *)p;
+    }
+    *ptr = g_static_ptr[device];
+    *n_cu = g_static_ncu[device];
+    return QED_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qed_status qed_push_emit_static(const qed_tables *tab, const qed_units *u, double charge, qed_species *lep,
+                                const qed_field *f, qed_species *ph_push, qed_species *ph_rec, qed_tally *tally,
+                                const qed_step *st, uint64_t *d_uid_next, uint64_t *d_status,
+                                const qed_schedule *sched, void *stream) {
+    if (!lep || !d_status) return fail(QED_ERR_ARG, "qed_push_emit_static: null leptons or status words");
+    if (lep->capacity > kStaticMaxLeptons)
+        return fail(QED_ERR_ARG, "qed_push_emit_static: lepton capacity %lld exceeds the static scratch limit of %lld",
+                    (long long)lep->capacity, (long long)kStaticMaxLeptons);
+    qed::FieldDev fd;
+    int fk = 0;
+    qed_status s = field_dev(f, lep->prec, fd, fk);
+    if (s) return s;
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device));
+    unsigned char *base = nullptr;
+    int n_cu = 0;
+    if ((s = static_scratch(device, &base, &n_cu))) return s;
+    WsInfo w;
+    std::memset(&w, 0, sizeof w);
+    w.n_cu = n_cu;
+    w.max_tiles = kStaticTiles;
+    w.max_leptons = kStaticMaxLeptons;
+    uint64_t *lb = (uint64_t *)(base + kOffLb);
+    uint32_t *tiles = (uint32_t *)(base + kOffTiles);
+    w.dev.ticket = (uint64_t *)(base + kOffTicket);
+    w.dev.lb.agg0 = lb;
+    w.dev.lb.agg1 = lb + kStaticTiles;
+    w.dev.lb.inc0 = lb + 2 * kStaticTiles;
+    w.dev.lb.inc1 = lb + 3 * kStaticTiles;
+    w.dev.status = (unsigned long long *)(base + kOffStatus);
+    w.dev.tile_cnt0 = tiles;
+    w.dev.tile_cnt1 = tiles + kStaticTiles;
+    w.dev.tile_pre0 = tiles + 2 * kStaticTiles;
+    w.dev.tile_pre1 = tiles + 3 * kStaticTiles;
+    w.dev.info = (qed::LaunchInfo *)(base + kOffInfo);
+    w.dev.stage.rec = base + kOffRec;
+    w.dev.stage.meta = (uint32_t *)(base + kOffMeta);
+    w.dev.stage.n_rec = (uint32_t *)(base + kOffNrec);
+    w.dev.stage.slots = kStaticSlots;
+    w.dev.max_tiles = kStaticTiles;
+    if ((s = push_common(tab, w, u, charge, lep, fd, fk, ph_push, ph_rec, tally, st, d_uid_next, sched, stream)))
+        return s;
+    hipLaunchKernelGGL(k_static_status, dim3(1), dim3(64), 0, (hipStream_t)stream, base,
+                       (unsigned long long *)d_status);
+    HIP_TRY(hipGetLastError());
+    return QED_OK;
 }
 
 qed_status qed_pair_create(const qed_tables *tab, qed_workspace *ws, const qed_units *u, qed_species *ph,
@@ -557,7 +709,7 @@ qed_status qed_pair_create(const qed_tables *tab, qed_workspace *ws, const qed_u
     a.ws = ws->dev;
     a.uid_next = d_uid_next;
     dim3 grid, block;
-    if ((s = shape(ws, sched, ph->capacity, grid, block))) return s;
+    if ((s = shape(info_of(ws), sched, ph->capacity, grid, block))) return s;
     // the physics pass counts pairs per wave (tiles of 64 photons)
     const int64_t tile_sz = 64;
     if ((ph->capacity + tile_sz - 1) / tile_sz + 1 > ws->max_tiles)
@@ -575,7 +727,7 @@ qed_status qed_pair_create(const qed_tables *tab, qed_workspace *ws, const qed_u
     sc.uid_next = d_uid_next;
     sc.mode = 1;
     sc.ws = ws->dev;
-    HIP_TRY(qed::launch_scan_tiles(sc, scan_grid(ws, ph->capacity, tile_sz), st_));
+    HIP_TRY(qed::launch_scan_tiles(sc, scan_grid(info_of(ws), ph->capacity, tile_sz), st_));
     HIP_TRY(qed::launch_pair_append(a, ph->prec, fk, grid, dim3(256), st_));
     return QED_OK;
 }
@@ -588,7 +740,7 @@ qed_status qed_compact(qed_workspace *ws, qed_species *ph, const qed_schedule *s
     if ((s = species_dev(ph, false, "qed_compact", a.s))) return s;
     a.ws = ws->dev;
     dim3 grid, block;
-    if ((s = shape(ws, sched, ph->capacity, grid, block))) return s;
+    if ((s = shape(info_of(ws), sched, ph->capacity, grid, block))) return s;
     HIP_TRY(qed::launch_compact(a, ph->prec, grid, block, (hipStream_t)stream));
     return QED_OK;
 }
