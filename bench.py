@@ -1,17 +1,20 @@
 """Throughput of the QED particle step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload yee|plane|batched|cascade]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--start S] [--workload yee|coupled|plane|batched|cascade]
 
 Default workload: 1e7 electrons (ln gamma0 ~ N(ln 2000, 0.3^2)) colliding with
 a focused a0 = 200 pulse (w0 = 3 lambda, 30 fs) sampled on a 256 x 128 x 128
 FP32 Yee grid, FP64 step, photon emission, photons with chi_gamma > 1e-3 pushed
-and tested for Breit-Wheeler pairs, 2000 steps (the whole collision).
+and tested for Breit-Wheeler pairs; the collision lasts 2000 steps.
 
-The timed region is K steps from the initial state with every input resident
-in HBM: field sampling onto the grid, electron and positron push/emission,
-photon push/pair creation and periodic compaction.  W warm-up steps run first
-and the state is then reset to the initial one.  The metric counts particles
-advanced per second (leptons plus pushed photons).  Prints one JSON line.
+The run is advanced, untimed, to step S - W (default S = 1000, mid-collision,
+where the beam is inside the pulse and the photon population is building
+up); W warm-up steps follow, then the K timed steps [S, S + K) (default
+K = 1000, the rest of the collision), every input resident in HBM: field
+sampling onto the grid, electron and positron push/emission, photon
+push/pair creation, periodic compaction and cell order.  The metric counts
+particles advanced per second (leptons plus pushed photons) in the timed
+steps.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -33,10 +36,14 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=None)
     p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--start", type=int, default=1000,
+                   help="first timed step (Yee workloads): the run is advanced untimed to start - warmup")
     p.add_argument("--workload", default="yee", choices=["yee", "coupled", "plane", "batched", "cascade"])
     p.add_argument("--electrons", type=int, default=None, help="override the electron count")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=1500, help="electrons in the oracle sample")
+    p.add_argument("--cpu-min-seconds", type=float, default=1.0,
+                   help="the oracle repeats the timed window from its start state until this much time has passed")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run a 1 GiB device copy first (reference for the traffic counters)")
     p.add_argument("--compact-every", type=int, default=16)
@@ -53,26 +60,33 @@ def parse():
     return p.parse_args()
 
 
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "qed_pair_create_yee1e7_f64_traffic.md")
+TRAFFIC_SUMMARIES = {
+    "pair": os.path.join(ROOT, "profiles", "qed_pair_create_yee1e7_f64_window_traffic.md"),
+    "push": os.path.join(ROOT, "profiles", "qed_push_emit_yee1e7_f64_window_traffic.md"),
+}
 KERNEL_SOURCES = ["paper_1311_1107_amd/csrc/qed_kernels.hip", "paper_1311_1107_amd/csrc/qed_kernels.h",
                   "paper_1311_1107_amd/csrc/qed_device.h"]
 
 
-def measured_traffic():
-    """HBM bytes per qed_pair_create call from the committed counter summary,
-    or None if the kernel sources have changed since the counters were taken."""
+def kernel_source_sha256() -> str:
     import hashlib
-
-    try:
-        lines = open(TRAFFIC_SUMMARY).read().splitlines()
-    except OSError:
-        return None
-    vals = dict(l.split(": ", 1) for l in lines if l.startswith(("traffic_bytes_per_call: ", "kernel_source_sha256: ")))
     h = hashlib.sha256()
     for src in KERNEL_SOURCES:
         with open(os.path.join(ROOT, src), "rb") as f:
             h.update(f.read())
-    if vals.get("kernel_source_sha256") != h.hexdigest() or "traffic_bytes_per_call" not in vals:
+    return h.hexdigest()
+
+
+def measured_traffic(call: str):
+    """Copy-calibrated HBM bytes per call of the timed window from the
+    committed counter summary of the driver's command, or None if there is
+    none or the kernel sources have changed since the counters were taken."""
+    try:
+        lines = open(TRAFFIC_SUMMARIES[call]).read().splitlines()
+    except (OSError, KeyError):
+        return None
+    vals = dict(l.split(": ", 1) for l in lines if l.startswith(("traffic_bytes_per_call: ", "kernel_source_sha256: ")))
+    if vals.get("kernel_source_sha256") != kernel_source_sha256() or "traffic_bytes_per_call" not in vals:
         return None
     return float(vals["traffic_bytes_per_call"])
 
@@ -95,8 +109,33 @@ def device_copy_gbs(reps: int = 10) -> float:
     return 2.0 * (1 << 30) / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(wl, n_sample: int, steps: int):
-    """The oracle, single-threaded, on a fixed uid subset of the same workload."""
+def host_cpu() -> dict:
+    """The host's CPU model and core counts."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+
+
+def oracle_threads() -> int:
+    """Threads for the all-core oracle leg: OMP_NUM_THREADS if set, else the CPUs this process may use."""
+    v = os.environ.get("OMP_NUM_THREADS", "")
+    return int(v) if v.isdigit() and int(v) > 0 else len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(wl, n_sample: int, start: int, steps: int, min_seconds: float):
+    """The oracle on a fixed uid subset of the same workload.  The subset is
+    advanced (untimed, on all host cores) to the first timed step; the timed
+    window [start, start + steps) then runs single-threaded (the oracle as
+    written) and on all host cores (its OpenMP driver: the same particles),
+    each repeated from a copy of the start state until min_seconds have
+    passed.  Leptons are independent in an external field with id-keyed
+    draws, so the subset evolves as it does inside the full run."""
     import numpy as np
 
     from oracle import oracle as O
@@ -113,27 +152,60 @@ def cpu_baseline(wl, n_sample: int, steps: int):
     ph = O.new_species(80 * m) if wl.push_photons else None
     rec = O.new_species(20 * m) if wl.record_photons else None
     un = [n]
-    tally = O.Tally()
     f = wl.field
-    t0 = time.perf_counter()
-    for k in range(steps):
+    threads = oracle_threads()
+
+    def field_at(k):
         if isinstance(f, W.YeePulse):
-            field = O.make_field(O.FIELD_YEE_SEPARABLE, a0=f.a0, shape=f.shape, spacing=f.spacing,
-                                 origin=f.origin, tperp=f.tperp, tpar=f.tpar[k])
-        else:
-            field = O.make_field(O.FIELD_PLANE_WAVE, a0=f.a0, n_periods=f.n_periods)
-        st = O.make_step(k * wl.dt, wl.dt, wl.seed, chi_photon_push_min=wl.chi_photon_push_min)
-        n_ph0 = ph["n"] if ph is not None else 0
-        O.push_emit(bt, W.LAMBDA_M, -1.0, el, field, ph, rec, st, un, tally)
-        O.push_emit(bt, W.LAMBDA_M, +1.0, po, field, ph, rec, st, un, tally)
-        if ph is not None:
-            O.pair_create(bt, W.LAMBDA_M, ph, field, el, po, st, un, tally, n_limit=n_ph0)
-    dt = time.perf_counter() - t0
-    c = tally.as_dict()
-    ps = c["N_mc"] + c["N_sokolov"] + c["N_nan"] + c["N_phstep"]
-    return {"value": ps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{m} electrons (uid subset) of the same workload, {steps} steps, "
-                      f"{ps} particle-steps in {dt:.1f} s, single thread"}
+            return O.make_field(O.FIELD_YEE_SEPARABLE, a0=f.a0, shape=f.shape, spacing=f.spacing,
+                                origin=f.origin, tperp=f.tperp, tpar=f.tpar[k])
+        return O.make_field(O.FIELD_PLANE_WAVE, a0=f.a0, n_periods=f.n_periods)
+
+    def run(species, k0, k1, th, tally):
+        e, p, g, r = species
+        for k in range(k0, k1):
+            field = field_at(k)
+            st = O.make_step(k * wl.dt, wl.dt, wl.seed, chi_photon_push_min=wl.chi_photon_push_min)
+            n_ph0 = g["n"] if g is not None else 0
+            O.push_emit(bt, W.LAMBDA_M, -1.0, e, field, g, r, st, un, tally, threads=th)
+            O.push_emit(bt, W.LAMBDA_M, +1.0, p, field, g, r, st, un, tally, threads=th)
+            if g is not None:
+                O.pair_create(bt, W.LAMBDA_M, g, field, e, p, st, un, tally, n_limit=n_ph0, threads=th)
+
+    t0 = time.perf_counter()
+    run((el, po, ph, rec), 0, start, threads, O.Tally())
+    advance_s = time.perf_counter() - t0
+    state = (el, po, ph, rec)
+    uid0 = un[0]
+    live0 = {name: (sp["n"] if sp is not None else 0) for name, sp in zip(("electrons", "positrons", "photons"), state)}
+
+    def window(th):
+        total_s, total_ps, reps = 0.0, 0, 0
+        while reps == 0 or total_s < min_seconds:
+            copy = tuple({k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in sp.items()}
+                         if sp is not None else None for sp in state)
+            un[0] = uid0
+            tally = O.Tally()
+            t1 = time.perf_counter()
+            run(copy, start, start + steps, th, tally)
+            total_s += time.perf_counter() - t1
+            c = tally.as_dict()
+            total_ps += c["N_mc"] + c["N_sokolov"] + c["N_nan"] + c["N_phstep"]
+            reps += 1
+        return total_ps / total_s, total_ps // reps, reps, total_s
+
+    v1, ps1, r1, s1 = window(0)
+    va, psa, ra, sa = window(threads)
+    cpu = host_cpu()
+    return {"value": v1, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{m} electrons (uid subset) of the same workload, advanced to step {start} "
+                      f"({live0['electrons']} e-, {live0['positrons']} e+, {live0['photons']} pushed photons there, "
+                      f"{advance_s:.1f} s on {threads} threads, untimed), then steps [{start}, {start + steps}): "
+                      f"{ps1} particle-steps per pass, {r1} passes in {s1:.2f} s, single thread",
+            "cpu": cpu["model"], "nproc": cpu["nproc"], "cpus_allowed": cpu["affinity"],
+            "all_cores": {"value": va, "unit": "particle-steps/s", "cores": threads, "kind": "oracle (OpenMP driver)",
+                          "sample": f"the same window, {psa} particle-steps per pass, {ra} passes in {sa:.2f} s",
+                          "speedup_over_one_core": va / v1}}
 
 
 def batched_comparison(steps: int, seed: int = 4):
@@ -294,12 +366,15 @@ def bench_plane(args):
         res[name] = {"pss": ps / wall, "ms_per_step": wall * 1e3 / K, "kernel_ms": kms, "launches": nl,
                      "photons": len(gam), "emissions": t["N_emit"], "status": int(rc),
                      "energy_balance": _energy_balance(run, r, init_el), "gamma": gam, "K": K, "n0": n0,
-                     "lep_steps": ps, "N_push": t["N_push"], "N_rec": t["N_rec"], "N_emit": t["N_emit"]}
+                     "lep_steps": ps, "N_mc": t["N_mc"], "N_push": t["N_push"], "N_rec": t["N_rec"],
+                     "N_emit": t["N_emit"]}
         del run
         torch.cuda.empty_cache()
     f64, f32 = res["f64"], res["f32"]
     es = 8
-    lep_bytes = f64["lep_steps"] * (13 * es + 16) + f64["N_emit"] * 16 + (f64["N_push"] + f64["N_rec"]) * (8 * es + 20)
+    # tau is read and written by Monte Carlo steps only (the Sokolov branch leaves it alone)
+    lep_bytes = (f64["lep_steps"] * 13 * es + f64["N_mc"] * 16 + f64["N_emit"] * 16
+                 + (f64["N_push"] + f64["N_rec"]) * (8 * es + 20))
     push_ms = f64["kernel_ms"].get("push_e", 0.0)
     achieved = lep_bytes / (push_ms * 1e-3) / 1e9 if push_ms > 0 else 0.0
     n_l = f64["launches"].get("push_e", 1)
@@ -392,7 +467,7 @@ def bench_cascade(args):
     ph = t["N_phstep"]
     es = 4
     rec_bytes = 8 * es + 20
-    lep_bytes = lep * (13 * es + 16) + t["N_emit"] * 16 + (t["N_push"] + t["N_rec"]) * rec_bytes
+    lep_bytes = lep * 13 * es + t["N_mc"] * 16 + t["N_emit"] * 16 + (t["N_push"] + t["N_rec"]) * rec_bytes
     ph_bytes = ph * (9 * es + 16) + t["N_pair"] * (7 * es + 8 + 2 * rec_bytes)
     push_ms = kms.get("push_e", 0.0) + kms.get("push_p", 0.0)
     pair_ms = kms.get("pair", 0.0)
@@ -458,52 +533,35 @@ def main():
         print(json.dumps(out), flush=True)
         return
     coupled = args.workload == "coupled"
-    if args.workload in ("yee", "coupled"):
-        wl = W.yee_beam(n=args.electrons or 10_000_000)
-        caps = dict(photon_capacity=42 * len(wl.electrons["x"]), record_capacity=6 * len(wl.electrons["x"]),
-                    pair_capacity=len(wl.electrons["x"]) // 4)
-        prec = B.QED_F64
-        desc = ("1e7 e- (ln gamma0 ~ N(ln 2000, 0.3^2), r <= 2 lambda, x in [20,28) lambda) vs focused pulse "
-                "a0=200 w0=3 lambda 30 fs on a 256x128x128 FP32 Yee grid, TSC gather, FP64, photons with "
-                "chi_gamma>1e-3 pushed + Breit-Wheeler pairs")
-        if coupled:
-            desc += ("; coupled: the pulse sampled once, then advanced by the Yee solver with the leptons' "
-                     "Esirkepov currents (1000 physical electrons per unit weight)")
-    else:
-        raise SystemExit(f"workload {args.workload}: not wired into bench.py yet")
-    K = args.steps if args.steps is not None else wl.steps
-    K = min(K, wl.steps)
+    wl = W.yee_beam(n=args.electrons or 10_000_000)
     n0 = len(wl.electrons["x"])
+    caps = dict(photon_capacity=42 * n0, record_capacity=6 * n0, pair_capacity=n0 // 4)
+    prec = B.QED_F64
+    desc = ("1e7 e- (ln gamma0 ~ N(ln 2000, 0.3^2), r <= 2 lambda, x in [20,28) lambda) vs focused pulse "
+            "a0=200 w0=3 lambda 30 fs on a 256x128x128 FP32 Yee grid, TSC gather, FP64, photons with "
+            "chi_gamma>1e-3 pushed + Breit-Wheeler pairs, 2000-step collision")
+    if coupled:
+        desc += ("; coupled: the pulse sampled once, then advanced by the Yee solver with the leptons' "
+                 "Esirkepov currents (1000 physical electrons per unit weight)")
+    W_ = max(0, args.warmup)
+    start = max(W_, min(args.start, wl.steps - 1))
+    K = args.steps if args.steps is not None else 1000
+    K = max(1, min(K, wl.steps - start))
 
     run = S.Run(wl, prec=prec, compact_every=args.compact_every, sort_every=args.sort_every,
                 photon_sort_every=args.photon_sort_every, coupled=coupled,
                 particles_per_weight=1000.0, field_bound_block=args.bound_block, **caps)
-    init = {k: v.clone() for k, v in run.el.a.items()}
-    init_el = run.el
-
-    def reset():
-        if run.el is not init_el:                  # a sort swapped the electron buffers
-            run.alt["el"], run.el = run.el, init_el
-        for k, v in init.items():
-            run.el.a[k].copy_(v)
-        run.el.count.fill_(n0)
-        for sp in (run.po, run.ph, run.rec):
-            if sp is not None:
-                sp.count.zero_()
-        run.uid_next.fill_(n0)
-        run.tally.zero()
-        run._photon_view()
-        if run.coupled:
-            run.fill_field(0)
-            run.skipped.zero_()
-
-    for k in range(args.warmup):
+    # untimed advance into the collision, then the warm-up steps
+    for k in range(start):
         run.step(k)
+        if (k + 1) % 250 == 0:
+            torch.cuda.synchronize()
+            print(f"bench: advanced to step {k + 1}/{start}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    reset()
-    torch.cuda.synchronize()
+    tal0 = run.tally.reduce()
+    counts0 = run.counts()
 
-    # per-kernel event timing on the stream the kernels run on
+    # per-call event timing on the stream the kernels run on
     stream = torch.cuda.current_stream()
     evs = {}
 
@@ -515,19 +573,17 @@ def main():
         b.record(stream)
         evs.setdefault(kind, []).append((a, b))
 
-    def step(n):
-        run.step(n, timed=timed)
-
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for n in range(K):
-        step(n)
-        if (n + 1) % 250 == 0:                     # the host runs at most a queue's depth ahead
-            print(f"bench: step {n + 1}/{K} enqueued", file=sys.stderr, flush=True)
+    for n in range(start, start + K):
+        run.step(n, timed=timed)
+        if (n + 1 - start) % 250 == 0:                 # the host runs at most a queue's depth ahead
+            print(f"bench: step {n + 1}/{start + K} enqueued", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     rc, rep = run.ws.status(raise_on_error=False)
-    tal = run.tally.reduce()
+    tal1 = run.tally.reduce()
+    tal = {k: tal1[k] - tal0[k] for k in tal1}           # the timed steps only
     counts = run.counts()
     kernel_ms = {k: sum(a.elapsed_time(b) for a, b in v) for k, v in evs.items() if v}
     n_launch = {k: len(v) for k, v in evs.items() if v}
@@ -535,63 +591,78 @@ def main():
     lepton_steps = tal["N_mc"] + tal["N_sokolov"] + tal["N_nan"]
     photon_steps = tal["N_phstep"]
     psteps = lepton_steps + photon_steps
-    # algorithmic bytes per unit (es = 8 for FP64, 4 for FP32 reals; tau is always FP64):
-    #   lepton-step: x,u read and written 12 es, tau read and written 16 B, weight read es (energy tally)
+    # algorithmic bytes per unit (es = 8 for FP64 reals; tau is always FP64):
+    #   lepton-step: x, u read and written 12 es, weight read es (energy tally)
+    #   Monte Carlo step: tau read and written 16 B (the Sokolov branch leaves tau alone)
     #   emission event: uid read 8 B, n_event read and written 8 B
     #   stored photon: x, k, w, chi 8 es, tau 8 B, uid 8 B, n_event 4 B written
     #   photon-step: x, k, tau read 6 es + 8 B; x, tau written 3 es + 8 B
     #   pair event: photon x, k, w read 7 es, tau written 8 B, two leptons written 2 (8 es + 20 B)
-    es = 8 if prec == B.QED_F64 else 4
+    # (the grid nodes the gathers read are not counted: the counters measure them)
+    es = 8
     rec_bytes = 8 * es + 20
-    lep_bytes = lepton_steps * (13 * es + 16) + tal["N_emit"] * 16 + (tal["N_push"] + tal["N_rec"]) * rec_bytes
+    lep_bytes = (lepton_steps * 13 * es + tal["N_mc"] * 16 + tal["N_emit"] * 16
+                 + (tal["N_push"] + tal["N_rec"]) * rec_bytes)
     ph_bytes = photon_steps * (9 * es + 16) + tal["N_pair"] * (7 * es + 8 + 2 * rec_bytes)
-    push_ms = kernel_ms.get("push_e", 0) + kernel_ms.get("push_p", 0)
-    pair_ms = kernel_ms.get("pair", 0)
-    if pair_ms >= push_ms:
-        dom, dom_bytes, dom_ms, dom_n = "qed_pair_create (photon step)", ph_bytes, pair_ms, n_launch.get("pair", 1)
-    else:
-        dom, dom_bytes, dom_ms = "qed_push_emit (lepton step)", lep_bytes, push_ms
-        dom_n = n_launch.get("push_e", 0) + n_launch.get("push_p", 0)
-    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
+    calls = {
+        "qed_push_emit (lepton step: k_push_emit, k_scan_tiles, k_push_append; electrons and positrons)":
+            (lep_bytes, kernel_ms.get("push_e", 0.0) + kernel_ms.get("push_p", 0.0),
+             n_launch.get("push_e", 0) + n_launch.get("push_p", 0), "push"),
+        "qed_pair_create (photon step: k_pair_create, k_scan_tiles, k_pair_append)":
+            (ph_bytes, kernel_ms.get("pair", 0.0), n_launch.get("pair", 0), "pair"),
+    }
+    per_call = {}
+    for name, (byts, ms, nl, key) in calls.items():
+        ach = byts / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        per_call[key] = {"call": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS, "bytes_per_launch": byts / max(nl, 1),
+                         "avg_launch_ms": ms / max(nl, 1), "launches": nl}
+    dom = max(per_call, key=lambda k: per_call[k]["avg_launch_ms"] * per_call[k]["launches"])
+    roof = dict(per_call[dom])
+    roof["kernel"] = roof.pop("call")
+    # counters are taken on the driver's command (1e7 electrons, steps [1000, 1020), 5 warm-up steps)
+    default_cfg = (n0 == 10_000_000 and start == 1000 and K == 20 and W_ == 5 and args.sort_every == 16
+                   and run.photon_sort_every == 16 and args.compact_every == 16 and not coupled
+                   and args.bound_block == 0)
+    tr = measured_traffic(dom) if default_cfg else None
+    roof["traffic"] = tr
+    if tr:
+        roof["traffic_ratio"] = tr / roof["bytes_per_launch"]
 
     out = {
         "metric": "QED particle-steps/s",
         "value": psteps / wall,
         "unit": "particle-steps/s",
-        "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "n_gpus": 1, "steps": K, "warmup": W_,
         "ms_per_step": wall * 1e3 / K,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if prec == B.QED_F64 else "f32+f64",
+        "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": desc, "electrons": n0, "grid": list(wl.field.shape) if hasattr(wl.field, "shape") else None,
-                   "steps_timed": K, "dt": wl.dt, "compact_every": args.compact_every,
-                   "sort_every": args.sort_every, "photon_sort_every": run.photon_sort_every,
-                   "bound_block": args.bound_block},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     # counters were taken on the default command: 1e7 electrons, 2000 steps, sort/compact every 16
-                     "traffic": (measured_traffic() if dom.startswith("qed_pair_create") and K == 2000 and n0 == 10_000_000
-                                 and args.sort_every == 16 and run.photon_sort_every == 16
-                                 and args.compact_every == 16 and not coupled
-                                 and args.bound_block == 0 else None),
-                     "bytes_per_launch": dom_bytes / max(dom_n, 1), "avg_launch_ms": dom_ms / max(dom_n, 1)},
+        "config": {"workload": desc, "electrons": n0, "grid": list(wl.field.shape),
+                   "steps_timed": [start, start + K], "advanced_untimed_to": start - W_, "dt": wl.dt,
+                   "compact_every": args.compact_every, "sort_every": args.sort_every,
+                   "photon_sort_every": run.photon_sort_every, "bound_block": args.bound_block},
+        "roofline": roof,
+        "roofline_calls": per_call,
         "detail": {"lepton_steps": lepton_steps, "photon_steps": photon_steps, "kernel_ms": kernel_ms,
-                   "launches": n_launch, "final_counts": counts, "emissions": tal["N_emit"], "pairs": tal["N_pair"],
-                   "status": int(rc), "lepton_bytes": lep_bytes, "photon_bytes": ph_bytes,
+                   "launches": n_launch, "counts_at_start": counts0, "counts_at_end": counts,
+                   "emissions": tal["N_emit"], "pairs": tal["N_pair"], "status": int(rc),
+                   "lepton_bytes": lep_bytes, "photon_bytes": ph_bytes,
                    "photon_steps_without_gather": tal.get("N_nogather", 0)},
     }
     if coupled:
         out["detail"]["deposit_skipped"] = int(run.skipped.item())
+    del run
+    torch.cuda.empty_cache()
     if args.batched_steps > 0 and not coupled:
-        del run
-        torch.cuda.empty_cache()
         out["batched_vs_plain"] = batched_comparison(args.batched_steps)
     # measured copy bandwidth on this GPU (after the timed region), for the ratio to it
     copy_gbs = device_copy_gbs()
     out["roofline"]["copy_GBs"] = copy_gbs
-    out["roofline"]["frac_of_copy"] = achieved / copy_gbs if copy_gbs > 0 else None
+    out["roofline"]["frac_of_copy"] = out["roofline"]["achieved"] / copy_gbs if copy_gbs > 0 else None
     if not args.no_cpu_baseline and not coupled:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample, K)
+        print("bench: oracle CPU baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample, start, K, args.cpu_min_seconds)
     print(json.dumps(out), flush=True)
 
 

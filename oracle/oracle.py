@@ -159,6 +159,10 @@ def lib():
                                      C.POINTER(Field), C.POINTER(Species), C.POINTER(Species),
                                      C.POINTER(Step), _u64p, _dp, C.POINTER(C.c_int64)]
         L.or_pair_create.restype = C.c_int
+        L.or_push_emit_omp.argtypes = L.or_push_emit.argtypes + [C.c_int]
+        L.or_push_emit_omp.restype = C.c_int
+        L.or_pair_create_omp.argtypes = L.or_pair_create.argtypes + [C.c_int]
+        L.or_pair_create_omp.restype = C.c_int
         L.or_sort_by_cell.argtypes = [C.POINTER(Species), C.c_int64, C.c_int64, C.c_int64, d, d, d, d, d, d]
         L.or_sort_by_cell_bands.argtypes = [C.POINTER(Species), C.c_int64, C.c_int64, C.c_int64, d, d, d, d, d, d,
                                             C.c_int32]
@@ -444,14 +448,16 @@ class Tally:
 
 def push_emit(tabs: BoundTables, lambda_m, charge, lep: dict, field: Field,
               ph_push: dict | None, ph_rec: dict | None, step: Step, uid_next: list,
-              tally: Tally) -> int:
+              tally: Tally, threads: int = 0) -> int:
+    """One lepton step; threads > 0 runs it on that many OpenMP threads
+    (or_push_emit_omp: the same results, energy tallies to rounding)."""
     U = _units_struct(lambda_m)
     L, P, R = _species_struct(lep), _species_struct(ph_push), _species_struct(ph_rec)
     un = (C.c_uint64 * 1)(uid_next[0])
-    rc = lib().or_push_emit(C.byref(tabs.t), C.byref(U), float(charge), C.byref(L), C.byref(field),
-                            C.byref(P) if P is not None else None,
-                            C.byref(R) if R is not None else None,
-                            C.byref(step), un, _ptr(tally.t), tally.c.ctypes.data_as(C.POINTER(C.c_int64)))
+    args = (C.byref(tabs.t), C.byref(U), float(charge), C.byref(L), C.byref(field),
+            C.byref(P) if P is not None else None, C.byref(R) if R is not None else None,
+            C.byref(step), un, _ptr(tally.t), tally.c.ctypes.data_as(C.POINTER(C.c_int64)))
+    rc = lib().or_push_emit_omp(*args, int(threads)) if threads > 0 else lib().or_push_emit(*args)
     uid_next[0] = int(un[0])
     if P is not None:
         ph_push["n"] = P.n
@@ -461,14 +467,15 @@ def push_emit(tabs: BoundTables, lambda_m, charge, lep: dict, field: Field,
 
 
 def pair_create(tabs: BoundTables, lambda_m, ph: dict, field: Field, elec: dict, posi: dict,
-                step: Step, uid_next: list, tally: Tally, n_limit: int | None = None) -> int:
+                step: Step, uid_next: list, tally: Tally, n_limit: int | None = None, threads: int = 0) -> int:
+    """One photon step; threads > 0 runs it on that many OpenMP threads."""
     U = _units_struct(lambda_m)
     P, Em, Ep = _species_struct(ph), _species_struct(elec), _species_struct(posi)
     un = (C.c_uint64 * 1)(uid_next[0])
     lim = int(ph["n"]) if n_limit is None else int(n_limit)
-    rc = lib().or_pair_create(C.byref(tabs.t), C.byref(U), C.byref(P), lim, C.byref(field),
-                              C.byref(Em), C.byref(Ep), C.byref(step), un, _ptr(tally.t),
-                              tally.c.ctypes.data_as(C.POINTER(C.c_int64)))
+    args = (C.byref(tabs.t), C.byref(U), C.byref(P), lim, C.byref(field), C.byref(Em), C.byref(Ep),
+            C.byref(step), un, _ptr(tally.t), tally.c.ctypes.data_as(C.POINTER(C.c_int64)))
+    rc = lib().or_pair_create_omp(*args, int(threads)) if threads > 0 else lib().or_pair_create(*args)
     uid_next[0] = int(un[0])
     ph["n"], elec["n"], posi["n"] = P.n, Em.n, Ep.n
     return rc

@@ -994,6 +994,178 @@ int or_pair_create(const or_tables *tab, const or_units *un,
 }
 
 /* ======================================================================== *
+ * 9b. The same steps on several OpenMP threads, for timing the oracle on all
+ *     host cores: contiguous chunks run the serial steps above into private
+ *     append buffers with ids from zero, then are joined in index order.
+ * ======================================================================== */
+static or_species species_view(const or_species *s, int64_t lo, int64_t n)
+{
+    or_species v = *s;
+    v.x = s->x + lo; v.y = s->y + lo; v.z = s->z + lo;
+    v.ux = s->ux + lo; v.uy = s->uy + lo; v.uz = s->uz + lo;
+    v.tau = s->tau + lo; v.w = s->w + lo; v.chi = s->chi ? s->chi + lo : NULL;
+    v.uid = s->uid + lo; v.n_ev = s->n_ev + lo;
+    v.n = n; v.capacity = n;
+    return v;
+}
+
+static or_species species_alloc(int64_t cap)
+{
+    or_species s;
+    memset(&s, 0, sizeof s);
+    s.capacity = cap;
+    double **f[] = { &s.x, &s.y, &s.z, &s.ux, &s.uy, &s.uz, &s.tau, &s.w, &s.chi };
+    for (int k = 0; k < 9; ++k) *f[k] = (double *)malloc(sizeof(double) * (size_t)(cap > 0 ? cap : 1));
+    s.uid = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(cap > 0 ? cap : 1));
+    s.n_ev = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(cap > 0 ? cap : 1));
+    return s;
+}
+
+static void species_release(or_species *s)
+{
+    free(s->x); free(s->y); free(s->z); free(s->ux); free(s->uy); free(s->uz);
+    free(s->tau); free(s->w); free(s->chi); free(s->uid); free(s->n_ev);
+}
+
+/* Append entry j of a chunk's buffer with its final id (optical depth drawn
+ * for that id, as a new particle gets it); 0 if the buffer is full. */
+static int append_with_id(or_species *dst, const or_species *src, int64_t j, uint64_t id, uint64_t seed)
+{
+    if (!append_ok(dst)) return 0;
+    int64_t m = dst->n++;
+    dst->x[m] = src->x[j]; dst->y[m] = src->y[j]; dst->z[m] = src->z[j];
+    dst->ux[m] = src->ux[j]; dst->uy[m] = src->uy[j]; dst->uz[m] = src->uz[j];
+    dst->w[m] = src->w[j];
+    if (dst->chi) dst->chi[m] = src->chi[j];
+    dst->uid[m] = id;
+    dst->n_ev[m] = src->n_ev[j];
+    dst->tau[m] = initial_tau(seed, id);
+    return 1;
+}
+
+/* Photons of the chunks' two buffers carry ids local to their chunk, in the
+ * chunk's serial emission order over both buffers; merging the two buffers
+ * by id restores that order, and the chunk's id base makes it global. */
+static int join_appends(or_species *dst0, or_species *dst1, or_species *b0, or_species *b1,
+                        uint64_t base, uint64_t seed, int64_t *count)
+{
+    int overflow = 0;
+    int64_t i0 = 0, i1 = 0;
+    while (i0 < b0->n || i1 < b1->n) {
+        int take0 = i1 >= b1->n || (i0 < b0->n && b0->uid[i0] < b1->uid[i1]);
+        or_species *dst = take0 ? dst0 : dst1;
+        or_species *src = take0 ? b0 : b1;
+        int64_t j = take0 ? i0++ : i1++;
+        if (!append_with_id(dst, src, j, base + src->uid[j], seed)) { overflow = 1; count[OR_C_OVERFLOW]++; }
+    }
+    return overflow;
+}
+
+int or_push_emit_omp(const or_tables *tab, const or_units *un, double q,
+                     or_species *L, const or_field *f, or_species *Pp, or_species *Pr,
+                     const or_step *st, uint64_t *uid_next, double *tally, int64_t *count, int n_threads)
+{
+    int nt = n_threads > 0 ? n_threads : 1;
+    int64_t n = L->n;
+    or_species *bp = (or_species *)calloc((size_t)nt, sizeof(or_species));
+    or_species *br = (or_species *)calloc((size_t)nt, sizeof(or_species));
+    uint64_t *ids = (uint64_t *)calloc((size_t)nt, sizeof(uint64_t));
+    double *tal = (double *)calloc((size_t)nt * OR_T_N, sizeof(double));
+    int64_t *cnt = (int64_t *)calloc((size_t)nt * OR_C_N, sizeof(int64_t));
+#pragma omp parallel for schedule(static, 1) num_threads(nt)
+    for (int c = 0; c < nt; ++c) {
+        int64_t lo = n * c / nt, hi = n * (c + 1) / nt;
+        or_species lv = species_view(L, lo, hi - lo);
+        int64_t cap = (hi - lo) * (st->max_events > 0 ? st->max_events : 1);
+        bp[c] = species_alloc(Pp ? cap : 0);
+        br[c] = species_alloc(Pr ? cap : 0);
+        ids[c] = 0;
+        or_push_emit(tab, un, q, &lv, f, Pp ? &bp[c] : NULL, Pr ? &br[c] : NULL, st, &ids[c],
+                     tal + (size_t)c * OR_T_N, cnt + (size_t)c * OR_C_N);
+    }
+    int overflow = 0;
+    uint64_t base = *uid_next;
+    for (int c = 0; c < nt; ++c) {
+        overflow |= join_appends(Pp, Pr, &bp[c], &br[c], base, st->seed, count);
+        base += ids[c];
+        for (int k = 0; k < OR_T_N; ++k) tally[k] += tal[(size_t)c * OR_T_N + k];
+        for (int k = 0; k < OR_C_N; ++k) count[k] += cnt[(size_t)c * OR_C_N + k];
+        species_release(&bp[c]);
+        species_release(&br[c]);
+    }
+    *uid_next = base;
+    free(bp); free(br); free(ids); free(tal); free(cnt);
+    return overflow;
+}
+
+static void move_entries(or_species *s, int64_t to, int64_t from, int64_t m)
+{
+    if (m <= 0 || to == from) return;
+    memmove(s->x + to, s->x + from, sizeof(double) * (size_t)m);
+    memmove(s->y + to, s->y + from, sizeof(double) * (size_t)m);
+    memmove(s->z + to, s->z + from, sizeof(double) * (size_t)m);
+    memmove(s->ux + to, s->ux + from, sizeof(double) * (size_t)m);
+    memmove(s->uy + to, s->uy + from, sizeof(double) * (size_t)m);
+    memmove(s->uz + to, s->uz + from, sizeof(double) * (size_t)m);
+    memmove(s->tau + to, s->tau + from, sizeof(double) * (size_t)m);
+    memmove(s->w + to, s->w + from, sizeof(double) * (size_t)m);
+    memmove(s->chi + to, s->chi + from, sizeof(double) * (size_t)m);
+    memmove(s->uid + to, s->uid + from, sizeof(uint64_t) * (size_t)m);
+    memmove(s->n_ev + to, s->n_ev + from, sizeof(uint32_t) * (size_t)m);
+}
+
+int or_pair_create_omp(const or_tables *tab, const or_units *un, or_species *P, int64_t n_limit,
+                       const or_field *f, or_species *Em, or_species *Ep, const or_step *st,
+                       uint64_t *uid_next, double *tally, int64_t *count, int n_threads)
+{
+    int nt = n_threads > 0 ? n_threads : 1;
+    int64_t n_step = n_limit < P->n ? n_limit : P->n, tail = P->n - n_step;
+    or_species *be = (or_species *)calloc((size_t)nt, sizeof(or_species));
+    or_species *bq = (or_species *)calloc((size_t)nt, sizeof(or_species));
+    int64_t *keep = (int64_t *)calloc((size_t)nt, sizeof(int64_t));
+    uint64_t *ids = (uint64_t *)calloc((size_t)nt, sizeof(uint64_t));
+    double *tal = (double *)calloc((size_t)nt * OR_T_N, sizeof(double));
+    int64_t *cnt = (int64_t *)calloc((size_t)nt * OR_C_N, sizeof(int64_t));
+#pragma omp parallel for schedule(static, 1) num_threads(nt)
+    for (int c = 0; c < nt; ++c) {
+        int64_t lo = n_step * c / nt, hi = n_step * (c + 1) / nt;
+        or_species pv = species_view(P, lo, hi - lo);
+        be[c] = species_alloc(hi - lo);
+        bq[c] = species_alloc(hi - lo);
+        ids[c] = 0;
+        or_pair_create(tab, un, &pv, hi - lo, f, &be[c], &bq[c], st, &ids[c],
+                       tal + (size_t)c * OR_T_N, cnt + (size_t)c * OR_C_N);
+        keep[c] = pv.n;
+    }
+    int overflow = 0;
+    uint64_t base = *uid_next;
+    int64_t kept = 0;
+    for (int c = 0; c < nt; ++c) {
+        int64_t lo = n_step * c / nt;
+        move_entries(P, kept, lo, keep[c]);           /* survivors, stably */
+        kept += keep[c];
+        /* pairs: e- then e+ of each decay, ids two per pair in photon order */
+        for (int64_t j = 0; j < be[c].n; ++j) {
+            for (int side = 0; side < 2; ++side) {
+                or_species *D = side == 0 ? Em : Ep;
+                or_species *S = side == 0 ? &be[c] : &bq[c];
+                if (!append_with_id(D, S, j, base + S->uid[j], st->seed)) { overflow = 1; count[OR_C_OVERFLOW]++; }
+            }
+        }
+        base += ids[c];
+        for (int k = 0; k < OR_T_N; ++k) tally[k] += tal[(size_t)c * OR_T_N + k];
+        for (int k = 0; k < OR_C_N; ++k) count[k] += cnt[(size_t)c * OR_C_N + k];
+        species_release(&be[c]);
+        species_release(&bq[c]);
+    }
+    move_entries(P, kept, n_step, tail);              /* photons created this step */
+    P->n = kept + tail;
+    *uid_next = base;
+    free(be); free(bq); free(keep); free(ids); free(tal); free(cnt);
+    return overflow;
+}
+
+/* ======================================================================== *
  * 10. Cell ordering of a species (a PIC code's particle sort): stable by the
  *     key (i ny + j) nz + k of the Yee cell holding the particle, with
  *     i = floor((x - x0) * (1/dx)) etc.; particles outside the grid last.

@@ -195,6 +195,26 @@ int or_pair_create(const or_tables *tab, const or_units *u,
                    const or_step *st, uint64_t *uid_next,
                    double *tally, int64_t *count);
 
+/* The same two steps on n_threads OpenMP threads (for timing the oracle on
+ * all host cores).  The particles are cut into contiguous chunks, one per
+ * thread; each chunk runs or_push_emit / or_pair_create as written, into its
+ * own append buffers with ids counted from zero; the chunks are then joined
+ * in index order: ids offset by the ids of the chunks before, the new
+ * particles' optical depths drawn for their final ids, appends cut at the
+ * buffers' capacities, survivors moved down.  Particles, ids, event
+ * counters and counts are identical to the serial step; energy tallies are
+ * summed per chunk, so they agree to rounding. */
+int or_push_emit_omp(const or_tables *tab, const or_units *u, double q,
+                     or_species *lep, const or_field *f,
+                     or_species *ph_push, or_species *ph_rec,
+                     const or_step *st, uint64_t *uid_next,
+                     double *tally, int64_t *count, int n_threads);
+int or_pair_create_omp(const or_tables *tab, const or_units *u,
+                       or_species *ph, int64_t n_limit, const or_field *f,
+                       or_species *elec, or_species *posi,
+                       const or_step *st, uint64_t *uid_next,
+                       double *tally, int64_t *count, int n_threads);
+
 /* Stable reorder by Yee cell (i ny + j) nz + k, i = floor((x - x0)*(1/dx)) etc.;
  * particles outside the grid last. */
 void or_sort_by_cell(or_species *s, int64_t nx, int64_t ny, int64_t nz, double dx, double dy, double dz,

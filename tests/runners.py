@@ -11,7 +11,7 @@ from paper_1311_1107_amd.workloads import LAMBDA_M, PlaneWave, Uniform, YeePulse
 
 def oracle_run(wl, tabs: O.BoundTables, steps: int, photon_capacity=None, record_capacity=None,
                pair_capacity=None, rad_model=O.RAD_HYBRID, chi_switch=1e-3, gamma_photon_min=2.0,
-               max_events=4, start=0, lazy_grid=False, compact_every=None, sort_every=0, variants=0):
+               max_events=4, start=0, lazy_grid=False, compact_every=None, sort_every=0, variants=0, threads=0):
     n0 = len(wl.electrons["x"])
     cap_pair = pair_capacity if pair_capacity is not None else (n0 if wl.push_photons else 0)
     el = O.species_from(wl.electrons, capacity=n0 + cap_pair)
@@ -37,10 +37,10 @@ def oracle_run(wl, tabs: O.BoundTables, steps: int, photon_capacity=None, record
                          gamma_photon_min=gamma_photon_min, chi_photon_push_min=wl.chi_photon_push_min,
                          max_events=max_events, variants=variants)
         n_ph0 = ph["n"] if ph is not None else 0
-        O.push_emit(tabs, LAMBDA_M, -1.0, el, field, ph, rec, st, uid_next, tally)
-        O.push_emit(tabs, LAMBDA_M, +1.0, po, field, ph, rec, st, uid_next, tally)
+        O.push_emit(tabs, LAMBDA_M, -1.0, el, field, ph, rec, st, uid_next, tally, threads=threads)
+        O.push_emit(tabs, LAMBDA_M, +1.0, po, field, ph, rec, st, uid_next, tally, threads=threads)
         if ph is not None:
-            O.pair_create(tabs, LAMBDA_M, ph, field, el, po, st, uid_next, tally, n_limit=n_ph0)
+            O.pair_create(tabs, LAMBDA_M, ph, field, el, po, st, uid_next, tally, n_limit=n_ph0, threads=threads)
         if sort_every and isinstance(f, YeePulse) and (n + 1) % sort_every == 0:
             for sp in (el, po, ph):
                 if sp is not None:
