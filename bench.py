@@ -264,8 +264,8 @@ def batched_comparison(steps: int, seed: int = 4):
     torch.cuda.empty_cache()
     print("bench: FP64 plain bunches done", file=sys.stderr, flush=True)
 
-    def fp32_batched(sd):
-        bun = BT.Bunches(e, off, a0s, B.QED_F32, tabs, seed=sd, record_capacity=cap)
+    def batched(sd, prec=B.QED_F32):
+        bun = BT.Bunches(e, off, a0s, prec, tabs, seed=sd, record_capacity=cap)
         best, _ = bun.autotune(trial_steps=3)
         chunk = 10
         bun.capture(chunk)
@@ -275,20 +275,27 @@ def batched_comparison(steps: int, seed: int = 4):
         out["graph_steps"] = chunk
         return bun, out
 
-    bun, r_b = fp32_batched(seed)
+    bun, r_b = batched(seed)
     g_b = photon_gamma(bun)
     del bun
     torch.cuda.empty_cache()
-    bun, r_c = fp32_batched(seed + 1000)
+    bun, r_c = batched(seed + 1000)
     g_c = photon_gamma(bun)
     del bun
     torch.cuda.empty_cache()
     print("bench: FP32 batched bunches done", file=sys.stderr, flush=True)
+    # the FP64 form in the batched launch too: separates the gain of batching from that of FP32
+    bun, r_d = batched(seed, B.QED_F64)
+    del bun
+    torch.cuda.empty_cache()
+    print("bench: FP64 batched bunches done", file=sys.stderr, flush=True)
     return {
         "workload": f"{len(a0s)} bunches, {n} e- (sizes 10^U(3,6)), a0 ~ U(50,500), gamma0 ~ U(500,5000), "
                     f"plane waves, {steps} steps, photons recorded",
-        "fp64_plain": r_plain, "fp32_batched_graph": r_b,
+        "fp64_plain": r_plain, "fp32_batched_graph": r_b, "fp64_batched_graph": r_d,
         "speedup": r_plain["ms_per_step"] / r_b["ms_per_step"],
+        "speedup_of_batching_fp64": r_plain["ms_per_step"] / r_d["ms_per_step"],
+        "speedup_of_fp32_batched": r_d["ms_per_step"] / r_b["ms_per_step"],
         "ks_photon_gamma_same_seed_p": float(stats.ks_2samp(g_plain, g_b).pvalue),
         "ks_photon_gamma_seed_plus_1000_p": float(stats.ks_2samp(g_plain, g_c).pvalue),
         "ks_sample": len(g_plain),

@@ -258,7 +258,8 @@ qed_status qed_tally_reduce(const qed_tally *t, double energy[QED_N_ENERGY] /* [
  * tickets of the scan and compaction kernels, and the sticky device status.
  * max_particles bounds the capacity of any species passed with it;
  * max_leptons bounds the capacity of the lepton species given to
- * qed_push_emit (emission records take about 124 bytes per lepton).  One
+ * qed_push_emit (event items and emission records take about 268 bytes per
+ * lepton in FP64).  One
  * workspace per stream; calls sharing a workspace must not overlap in time.
  * ------------------------------------------------------------------------ */
 typedef struct qed_workspace qed_workspace;
@@ -310,9 +311,9 @@ qed_status qed_push_emit(const qed_tables *tab, qed_workspace *ws, const qed_uni
 /* The same step as qed_push_emit for callers that cannot allocate (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * no qed_workspace; the look-back words, per-tile counts and emission
- * records live in a static device array of the library (about 16.4 MB,
+ * records live in a static device array of the library (about 17.7 MB,
  * held on each GPU the library runs on until the process ends), and the call
- * makes no allocation.  lep->capacity must not exceed 131072 (QED_ERR_ARG
+ * makes no allocation.  lep->capacity must not exceed 65536 (QED_ERR_ARG
  * otherwise).  d_status [device] is 6 words the caller zeroes once: the call
  * ORs its status flags into d_status[0] (bit 0 capacity, bit 1 non-finite)
  * and raises d_status[1..4] (needed counts: photons pushed, photons

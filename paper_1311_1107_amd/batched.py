@@ -54,6 +54,7 @@ class Bunches:
         self.views = [self.el.view(int(self.offsets[b]), self.counts[b:b + 1].data_ptr(),
                                    int(self.offsets[b + 1] - self.offsets[b])) for b in range(self.nb)]
         self.fields = [D.plane_wave(float(a), n_periods) for a in self.a0s]
+        self.n_periods = float(n_periods)
         self.sched = None
         self.graph = None
         self.graph_steps = 0
@@ -76,9 +77,14 @@ class Bunches:
                                 self.sched)
         B.qed_step_advance(self.d_step.data_ptr())
 
-    def autotune(self, trial_steps: int = 3, cache_path: str | None = None):
+    def autotune(self, trial_steps: int = 3, cache_path: str | None = None, trial_time: float | None = None):
+        """Pick the schedule of the batched step.  The candidates are timed on a
+        scratch copy of the state at trial_time, by default one pulse length
+        (2 pi n_periods): the pulse then covers about half of each bunch's
+        box, so the trial steps emit as the run does in the pulse."""
         cands = [D.schedule(b, 1, bpc) for b, bpc in CANDIDATES]
-        st = D.step(0.0, DT, self.seed, rad_model=self.rad_model)
+        t = trial_time if trial_time is not None else 2.0 * np.pi * self.n_periods
+        st = D.step(t, DT, self.seed, rad_model=self.rad_model)
         best, ms = B.qed_autotune_batched(self.tables.h, self.ws.h, self.units, -1.0, self.el.struct(), self.bun,
                                           self.rec.struct(), st, cands, trial_steps, cache_path)
         self.sched = best

@@ -87,6 +87,9 @@ struct qed_workspace {
     qed::LaunchInfo *d_info;
     void *d_rec;              // emission records
     uint32_t *d_meta, *d_nrec;
+    void *d_item;             // event items of the lepton step
+    double *d_item_tau;
+    uint32_t *d_item_idx, *d_item_map;
     qed::WsDev dev;
 };
 
@@ -224,7 +227,11 @@ qed_status qed_workspace_create(int64_t max_particles, int64_t max_leptons, qed_
         hipMalloc(&w->d_info, sizeof(qed::LaunchInfo)) != hipSuccess ||
         hipMalloc(&w->d_rec, sizeof(double) * qed::kRecReals * slots) != hipSuccess ||
         hipMalloc(&w->d_meta, sizeof(uint32_t) * slots) != hipSuccess ||
-        hipMalloc(&w->d_nrec, sizeof(uint32_t) * w->max_tiles) != hipSuccess) {
+        hipMalloc(&w->d_nrec, sizeof(uint32_t) * w->max_tiles) != hipSuccess ||
+        hipMalloc(&w->d_item, sizeof(double) * qed::kItemReals * slots) != hipSuccess ||
+        hipMalloc(&w->d_item_tau, sizeof(double) * slots) != hipSuccess ||
+        hipMalloc(&w->d_item_idx, sizeof(uint32_t) * slots) != hipSuccess ||
+        hipMalloc(&w->d_item_map, sizeof(uint32_t) * slots) != hipSuccess) {
         qed_workspace_free(w);
         return fail(QED_ERR_NOMEM, "qed_workspace_create: device allocation failed");
     }
@@ -249,6 +256,10 @@ qed_status qed_workspace_create(int64_t max_particles, int64_t max_leptons, qed_
     w->dev.stage.rec = w->d_rec;
     w->dev.stage.meta = w->d_meta;
     w->dev.stage.n_rec = w->d_nrec;
+    w->dev.stage.item = w->d_item;
+    w->dev.stage.item_tau = w->d_item_tau;
+    w->dev.stage.item_idx = w->d_item_idx;
+    w->dev.stage.item_map = w->d_item_map;
     w->dev.stage.slots = slots;
     w->dev.max_tiles = w->max_tiles;
     *out = w;
@@ -265,6 +276,10 @@ void qed_workspace_free(qed_workspace *w) {
     (void)hipFree(w->d_rec);
     (void)hipFree(w->d_meta);
     (void)hipFree(w->d_nrec);
+    (void)hipFree(w->d_item);
+    (void)hipFree(w->d_item_tau);
+    (void)hipFree(w->d_item_idx);
+    (void)hipFree(w->d_item_map);
     delete w;
 }
 
@@ -332,6 +347,7 @@ qed_status field_dev(const qed_field *f, int prec, qed::FieldDev &d, int &fk) {
         if (!(f->n_periods > 0.0) || !std::isfinite(f->a0)) return fail(QED_ERR_ARG, "field: plane wave needs n_periods > 0");
         d.a0 = f->a0;
         d.Phi = 2.0 * qed::kPi * f->n_periods;
+        d.inv_Phi = 1.0 / d.Phi;
         fk = qed::FIELD_PLANE;
     } else if (f->kind == QED_FIELD_YEE) {
         if (!f->grid || f->nx < 1 || f->ny < 1 || f->nz < 1 || !(f->dx > 0) || !(f->dy > 0) || !(f->dz > 0))
@@ -501,22 +517,35 @@ static qed_status push_common(const qed_tables *tab, const WsInfo &ws, const qed
     if (lep->capacity > ws.max_leptons)
         return fail(QED_ERR_ARG, "qed_push_emit: %lld leptons exceed the workspace's max_leptons %lld",
                     (long long)lep->capacity, (long long)ws.max_leptons);
+    if (lep->capacity >= ((int64_t)1 << 32))
+        return fail(QED_ERR_ARG, "qed_push_emit: lepton capacity must be below 2^32");
     dim3 grid, block;
     if ((s = shape(ws, sched, lep->capacity, grid, block))) return s;
-    a.tile_sz = block.x;
+    a.tile_sz = qed::kWave;
     hipStream_t st_ = (hipStream_t)stream;
-    // physics pass, scan of the per-tile photon counts, photon appends
-    HIP_TRY(qed::launch_push_emit(a, lep->prec, fk, grid, block, st_));
+    // stream pass (tiles of one wave); list of the particles with events; event
+    // pass over that list in full waves; scan of the photon counts per 64
+    // events; photon appends
+    HIP_TRY(qed::launch_lepton_stream(a, lep->prec, fk, grid, block, st_));
     qed::ScanArgs sc;
     std::memset(&sc, 0, sizeof sc);
     sc.src_count = lep->d_count;
-    sc.tile_sz = block.x;
+    sc.tile_sz = qed::kWave;
+    sc.uid_next = uid_next;                  // not read in this mode
+    sc.mode = 2;
+    sc.ws = ws.dev;
+    const dim3 sg = scan_grid(ws, lep->capacity, qed::kWave);
+    HIP_TRY(qed::launch_scan_tiles(sc, sg, st_));
+    HIP_TRY(qed::launch_lepton_events(a, lep->prec, grid, block, st_));
+    std::memset(&sc, 0, sizeof sc);
+    sc.src_count = &ws.dev.info->n_items;
+    sc.tile_sz = qed::kWave;
     sc.d0 = a.pp;
     sc.d1 = a.pr;
     sc.uid_next = uid_next;
     sc.mode = 0;
     sc.ws = ws.dev;
-    HIP_TRY(qed::launch_scan_tiles(sc, scan_grid(ws, lep->capacity, block.x), st_));
+    HIP_TRY(qed::launch_scan_tiles(sc, sg, st_));
     HIP_TRY(qed::launch_push_append(a, lep->prec, grid, dim3(256), st_));
     return QED_OK;
 }
@@ -547,6 +576,7 @@ qed_status qed_push_emit_batched(const qed_tables *tab, qed_workspace *ws, const
     fd.offsets = b->offsets;
     fd.a0s = b->a0;
     fd.nper = b->n_periods;
+    fd.lds_bunches = qed::lds_bunch_bytes(b->n_bunches) <= qed::kLdsBunchBytes;
     if (!ws) return fail(QED_ERR_ARG, "qed_push_emit_batched: null workspace");
     return push_common(tab, info_of(ws), u, charge, lep, fd, qed::FIELD_BUNCHED, ph_push, ph_rec, tally, st,
                        d_uid_next, sched, stream);
@@ -563,7 +593,7 @@ qed_status qed_push_emit_batched(const qed_tables *tab, qed_workspace *ws, const
 // hipGetSymbolAddress, once per device.
 namespace {
 
-constexpr int64_t kStaticMaxLeptons = 131072;                      // per call
+constexpr int64_t kStaticMaxLeptons = 65536;                       // per call
 constexpr int64_t kStaticTiles = kStaticMaxLeptons / 64 + 1;      // tiles of 64 at the smallest block
 constexpr int64_t kStaticSlots = ((kStaticMaxLeptons + 255) / 256 + 1) * 256;
 
@@ -576,7 +606,11 @@ constexpr size_t kOffTiles = kOffLb + align256(sizeof(uint64_t) * 4 * kStaticTil
 constexpr size_t kOffNrec = kOffTiles + align256(sizeof(uint32_t) * 4 * kStaticTiles);
 constexpr size_t kOffMeta = kOffNrec + align256(sizeof(uint32_t) * kStaticTiles);
 constexpr size_t kOffRec = kOffMeta + align256(sizeof(uint32_t) * kStaticSlots);
-constexpr size_t kStaticBytes = kOffRec + align256(sizeof(double) * qed::kRecReals * kStaticSlots);
+constexpr size_t kOffItem = kOffRec + align256(sizeof(double) * qed::kRecReals * kStaticSlots);
+constexpr size_t kOffItemTau = kOffItem + align256(sizeof(double) * qed::kItemReals * kStaticSlots);
+constexpr size_t kOffItemIdx = kOffItemTau + align256(sizeof(double) * kStaticSlots);
+constexpr size_t kOffItemMap = kOffItemIdx + align256(sizeof(uint32_t) * kStaticSlots);
+constexpr size_t kStaticBytes = kOffItemMap + align256(sizeof(uint32_t) * kStaticSlots);
 
 static __device__ __align__(256) unsigned char scratch[kStaticBytes];
 
@@ -679,6 +713,10 @@ qed_status qed_push_emit_static(const qed_tables *tab, const qed_units *u, doubl
     w.dev.stage.rec = base + kOffRec;
     w.dev.stage.meta = (uint32_t *)(base + kOffMeta);
     w.dev.stage.n_rec = (uint32_t *)(base + kOffNrec);
+    w.dev.stage.item = base + kOffItem;
+    w.dev.stage.item_tau = (double *)(base + kOffItemTau);
+    w.dev.stage.item_idx = (uint32_t *)(base + kOffItemIdx);
+    w.dev.stage.item_map = (uint32_t *)(base + kOffItemMap);
     w.dev.stage.slots = kStaticSlots;
     w.dev.max_tiles = kStaticTiles;
     if ((s = push_common(tab, w, u, charge, lep, fd, fk, ph_push, ph_rec, tally, st, d_uid_next, sched, stream)))
@@ -1020,13 +1058,28 @@ qed_status qed_autotune_batched(const qed_tables *tab, qed_workspace *ws, const 
             std::fclose(fp);
         }
     }
-    // scratch copy of the mutable lepton state, restored after each trial
+    // scratch copy of the mutable lepton state, restored after each trial and
+    // whatever happens; the workspace's status words and the recorded-photon
+    // count are restored too, so trial appends leave no trace
+    struct Scratch {
+        void *saved = nullptr;
+        double *t_energy = nullptr;
+        int64_t *t_count = nullptr;
+        uint64_t *t_uid = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Scratch() {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            (void)hipFree(t_energy);
+            (void)hipFree(t_count);
+            (void)hipFree(t_uid);
+            if (saved) (void)hipFree(saved);
+        }
+    } sc;
     const size_t es = lep->prec == QED_F64 ? 8 : 4;
-    void *saved = nullptr;
     const size_t bytes = (size_t)n * (6 * es + 8 + 4);
-    if (n > 0 && hipMalloc(&saved, bytes) != hipSuccess) return fail(QED_ERR_NOMEM, "qed_autotune_batched: no scratch");
     auto copy_state = [&](bool save) -> hipError_t {
-        char *p = (char *)saved;
+        char *p = (char *)sc.saved;
         void *arr[6] = {lep->x, lep->y, lep->z, lep->ux, lep->uy, lep->uz};
         for (int k = 0; k < 6; ++k) {
             hipError_t e = save ? hipMemcpyAsync(p, arr[k], n * es, hipMemcpyDeviceToDevice, s)
@@ -1041,50 +1094,60 @@ qed_status qed_autotune_batched(const qed_tables *tab, qed_workspace *ws, const 
         return save ? hipMemcpyAsync(p, lep->n_event, n * 4, hipMemcpyDeviceToDevice, s)
                     : hipMemcpyAsync(lep->n_event, p, n * 4, hipMemcpyDeviceToDevice, s);
     };
-    // scratch tally, step counter and id counter
-    double *t_energy = nullptr;
-    int64_t *t_count = nullptr;
-    uint64_t *t_uid = nullptr;
     int64_t rec_count0 = 0;
+    unsigned long long status0[8];
+    HIP_TRY(hipMemcpy(status0, ws->d_status, sizeof status0, hipMemcpyDeviceToHost));
     if (ph_rec) HIP_TRY(hipMemcpy(&rec_count0, ph_rec->d_count, sizeof rec_count0, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMalloc(&t_energy, sizeof(double) * QED_N_ENERGY));
-    HIP_TRY(hipMalloc(&t_count, sizeof(int64_t) * QED_N_COUNT));
-    HIP_TRY(hipMalloc(&t_uid, sizeof(uint64_t)));
-    qed_tally tal{t_energy, t_count, 1};
+    if (n > 0 && hipMalloc(&sc.saved, bytes) != hipSuccess) return fail(QED_ERR_NOMEM, "qed_autotune_batched: no scratch");
+    HIP_TRY(hipMalloc(&sc.t_energy, sizeof(double) * QED_N_ENERGY));
+    HIP_TRY(hipMalloc(&sc.t_count, sizeof(int64_t) * QED_N_COUNT));
+    HIP_TRY(hipMalloc(&sc.t_uid, sizeof(uint64_t)));
+    HIP_TRY(hipEventCreate(&sc.e0));
+    HIP_TRY(hipEventCreate(&sc.e1));
     if (n > 0) HIP_TRY(copy_state(true));
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
-    qed_status rc = QED_OK;
+    qed_tally tal{sc.t_energy, sc.t_count, 1};
     double best_t = 1e300;
-    for (int c = 0; c < n_cand && rc == QED_OK; ++c) {
-        const uint64_t big = 1ull << 62;
-        HIP_TRY(hipMemcpy(t_uid, &big, sizeof big, hipMemcpyHostToDevice));
-        qed_step stc = *st;
-        stc.d_step = nullptr;
-        // one untimed warm-up step, then the timed trial
-        for (int k = 0; k <= trial_steps && rc == QED_OK; ++k) {
-            if (k == 1) HIP_TRY(hipEventRecord(e0, s));
-            stc.t = st->t + k * st->dt;
-            rc = qed_push_emit_batched(tab, ws, u, charge, lep, b, nullptr, ph_rec, &tal, &stc, t_uid, &cand[c], stream);
-        }
-        HIP_TRY(hipEventRecord(e1, s));
-        HIP_TRY(hipEventSynchronize(e1));
-        float ms = 0;
-        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-        if (rc == QED_OK && ms < best_t) { best_t = ms; *best = cand[c]; }
-        if (rc != QED_OK) rc = QED_OK;          // an invalid candidate is skipped
+    // the caller's state is first changed here: every path below restores it
+    auto restore = [&]() -> qed_status {
         if (n > 0) HIP_TRY(copy_state(false));
         HIP_TRY(hipStreamSynchronize(s));
         if (ph_rec) HIP_TRY(hipMemcpy(ph_rec->d_count, &rec_count0, sizeof rec_count0, hipMemcpyHostToDevice));
-        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(hipMemcpy(ws->d_status, status0, sizeof status0, hipMemcpyHostToDevice));
+        return QED_OK;
+    };
+    auto trials = [&]() -> qed_status {
+        for (int c = 0; c < n_cand; ++c) {
+            const uint64_t big = 1ull << 62;
+            HIP_TRY(hipMemcpy(sc.t_uid, &big, sizeof big, hipMemcpyHostToDevice));
+            qed_step stc = *st;
+            stc.d_step = nullptr;
+            // one untimed warm-up step, then the timed trial
+            qed_status rc = QED_OK;
+            for (int k = 0; k <= trial_steps && rc == QED_OK; ++k) {
+                if (k == 1) HIP_TRY(hipEventRecord(sc.e0, s));
+                stc.t = st->t + k * st->dt;
+                rc = qed_push_emit_batched(tab, ws, u, charge, lep, b, nullptr, ph_rec, &tal, &stc, sc.t_uid,
+                                           &cand[c], stream);
+            }
+            HIP_TRY(hipEventRecord(sc.e1, s));
+            HIP_TRY(hipEventSynchronize(sc.e1));
+            float ms = 0;
+            if (rc == QED_OK) {
+                HIP_TRY(hipEventElapsedTime(&ms, sc.e0, sc.e1));
+                if (ms < best_t) { best_t = ms; *best = cand[c]; }
+            }                                       // an invalid candidate is skipped
+            qed_status r = restore();
+            if (r) return r;
+        }
+        return QED_OK;
+    };
+    qed_status rc = trials();
+    if (rc) {
+        const std::string msg = g_err;
+        (void)restore();
+        g_err = msg;
+        return rc;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipFree(t_energy);
-    (void)hipFree(t_count);
-    (void)hipFree(t_uid);
-    if (saved) (void)hipFree(saved);
     if (best_t >= 1e300) return fail(QED_ERR_ARG, "qed_autotune_batched: no valid candidate");
     if (best_ms) *best_ms = best_t / trial_steps;
     if (cache_path) {

@@ -62,16 +62,29 @@ __device__ __forceinline__ double initial_tau(uint64_t seed, uint64_t uid) {
 // ------------------------------------------------------------------------
 // Real-type helpers: the FP64 form and the FP32 precision form.
 // ------------------------------------------------------------------------
+// The FP64 form uses the correctly rounded library functions.  The FP32
+// precision form uses the hardware's single-precision square root,
+// reciprocal, base-2 logarithm and exponential (V_SQRT_F32, V_RCP_F32,
+// V_LOG_F32, V_EXP_F32, each within about one ulp for the normal arguments
+// met here); their error is far below the form's 1e-5 bar on the momenta.
 template <typename R> struct Math;
 template <> struct Math<double> {
     static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
     static __device__ __forceinline__ double log_(double x) { return log(x); }
     static __device__ __forceinline__ double exp_(double x) { return exp(x); }
+    static __device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
+    static __device__ __forceinline__ double div_(double a, double b) { return a / b; }
 };
 template <> struct Math<float> {
-    static __device__ __forceinline__ float sqrt_(float x) { return sqrtf(x); }
-    static __device__ __forceinline__ float log_(float x) { return logf(x); }
-    static __device__ __forceinline__ float exp_(float x) { return expf(x); }
+    static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float log_(float x) {
+        return __builtin_amdgcn_logf(x) * 0.693147180559945309f;              // ln 2
+    }
+    static __device__ __forceinline__ float exp_(float x) {
+        return __builtin_amdgcn_exp2f(x * 1.44269504088896341f);              // log2 e
+    }
+    static __device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float div_(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 };
 
 // ------------------------------------------------------------------------

@@ -26,7 +26,7 @@ struct SpeciesDev {
 struct FieldDev {
     int kind;
     double E[3], B[3];
-    double a0, Phi;                  // plane wave: amplitude, 2 pi n_periods
+    double a0, Phi, inv_Phi;         // plane wave: amplitude, 2 pi n_periods, its reciprocal
     const float *grid;
     int64_t nx, ny, nz;
     double inv_dx, inv_dy, inv_dz, x0, y0, z0;
@@ -35,7 +35,14 @@ struct FieldDev {
     int n_bunches;                   // bunched plane waves
     const int64_t *offsets;
     const double *a0s, *nper;
+    int lds_bunches;                 // the bunch table fits kLdsBunchBytes: staged in LDS
 };
+
+// Bunch table staged in LDS by the lepton step of the batched form (offsets,
+// amplitudes, phase lengths and their reciprocals): 8 (n + 1) + 24 n bytes
+// for n bunches.
+constexpr int kLdsBunchBytes = 16384;
+__host__ __device__ constexpr int64_t lds_bunch_bytes(int64_t n) { return 8 * (n + 1) + 24 * n; }
 
 struct StepDev {
     double t, dt;
@@ -53,23 +60,34 @@ struct ConstsDev {
     double q, es_inv, A, tau0;
 };
 
-// Emission records written by the physics pass for the append pass: one per
-// particle that stored photons in the step, at slot tile * tile_size + rank.
-// Reals (SoA, stride `slots`): 0-2 position x^n, 3-5 direction u_hat, 6 weight,
-// 7-10 gamma_gamma of each event, 11-14 chi_gamma of each event.
+// Event items written by the stream pass of the lepton step for its event
+// pass: one per particle whose optical depth runs out in the step, at slot
+// tile * 64 + rank (tiles of one wave).  Reals (SoA, stride `slots`): 0-2
+// position x^n, 3-5 u after the push, 6-8 E, 9-11 B, 12 gamma after the push,
+// 13 chi_e, 14 emission rate W, 15 weight; the optical depth and the
+// particle's index in arrays of their own.
+constexpr int kItemReals = 16;
+// Emission records written by the event pass for the append pass: one per
+// event item, in item order (dense).  Reals (SoA, stride `slots`): 0-2
+// position x^n, 3-5 direction u_hat, 6 weight, 7-10 gamma_gamma of each event,
+// 11-14 chi_gamma of each event.
 constexpr int kRecReals = 15;
 struct StageDev {
+    void *item;                      // kItemReals * slots reals (double or float)
+    double *item_tau;                // per item slot
+    uint32_t *item_idx;              // per item slot: index of the particle
+    uint32_t *item_map;              // item d (dense, in particle order) -> its slot
     void *rec;                       // kRecReals * slots reals (double or float)
     uint32_t *meta;                  // per record: events (bits 0-2), destination of event k (2 bits at 3+2k)
-    uint32_t *n_rec;                 // per tile
+    uint32_t *n_rec;                 // per chunk of 64 records
     int64_t slots;
 };
 
-// Written by the scan pass for the append pass of the same launch.
+// Written by the scan passes for the passes after them in the same launch.
 struct LaunchInfo {
     int64_t base0, base1;            // counts of the two destination buffers before the launch
     uint64_t uid0;                   // first id handed out by the launch
-    int64_t pad;
+    int64_t n_items;                 // event items of the lepton step
 };
 
 struct WsDev {
@@ -119,9 +137,10 @@ struct CompactArgs {
 };
 
 // Scan pass: prefixes of the per-tile append counts of the physics pass that
-// ran over the `src` species with tiles of tile_sz; mode 0 appends photons
+// ran over *src_count units with tiles of tile_sz; mode 0 appends photons
 // (buffer 0 pushed, buffer 1 recorded, one id each), mode 1 appends pairs
-// (one electron in buffer 0 and one positron in buffer 1 per event, two ids).
+// (one electron in buffer 0 and one positron in buffer 1 per event, two ids),
+// mode 2 lists the lepton step's event items (item_map, info->n_items).
 struct ScanArgs {
     const int64_t *src_count;
     int64_t tile_sz;
@@ -131,7 +150,8 @@ struct ScanArgs {
     WsDev ws;
 };
 
-hipError_t launch_push_emit(const PushArgs &a, int prec, int fk, dim3 grid, dim3 block, hipStream_t s);
+hipError_t launch_lepton_stream(const PushArgs &a, int prec, int fk, dim3 grid, dim3 block, hipStream_t s);
+hipError_t launch_lepton_events(const PushArgs &a, int prec, dim3 grid, dim3 block, hipStream_t s);
 hipError_t launch_pair_create(const PairArgs &a, int prec, int fk, dim3 grid, dim3 block, hipStream_t s);
 hipError_t launch_scan_tiles(const ScanArgs &a, dim3 grid, hipStream_t s);
 hipError_t launch_push_append(const PushArgs &a, int prec, dim3 grid, dim3 block, hipStream_t s);

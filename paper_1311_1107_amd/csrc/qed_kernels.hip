@@ -22,31 +22,35 @@ namespace qed {
 // ------------------------------------------------------------------------
 // Plane wave from a_y = a0 sin^2(pi phi/Phi) sin(phi), phi = t - x:
 // E_y = B_z = -(da_y/dphi).
+// inv_Phi = 1/Phi is given, so that no lane divides.
 template <typename R>
-__device__ __forceinline__ R plane_wave_da(double t, R x, double a0, double Phi);
+__device__ __forceinline__ R plane_wave_da(double t, R x, double a0, double Phi, double inv_Phi);
 
 template <>
-__device__ __forceinline__ double plane_wave_da<double>(double t, double x, double a0, double Phi) {
+__device__ __forceinline__ double plane_wave_da<double>(double t, double x, double a0, double Phi, double inv_Phi) {
     const double phi = t - x;
     if (!(phi > 0.0 && phi < Phi)) return 0.0;
-    const double arg = kPi * phi / Phi;
+    const double k = kPi * inv_Phi;                    // envelope wave number pi/Phi
     double se, ce, sp, cp;
-    sincos(arg, &se, &ce);
+    sincos(k * phi, &se, &ce);
     sincos(phi, &sp, &cp);
-    return a0 * ((kPi / Phi) * (2.0 * se * ce) * sp + se * se * cp);
+    return a0 * (k * (2.0 * se * ce) * sp + se * se * cp);
 }
 
 template <>
-__device__ __forceinline__ float plane_wave_da<float>(double t, float x, double a0, double Phi) {
-    // phase formed and reduced in FP64, trigonometry in FP32
+__device__ __forceinline__ float plane_wave_da<float>(double t, float x, double a0, double Phi, double inv_Phi) {
+    // phases formed and reduced in FP64, in revolutions: the envelope's
+    // phi/(2 Phi) in [0, 1/2) and the carrier's phi/(2 pi) less its nearest
+    // integer; their sines and cosines from the hardware's single-precision
+    // V_SIN_F32 / V_COS_F32 (arguments in revolutions)
     const double phi = t - (double)x;
     if (!(phi > 0.0 && phi < Phi)) return 0.0f;
-    const float arg = (float)(kPi * phi / Phi);
-    const double red = phi - (2.0 * kPi) * rint(phi * (0.5 / kPi));
-    float se, ce, sp, cp;
-    sincosf(arg, &se, &ce);
-    sincosf((float)red, &sp, &cp);
-    return (float)a0 * ((float)(kPi / Phi) * (2.0f * se * ce) * sp + se * se * cp);
+    const double rc = phi * (0.5 / kPi);
+    const float re = (float)(phi * (0.5 * inv_Phi));
+    const float rr = (float)(rc - rint(rc));
+    const float se = __builtin_amdgcn_sinf(re), ce = __builtin_amdgcn_cosf(re);
+    const float sp = __builtin_amdgcn_sinf(rr), cp = __builtin_amdgcn_cosf(rr);
+    return (float)a0 * ((float)(kPi * inv_Phi) * (2.0f * se * ce) * sp + se * se * cp);
 }
 
 // Quadratic (TSC) weights for offset d from the nearest node.
@@ -301,12 +305,12 @@ __device__ __forceinline__ void yee_gather_wave(const FieldDev &f, bool act, R x
 
 template <typename R, int FK>
 __device__ __forceinline__ void field_at(const FieldDev &f, double t, R x, R y, R z,
-                                         double a0, double Phi, R E[3], R B[3]) {
+                                         double a0, double Phi, double inv_Phi, R E[3], R B[3]) {
     if (FK == FIELD_UNIFORM) {
         E[0] = (R)f.E[0]; E[1] = (R)f.E[1]; E[2] = (R)f.E[2];
         B[0] = (R)f.B[0]; B[1] = (R)f.B[1]; B[2] = (R)f.B[2];
     } else if (FK == FIELD_PLANE || FK == FIELD_BUNCHED) {
-        const R da = plane_wave_da<R>(t, x, a0, Phi);
+        const R da = plane_wave_da<R>(t, x, a0, Phi, inv_Phi);
         E[0] = R(0); E[1] = -da; E[2] = R(0);
         B[0] = R(0); B[1] = R(0); B[2] = -da;
     } else {
@@ -411,42 +415,79 @@ struct Emitted {
     }
 };
 
-// Physics pass of the lepton step.  Writes each particle's new state, and for
-// particles that store photons an emission record for the append pass.
-// FP32 analytic-field steps run three waves per SIMD (168 VGPRs, a few spills):
-// 7 % faster on the batched bunches than two waves with 180 VGPRs
-template <typename R, int FK>
-__global__ void __launch_bounds__(256, (sizeof(R) == 4 && FK != FIELD_YEE) ? 3 : 1)
-k_push_emit(PushArgs a) {
-    __shared__ R s_lh[kMaxChiNodes];
-    __shared__ float s_box[FK == FIELD_YEE ? kMaxWaves * kWBFloats : 1];
-    __shared__ R s_lg[kMaxChiNodes];
-    __shared__ uint32_t s_wave[3 * kMaxWaves];
-    __shared__ int64_t s_b0;
-    __shared__ double s_red[kNEnergy * kMaxWaves];
-    __shared__ int64_t s_cnt[N_COUNT_USED];
+// Bunch of each lane in the batched form (bunch b holds [offsets[b],
+// offsets[b+1])): the wave counts the offsets at or below its first particle,
+// 64 at a time, then each lane steps forward past the bunch ends before it.
+// Called by all lanes of the wave.
+__device__ __forceinline__ int lane_bunch(const int64_t *offsets, int n_bunches, int64_t first, int64_t i) {
+    int b = 0;
+    for (int base = 1; base <= n_bunches; base += kWave) {
+        const int k = base + lane_id();
+        const uint64_t m = __ballot(k <= n_bunches && offsets[k] <= first);
+        b += __popcll(m);
+        if (m != ~0ull) break;
+    }
+    while (b + 1 < n_bunches && i >= offsets[b + 1]) ++b;
+    return b;
+}
 
-    const int tid = threadIdx.x;
+// Stream pass of the lepton step.  Each wave steps its own tile of 64
+// particles, with no block barrier: field at x^n, Boris push to u_L, chi_e
+// (Eq. 1), then either the Sokolov step (Eqs. 4-5) or, for the optical-depth
+// Monte Carlo (Eqs. 6-8), the decrement of tau by W dt.  A particle whose
+// tau runs out within the step is left as it was: its state after the push
+// goes to an event item (slot tile * 64 + rank), and the event pass finishes
+// it with the other event particles in full waves.  The tile's item count
+// goes to tile_cnt0 for the scan that lists the items.
+template <typename R, int FK>
+__global__ void __launch_bounds__(256)
+k_lepton_stream(PushArgs a) {
+    __shared__ R s_lh[kMaxChiNodes];
+    __shared__ R s_lg[kMaxChiNodes];
+    __shared__ float s_box[FK == FIELD_YEE ? kMaxWaves * kWBFloats : 1];
+    __shared__ int64_t s_cnt[N_COUNT_USED];
+    extern __shared__ __align__(16) unsigned char s_dyn[];      // bunch table (batched form)
+
+    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave, nw = blockDim.x / kWave;
     const TablesDev &tb = a.tab;
-    for (int i = tid; i < tb.e_n_chi; i += blockDim.x) {
-        s_lh[i] = (R)tb.ln_hrad[i];
-        s_lg[i] = (R)tb.ln_g[i];
+    for (int k = tid; k < tb.e_n_chi; k += blockDim.x) {
+        s_lh[k] = (R)tb.ln_hrad[k];
+        s_lg[k] = (R)tb.ln_g[k];
+    }
+    // batched form: offsets, amplitudes and phase lengths 2 pi n_periods of the
+    // bunches in LDS when they fit, else read from global memory
+    const int nb = a.f.n_bunches;
+    const int64_t *b_off = a.f.offsets;
+    const double *b_a0 = a.f.a0s, *b_np = a.f.nper;
+    double *s_phi = nullptr, *s_iphi = nullptr;
+    if (FK == FIELD_BUNCHED && a.f.lds_bunches) {
+        int64_t *so = (int64_t *)s_dyn;
+        double *sa = (double *)(so + nb + 1);
+        s_phi = sa + nb;
+        s_iphi = s_phi + nb;
+        for (int k = tid; k <= nb; k += blockDim.x) so[k] = a.f.offsets[k];
+        for (int k = tid; k < nb; k += blockDim.x) {
+            sa[k] = a.f.a0s[k];
+            s_phi[k] = 2.0 * kPi * a.f.nper[k];
+            s_iphi[k] = 1.0 / s_phi[k];
+        }
+        b_off = so;
+        b_a0 = sa;
     }
     const int64_t n = *a.lep.count;
     const double t = a.st.d_step ? a.st.t + (double)(*a.st.d_step) * a.st.dt : a.st.t;
     const double dt = a.st.dt;
     const R dtr = (R)dt;
-    const int64_t tile_sz = blockDim.x;
-    const int64_t n_tiles = (n + tile_sz - 1) / tile_sz;
+    const int64_t n_chunks = (n + blockDim.x - 1) / blockDim.x;
+    const int64_t n_tiles = (n + kWave - 1) / kWave;
     const bool atomic_slots = n_tiles > a.tal.n_slots;
     const R q = (R)a.c.q, hq = R(0.5) * q * dtr;
     const R es_inv = (R)a.c.es_inv, Ah = (R)a.c.A, tau0 = (R)a.c.tau0;
     const R lnchi0 = (R)tb.e_lnchi0, inv_d = (R)tb.e_inv_dlnchi;
-    const R* qtab = emit_q_ptr<R>(tb);
     R *X = (R *)a.lep.x, *Y = (R *)a.lep.y, *Z = (R *)a.lep.z;
     R *UX = (R *)a.lep.ux, *UY = (R *)a.lep.uy, *UZ = (R *)a.lep.uz;
     const R *Wt = (const R *)a.lep.w;
-    R *rec = (R *)a.ws.stage.rec;
+    R *item = (R *)a.ws.stage.item;
     const int64_t slots = a.ws.stage.slots;
     int cnt[N_COUNT_USED];
 #pragma unroll
@@ -454,57 +495,41 @@ k_push_emit(PushArgs a) {
     __syncthreads();
 
     for (int64_t it = 0;; ++it) {
-        const int64_t tile = xcd_tile(it, n_tiles);
-        if (tile < 0) break;
-        if (FK == FIELD_BUNCHED) {
-            if (tid == 0) {
-                const int64_t first = tile * tile_sz;
-                int lo = 0, hi = a.f.n_bunches;     // offsets[lo] <= first < offsets[hi]
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (a.f.offsets[mid] <= first) lo = mid; else hi = mid;
-                }
-                s_b0 = lo;
-            }
-            __syncthreads();
-        }
-        const int64_t i = tile * tile_sz + tid;
+        const int64_t chunk = xcd_tile(it, n_chunks);
+        if (chunk < 0) break;
+        const int64_t tile = chunk * nw + wid;             // = i / 64
+        const int64_t i = chunk * blockDim.x + tid;
         const bool live = i < n;
         double en[kNEnergy];
 #pragma unroll
         for (int k = 0; k < kNEnergy; ++k) en[k] = 0.0;
-        Emitted<R> em;
-        em.n = 0;
-        R x = R(0), y = R(0), z = R(0);
-        R uhx = R(0), uhy = R(0), uhz = R(0);       // photon direction
-        R wgt = R(0);
-        // Yee field: the wave-cooperative gather (254 VGPRs in FP64, still two waves
-        // per SIMD; 3 % faster than each lane gathering its own rows)
-        constexpr bool kWaveGather = FK == FIELD_YEE;
-        R E[3], B[3];
-        if constexpr (kWaveGather)
-            yee_gather_wave<R>(a.f, live, live ? X[i] : R(0), live ? Y[i] : R(0), live ? Z[i] : R(0), E, B,
-                               s_box + (tid / kWave) * kWBFloats);
-        if (live) {
-            x = X[i]; y = Y[i]; z = Z[i];
-            const R ux = UX[i], uy = UY[i], uz = UZ[i];
-            double a0 = a.f.a0, Phi = a.f.Phi;
-            if (FK == FIELD_BUNCHED) {
-                int64_t b = s_b0;
-                while (b + 1 < a.f.n_bunches && i >= a.f.offsets[b + 1]) ++b;
-                a0 = a.f.a0s[b];
-                Phi = 2.0 * kPi * a.f.nper[b];
+        double a0 = a.f.a0, Phi = a.f.Phi, inv_Phi = a.f.inv_Phi;
+        if (FK == FIELD_BUNCHED) {
+            const int b = lane_bunch(b_off, nb, tile * kWave, i);
+            if (live) {
+                a0 = b_a0[b];
+                if (s_phi) { Phi = s_phi[b]; inv_Phi = s_iphi[b]; }
+                else { Phi = 2.0 * kPi * b_np[b]; inv_Phi = 1.0 / Phi; }
             }
-            if constexpr (!kWaveGather) field_at<R, FK>(a.f, t, x, y, z, a0, Phi, E, B);
+        }
+        const R x = live ? X[i] : R(0), y = live ? Y[i] : R(0), z = live ? Z[i] : R(0);
+        R E[3], B[3];
+        if constexpr (FK == FIELD_YEE) yee_gather_wave<R>(a.f, live, x, y, z, E, B, s_box + wid * kWBFloats);
+        bool event = false;
+        R uLx = R(0), uLy = R(0), uLz = R(0), gL = R(1), chi = R(0), W = R(0), wgt = R(0);
+        double tau = 0.0;
+        if (live) {
+            const R ux = UX[i], uy = UY[i], uz = UZ[i];
+            if constexpr (FK != FIELD_YEE) field_at<R, FK>(a.f, t, x, y, z, a0, Phi, inv_Phi, E, B);
             const R g_old = Math<R>::sqrt_(R(1) + (ux * ux + uy * uy + uz * uz));
 
             // Boris: half electric kick, magnetic rotation, half kick
             const R umx = ux + hq * E[0], umy = uy + hq * E[1], umz = uz + hq * E[2];
             const R gm = Math<R>::sqrt_(R(1) + (umx * umx + umy * umy + umz * umz));
-            const R hg = hq / gm;
+            const R hg = Math<R>::div_(hq, gm);
             const R tx = hg * B[0], ty = hg * B[1], tz = hg * B[2];
             const R t2 = tx * tx + ty * ty + tz * tz;
-            const R s2 = R(2) / (R(1) + t2);
+            const R s2 = R(2) * Math<R>::rcp_(R(1) + t2);
             const R sx = s2 * tx, sy = s2 * ty, sz = s2 * tz;
             const R px = umx + (umy * tz - umz * ty);
             const R py = umy + (umz * tx - umx * tz);
@@ -512,12 +537,12 @@ k_push_emit(PushArgs a) {
             const R qx = umx + (py * sz - pz * sy);
             const R qy = umy + (pz * sx - px * sz);
             const R qz = umz + (px * sy - py * sx);
-            const R uLx = qx + hq * E[0], uLy = qy + hq * E[1], uLz = qz + hq * E[2];
-            const R gL = Math<R>::sqrt_(R(1) + (uLx * uLx + uLy * uLy + uLz * uLz));
+            uLx = qx + hq * E[0]; uLy = qy + hq * E[1]; uLz = qz + hq * E[2];
+            gL = Math<R>::sqrt_(R(1) + (uLx * uLx + uLy * uLy + uLz * uLz));
             wgt = Wt[i];
             en[E_WORK] = (double)wgt * (double)(gL - g_old);
 
-            const R chi = chi_of<R>(es_inv, gL, uLx, uLy, uLz, E, B);
+            chi = chi_of<R>(es_inv, gL, uLx, uLy, uLz, E, B);
             R unx = uLx, uny = uLy, unz = uLz;
             R dvx = R(0), dvy = R(0), dvz = R(0);
             int rad = a.st.rad;
@@ -526,7 +551,7 @@ k_push_emit(PushArgs a) {
             if (rad == RAD_SOKOLOV || (rad == RAD_HYBRID && (double)chi < a.st.chi_switch)) {
                 // Sokolov scheme (Eq. 4) with P_rad of Eq. 5
                 cnt[C_SOKOLOV]++;
-                const R igL = R(1) / gL;
+                const R igL = Math<R>::rcp_(gL);
                 const R vx = uLx * igL, vy = uLy * igL, vz = uLz * igL;
                 const R fx = q * (E[0] + (vy * B[2] - vz * B[1]));
                 const R fy = q * (E[1] + (vz * B[0] - vx * B[2]));
@@ -535,7 +560,7 @@ k_push_emit(PushArgs a) {
                 const R g = chi > R(0) ? g_at<R>(s_lg, tb, lnchi0, inv_d, chi) : R(1);
                 // variant: delta_v with the quantum-reduced tau_0 g(chi)
                 const R tq = (a.st.variants & VAR_SOKOLOV_G) ? tau0 * g : tau0;
-                const R tden = tq / (R(1) + tq * vf);
+                const R tden = Math<R>::div_(tq, R(1) + tq * vf);
                 dvx = tden * (fx - vx * vf);
                 dvy = tden * (fy - vy * vf);
                 dvz = tden * (fz - vz * vf);
@@ -547,76 +572,161 @@ k_push_emit(PushArgs a) {
                 unz = uLz + dtr * (q * bz - Pg * uLz);
                 en[E_RAD] = (double)wgt * (double)P * dt;
             } else if (rad == RAD_MC || rad == RAD_HYBRID) {
-                // optical-depth Monte Carlo, Eqs. 6-8
+                // optical-depth Monte Carlo, Eqs. 6-8: dtau/dt = W
                 cnt[C_MC]++;
-                R p = Math<R>::sqrt_(uLx * uLx + uLy * uLy + uLz * uLz);
-                if (p > R(0)) { const R ip = R(1) / p; uhx = uLx * ip; uhy = uLy * ip; uhz = uLz * ip; }
-                R gam = gL, ce = chi;
-                R W = R(0);
-                if (p > R(0) && ce > R(0)) {
+                const R p = Math<R>::sqrt_(uLx * uLx + uLy * uLy + uLz * uLz);
+                if (p > R(0) && chi > R(0)) {
                     bool above = false;
-                    W = Ah * h_rad_at<R>(s_lh, tb, lnchi0, inv_d, ce, above) / gam;
+                    W = Math<R>::div_(Ah * h_rad_at<R>(s_lh, tb, lnchi0, inv_d, chi, above), gL);
                     if (above) cnt[C_RANGE]++;
                 }
-                double tau = a.lep.tau[i];
-                double t_left = dt;
-                uint32_t nev = 0;
-                uint64_t uid = 0;
-                int k = 0;
-                for (;;) {
-                    const double Wd = (double)W;
-                    if (!(W > R(0)) || tau > Wd * t_left) { tau -= Wd * t_left; break; }
-                    if (k == a.st.kmax) { tau -= Wd * t_left; cnt[C_CAP]++; break; }
-                    t_left -= (tau > 0.0 ? tau : 0.0) / Wd;
-                    if (k == 0) { nev = a.lep.n_ev[i]; uid = a.lep.uid[i]; }
-                    const U64x4 o = philox4x64_10(uid, (uint64_t)nev, (uint64_t)RNG_EMIT, 0ull, a.st.seed, 0ull);
-                    const double r1 = u01(o.a), r2 = u01(o.b);
-                    R xi = Math<R>::exp_(quantile<R>(qtab, tb.e_n_chi, tb.e_n_q, lnchi0, inv_d,
-                                                     tb.e_logit_max, tb.e_inv_dt, Math<R>::log_(ce), r1));
-                    if (xi > R(1)) xi = R(1);
-                    const R gg = xi * gam;
-                    cnt[C_EMIT]++;
-                    uint8_t d;
-                    R chig_k = R(0);
-                    const double eg = (double)wgt * (double)gg;
-                    if ((double)gg > a.st.gmin) {
-                        chig_k = xi * ce;
-                        if (a.pp.present && (double)chig_k > a.st.chi_push_min) { d = 0; cnt[C_PUSH]++; en[E_PUSH] += eg; }
-                        else if (a.pr.present) { d = 1; cnt[C_REC]++; en[E_REC] += eg; }
-                        else { d = 2; cnt[C_DROP]++; en[E_DROP] += eg; }
-                    } else {
-                        d = 3; cnt[C_SUB]++; en[E_SUB] += eg;
-                    }
-                    em.put(k, gg, chig_k, d);
-                    if (!a.st.no_recoil) {
-                        // Eq. 8: |p_f| = |p| - eps_gamma/c, clamped at zero
-                        p = p - gg;
-                        if (p < R(0)) p = R(0);
-                        gam = Math<R>::sqrt_(R(1) + p * p);
-                        ce = chi_of<R>(es_inv, gam, p * uhx, p * uhy, p * uhz, E, B);
-                        W = R(0);
-                        if (p > R(0) && ce > R(0)) {
-                            bool above = false;
-                            W = Ah * h_rad_at<R>(s_lh, tb, lnchi0, inv_d, ce, above) / gam;
-                            if (above) cnt[C_RANGE]++;
-                        }
-                    }
-                    tau = -log(r2);
-                    ++nev;
-                    ++k;
-                }
-                if (em.n > 0) { unx = p * uhx; uny = p * uhy; unz = p * uhz; a.lep.n_ev[i] = nev; }
-                a.lep.tau[i] = tau;
+                tau = a.lep.tau[i];
+                const double Wd = (double)W;
+                if (!(W > R(0)) || tau > Wd * dt) a.lep.tau[i] = tau - Wd * dt;
+                else event = true;                          // finished by the event pass
             }
-            const R gn = Math<R>::sqrt_(R(1) + (unx * unx + uny * uny + unz * unz));
-            const R ign = R(1) / gn;
-            X[i] = x + dtr * (unx * ign + dvx);
-            Y[i] = y + dtr * (uny * ign + dvy);
-            Z[i] = z + dtr * (unz * ign + dvz);
-            UX[i] = unx; UY[i] = uny; UZ[i] = unz;
+            if (!event) {
+                const R gn = Math<R>::sqrt_(R(1) + (unx * unx + uny * uny + unz * unz));
+                const R ign = Math<R>::rcp_(gn);
+                X[i] = x + dtr * (unx * ign + dvx);
+                Y[i] = y + dtr * (uny * ign + dvy);
+                Z[i] = z + dtr * (unz * ign + dvz);
+                UX[i] = unx; UY[i] = uny; UZ[i] = unz;
+            }
         }
+        uint32_t n_items;
+        const uint32_t rank = ballot_excl(event, n_items);
+        if (event) {
+            const int64_t sl = tile * kWave + rank;
+            const R v[kItemReals] = {x, y, z, uLx, uLy, uLz, E[0], E[1], E[2], B[0], B[1], B[2], gL, chi, W, wgt};
+#pragma unroll
+            for (int k = 0; k < kItemReals; ++k) item[k * slots + sl] = v[k];
+            a.ws.stage.item_tau[sl] = tau;
+            a.ws.stage.item_idx[sl] = (uint32_t)i;
+        }
+        if (tile < n_tiles) {
+            if (lane == 0) a.ws.tile_cnt0[tile] = n_items;
+            wave_energy<kNEnergy>(a.tal, tile, atomic_slots, en);
+        }
+    }
+    block_counts(a.tal, cnt, s_cnt);
+}
 
-        // --- emission record and the tile's append counts -----------------
+// Event pass of the lepton step.  Each wave takes 64 consecutive event items
+// (in particle order) and runs their emissions in full waves: the local-time
+// sub-loop of at most kmax events, each a Philox draw, the photon fraction
+// from the inverse CDF of Eq. 7 and the recoil of Eq. 8, the new chi_e and W
+// after it; then the particle's new momentum, position, tau and event
+// counter.  Photons to be stored go to an emission record at the item's
+// dense position; the counts of each 64-item chunk go to tile_cnt0/1 for the
+// scan of the appends.
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_lepton_events(PushArgs a) {
+    __shared__ R s_lh[kMaxChiNodes];
+    __shared__ int64_t s_cnt[N_COUNT_USED];
+
+    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave, nw = blockDim.x / kWave;
+    const TablesDev &tb = a.tab;
+    for (int k = tid; k < tb.e_n_chi; k += blockDim.x) s_lh[k] = (R)tb.ln_hrad[k];
+    const int64_t n_items = a.ws.info->n_items;
+    const int64_t n_chunks = (n_items + kWave - 1) / kWave;
+    const bool atomic_slots = n_chunks > a.tal.n_slots;
+    const double dt = a.st.dt;
+    const R dtr = (R)dt;
+    const R es_inv = (R)a.c.es_inv, Ah = (R)a.c.A;
+    const R lnchi0 = (R)tb.e_lnchi0, inv_d = (R)tb.e_inv_dlnchi;
+    const R *qtab = emit_q_ptr<R>(tb);
+    R *X = (R *)a.lep.x, *Y = (R *)a.lep.y, *Z = (R *)a.lep.z;
+    R *UX = (R *)a.lep.ux, *UY = (R *)a.lep.uy, *UZ = (R *)a.lep.uz;
+    const R *item = (const R *)a.ws.stage.item;
+    R *rec = (R *)a.ws.stage.rec;
+    const int64_t slots = a.ws.stage.slots;
+    int cnt[N_COUNT_USED];
+#pragma unroll
+    for (int k = 0; k < N_COUNT_USED; ++k) cnt[k] = 0;
+    __syncthreads();
+
+    const int64_t waves = (int64_t)gridDim.x * nw;
+    for (int64_t c = (int64_t)blockIdx.x * nw + wid; c < n_chunks; c += waves) {
+        const int64_t d = c * kWave + lane;
+        const bool have = d < n_items;
+        double en[kNEnergy];
+#pragma unroll
+        for (int k = 0; k < kNEnergy; ++k) en[k] = 0.0;
+        Emitted<R> em;
+        em.n = 0;
+        R x = R(0), y = R(0), z = R(0), uhx = R(0), uhy = R(0), uhz = R(0), wgt = R(0);
+        if (have) {
+            const int64_t sl = a.ws.stage.item_map[d];
+            const int64_t i = a.ws.stage.item_idx[sl];
+            R v[kItemReals];
+#pragma unroll
+            for (int k = 0; k < kItemReals; ++k) v[k] = item[k * slots + sl];
+            x = v[0]; y = v[1]; z = v[2];
+            const R uLx = v[3], uLy = v[4], uLz = v[5];
+            const R E[3] = {v[6], v[7], v[8]}, B[3] = {v[9], v[10], v[11]};
+            R gam = v[12], ce = v[13], W = v[14];
+            wgt = v[15];
+            double tau = a.ws.stage.item_tau[sl];
+            R p = Math<R>::sqrt_(uLx * uLx + uLy * uLy + uLz * uLz);
+            if (p > R(0)) { const R ip = Math<R>::rcp_(p); uhx = uLx * ip; uhy = uLy * ip; uhz = uLz * ip; }
+            double t_left = dt;
+            uint32_t nev = a.lep.n_ev[i];
+            const uint64_t uid = a.lep.uid[i];
+            int k = 0;
+            for (;;) {
+                const double Wd = (double)W;
+                if (!(W > R(0)) || tau > Wd * t_left) { tau -= Wd * t_left; break; }
+                if (k == a.st.kmax) { tau -= Wd * t_left; cnt[C_CAP]++; break; }
+                t_left -= (tau > 0.0 ? tau : 0.0) / Wd;
+                const U64x4 o = philox4x64_10(uid, (uint64_t)nev, (uint64_t)RNG_EMIT, 0ull, a.st.seed, 0ull);
+                const double r1 = u01(o.a), r2 = u01(o.b);
+                R xi = Math<R>::exp_(quantile<R>(qtab, tb.e_n_chi, tb.e_n_q, lnchi0, inv_d,
+                                                 tb.e_logit_max, tb.e_inv_dt, Math<R>::log_(ce), r1));
+                if (xi > R(1)) xi = R(1);
+                const R gg = xi * gam;
+                cnt[C_EMIT]++;
+                uint8_t dst;
+                R chig_k = R(0);
+                const double eg = (double)wgt * (double)gg;
+                if ((double)gg > a.st.gmin) {
+                    chig_k = xi * ce;
+                    if (a.pp.present && (double)chig_k > a.st.chi_push_min) { dst = 0; cnt[C_PUSH]++; en[E_PUSH] += eg; }
+                    else if (a.pr.present) { dst = 1; cnt[C_REC]++; en[E_REC] += eg; }
+                    else { dst = 2; cnt[C_DROP]++; en[E_DROP] += eg; }
+                } else {
+                    dst = 3; cnt[C_SUB]++; en[E_SUB] += eg;
+                }
+                em.put(k, gg, chig_k, dst);
+                if (!a.st.no_recoil) {
+                    // Eq. 8: |p_f| = |p| - eps_gamma/c, clamped at zero
+                    p = p - gg;
+                    if (p < R(0)) p = R(0);
+                    gam = Math<R>::sqrt_(R(1) + p * p);
+                    ce = chi_of<R>(es_inv, gam, p * uhx, p * uhy, p * uhz, E, B);
+                    W = R(0);
+                    if (p > R(0) && ce > R(0)) {
+                        bool above = false;
+                        W = Math<R>::div_(Ah * h_rad_at<R>(s_lh, tb, lnchi0, inv_d, ce, above), gam);
+                        if (above) cnt[C_RANGE]++;
+                    }
+                }
+                tau = -log(r2);
+                ++nev;
+                ++k;
+            }
+            const R unx = p * uhx, uny = p * uhy, unz = p * uhz;
+            const R gn = Math<R>::sqrt_(R(1) + (unx * unx + uny * uny + unz * unz));
+            const R ign = Math<R>::rcp_(gn);
+            X[i] = x + dtr * (unx * ign);
+            Y[i] = y + dtr * (uny * ign);
+            Z[i] = z + dtr * (unz * ign);
+            UX[i] = unx; UY[i] = uny; UZ[i] = unz;
+            a.lep.n_ev[i] = nev;
+            a.lep.tau[i] = tau;
+        }
+        // --- the item's emission record and the chunk's append counts -------
         uint32_t c0 = 0, c1 = 0, meta = (uint32_t)em.n;
 #pragma unroll
         for (int k = 0; k < kMaxEvents; ++k)
@@ -625,26 +735,24 @@ k_push_emit(PushArgs a) {
                 c1 += em.dst[k] == 1;
                 meta |= (uint32_t)em.dst[k] << (3 + 2 * k);
             }
-        const bool has = (c0 + c1) > 0;
-        uint32_t rank, n_rec, tot0, tot1;
-        block_rank3(has, c0, c1, rank, n_rec, tot0, tot1, s_wave);
-        if (has) {
-            const int64_t sl = tile * tile_sz + rank;
-            rec[0 * slots + sl] = x; rec[1 * slots + sl] = y; rec[2 * slots + sl] = z;
-            rec[3 * slots + sl] = uhx; rec[4 * slots + sl] = uhy; rec[5 * slots + sl] = uhz;
-            rec[6 * slots + sl] = wgt;
+        if (have) {
+            if (c0 + c1 > 0) {
+                rec[0 * slots + d] = x; rec[1 * slots + d] = y; rec[2 * slots + d] = z;
+                rec[3 * slots + d] = uhx; rec[4 * slots + d] = uhy; rec[5 * slots + d] = uhz;
+                rec[6 * slots + d] = wgt;
 #pragma unroll
-            for (int k = 0; k < kMaxEvents; ++k)
-                if (k < em.n) { rec[(7 + k) * slots + sl] = em.gg[k]; rec[(11 + k) * slots + sl] = em.chig[k]; }
-            a.ws.stage.meta[sl] = meta;
+                for (int k = 0; k < kMaxEvents; ++k)
+                    if (k < em.n) { rec[(7 + k) * slots + d] = em.gg[k]; rec[(11 + k) * slots + d] = em.chig[k]; }
+            }
+            a.ws.stage.meta[d] = meta;
         }
-        if (tid == 0) {
-            a.ws.tile_cnt0[tile] = tot0;
-            a.ws.tile_cnt1[tile] = tot1;
-            a.ws.stage.n_rec[tile] = n_rec;
+        const uint32_t t0 = wave_sum_u32(c0), t1 = wave_sum_u32(c1);
+        if (lane == 0) {
+            a.ws.tile_cnt0[c] = t0;
+            a.ws.tile_cnt1[c] = t1;
+            a.ws.stage.n_rec[c] = (uint32_t)(n_items - c * kWave < kWave ? n_items - c * kWave : kWave);
         }
-        tile_energy<kNEnergy>(a.tal, tile, atomic_slots, en, s_red);
-        __syncthreads();
+        wave_energy<kNEnergy>(a.tal, c, atomic_slots, en);
     }
     block_counts(a.tal, cnt, s_cnt);
 }
@@ -669,7 +777,8 @@ k_scan_tiles(ScanArgs a) {
     const int64_t n_st = (n_tiles + per - 1) / per;
     const int64_t base0 = a.d0.present ? *a.d0.count : 0;
     const int64_t base1 = a.d1.present ? *a.d1.count : 0;
-    const uint64_t uid0 = *a.uid_next;
+    // the item list (mode 2) hands out no ids and has no id counter
+    const uint64_t uid0 = a.mode == 2 ? 0ull : *a.uid_next;
     __syncthreads();
     for (;;) {
         if (tid == 0) s_ticket = atomicAdd((unsigned long long *)a.ws.ticket, 1ull);
@@ -681,10 +790,16 @@ k_scan_tiles(ScanArgs a) {
             if (tid == 0 && st == n_st + (int64_t)gridDim.x - 1) {
                 uint32_t t0 = 0, t1 = 0;
                 if (n_st > 0) lb_wait_inclusive(a.ws.lb, n_st - 1, epoch, t0, t1);
-                a.ws.info->base0 = base0;
-                a.ws.info->base1 = base1;
-                a.ws.info->uid0 = uid0;
-                if (a.mode == 0) {
+                if (a.mode == 2) {
+                    a.ws.info->n_items = (int64_t)t0;
+                } else {
+                    a.ws.info->base0 = base0;
+                    a.ws.info->base1 = base1;
+                    a.ws.info->uid0 = uid0;
+                }
+                if (a.mode == 2) {
+                    // the item list needs no destination counts or ids
+                } else if (a.mode == 0) {
                     if (a.d0.present) {
                         int64_t want = base0 + (int64_t)t0;
                         if (want > a.d0.cap) { status_flag(a.ws.status, 1ull); status_need(a.ws.status, 0, want); want = a.d0.cap; }
@@ -716,7 +831,7 @@ k_scan_tiles(ScanArgs a) {
         for (int j = 0; j < kScanItems; ++j) {
             const int64_t idx = b + j;
             v0[j] = idx < n_tiles ? a.ws.tile_cnt0[idx] : 0u;
-            v1[j] = idx < n_tiles ? a.ws.tile_cnt1[idx] : 0u;
+            v1[j] = idx < n_tiles && a.mode != 2 ? a.ws.tile_cnt1[idx] : 0u;
             s0 += v0[j];
             s1 += v1[j];
         }
@@ -732,7 +847,14 @@ k_scan_tiles(ScanArgs a) {
 #pragma unroll
         for (int j = 0; j < kScanItems; ++j) {
             const int64_t idx = b + j;
-            if (idx < n_tiles) { a.ws.tile_pre0[idx] = r0; a.ws.tile_pre1[idx] = r1; }
+            if (idx < n_tiles) {
+                a.ws.tile_pre0[idx] = r0;
+                a.ws.tile_pre1[idx] = r1;
+                // mode 2: item r0 + m of the list is the tile's m-th, at slot idx * tile_sz + m
+                if (a.mode == 2)
+                    for (uint32_t m = 0; m < v0[j]; ++m)
+                        a.ws.stage.item_map[r0 + m] = (uint32_t)(idx * a.tile_sz + m);
+            }
             r0 += v0[j];
             r1 += v1[j];
         }
@@ -753,14 +875,15 @@ __device__ __forceinline__ uint32_t list_tiles(const uint32_t *cnt, int64_t c, i
     return m;
 }
 
-// Append pass of the lepton step: photons from the emission records, at the
-// offsets of the scan pass, with ids in the parents' serial order.
+// Append pass of the lepton step: photons from the emission records of the
+// event pass (chunks of 64 items), at the offsets of the scan pass, with ids
+// in the parents' serial order.
 template <typename R>
 __global__ void __launch_bounds__(256)
 k_push_append(PushArgs a) {
     __shared__ int64_t s_cnt[N_COUNT_USED];
-    const int64_t n = *a.lep.count;
-    const int64_t tile_sz = a.tile_sz;
+    const int64_t n = a.ws.info->n_items;
+    const int64_t tile_sz = kWave;
     const int64_t n_tiles = (n + tile_sz - 1) / tile_sz;
     const LaunchInfo info = *a.ws.info;
     const R dtr = (R)a.st.dt;
@@ -770,15 +893,14 @@ k_push_append(PushArgs a) {
     int cnt[N_COUNT_USED];
 #pragma unroll
     for (int k = 0; k < N_COUNT_USED; ++k) cnt[k] = 0;
-    // the block walks the physics blocks' tiles (same grid, same XCD), one
-    // tile per wave; a wave writes a tile's records 64 at a time, in order
+    // one chunk of records per wave (XCD-contiguous ranges of chunks)
     for (int64_t it = wid;; it += nw) {
         const int64_t tile = xcd_tile(it, n_tiles);
         if (tile < 0) break;
         const uint32_t nrec = a.ws.stage.n_rec[tile];
         if (nrec == 0u) continue;
         uint32_t base0 = a.ws.tile_pre0[tile], base1 = a.ws.tile_pre1[tile];
-        for (uint32_t r0 = 0; r0 < nrec; r0 += kWave) {
+        for (uint32_t r0 = 0; r0 < nrec; r0 += kWave) {    // one round: chunks hold 64 records
             const uint32_t r = r0 + (uint32_t)lane;
             const bool have = r < nrec;
             const int64_t sl = tile * tile_sz + r;
@@ -957,11 +1079,11 @@ k_pair_create(PairArgs a) {
             }
         }
         if (live) {
-            if constexpr (FK != FIELD_YEE) field_at<R, FK>(a.f, t, x, y, z, a.f.a0, a.f.Phi, E, B);
+            if constexpr (FK != FIELD_YEE) field_at<R, FK>(a.f, t, x, y, z, a.f.a0, a.f.Phi, a.f.inv_Phi, E, B);
             const R chig = chi_of<R>(es_inv, kk, kx, ky, kz, E, B);
             cnt[C_PHSTEP]++;
             R Wp = R(0);
-            const R ik = R(1) / kk;
+            const R ik = Math<R>::rcp_(kk);
             if (kk > R(2) && chig >= chi_min) {
                 bool above = false;
                 const R l = lerp_rate<R>(s_lp, tb.p_n_chi, lnchi0, inv_d, Math<R>::log_(chig), above);
@@ -1031,7 +1153,7 @@ k_pair_append(PairArgs a) {
                 const R kx = ((const R *)a.ph.ux)[i], ky = ((const R *)a.ph.uy)[i], kz = ((const R *)a.ph.uz)[i];
                 const R wgt = ((const R *)a.ph.w)[i];
                 R E[3], B[3];
-                field_at<R, FK>(a.f, t, x, y, z, a.f.a0, a.f.Phi, E, B);
+                field_at<R, FK>(a.f, t, x, y, z, a.f.a0, a.f.Phi, a.f.inv_Phi, E, B);
                 const R kk = Math<R>::sqrt_(fma(kz, kz, fma(ky, ky, kx * kx)));     // as in the physics pass
                 const R chig = chi_of<R>(es_inv, kk, kx, ky, kz, E, B);
                 const R khx = kx / kk, khy = ky / kk, khz = kz / kk;
@@ -1252,18 +1374,28 @@ __global__ void k_step_advance(int64_t *d_step) {
 // launchers
 // ------------------------------------------------------------------------
 template <typename R>
-hipError_t launch_push(const PushArgs &a, int fk, dim3 grid, dim3 block, hipStream_t s) {
+hipError_t launch_stream(const PushArgs &a, int fk, dim3 grid, dim3 block, hipStream_t s) {
     switch (fk) {
-    case FIELD_UNIFORM: hipLaunchKernelGGL((k_push_emit<R, FIELD_UNIFORM>), grid, block, 0, s, a); break;
-    case FIELD_PLANE: hipLaunchKernelGGL((k_push_emit<R, FIELD_PLANE>), grid, block, 0, s, a); break;
-    case FIELD_YEE: hipLaunchKernelGGL((k_push_emit<R, FIELD_YEE>), grid, block, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_push_emit<R, FIELD_BUNCHED>), grid, block, 0, s, a); break;
+    case FIELD_UNIFORM: hipLaunchKernelGGL((k_lepton_stream<R, FIELD_UNIFORM>), grid, block, 0, s, a); break;
+    case FIELD_PLANE: hipLaunchKernelGGL((k_lepton_stream<R, FIELD_PLANE>), grid, block, 0, s, a); break;
+    case FIELD_YEE: hipLaunchKernelGGL((k_lepton_stream<R, FIELD_YEE>), grid, block, 0, s, a); break;
+    default: {
+        const size_t lds = a.f.lds_bunches ? (size_t)lds_bunch_bytes(a.f.n_bunches) : 0;
+        hipLaunchKernelGGL((k_lepton_stream<R, FIELD_BUNCHED>), grid, block, lds, s, a);
+        break;
+    }
     }
     return hipGetLastError();
 }
 
-hipError_t launch_push_emit(const PushArgs &a, int prec, int fk, dim3 grid, dim3 block, hipStream_t s) {
-    return prec == 0 ? launch_push<double>(a, fk, grid, block, s) : launch_push<float>(a, fk, grid, block, s);
+hipError_t launch_lepton_stream(const PushArgs &a, int prec, int fk, dim3 grid, dim3 block, hipStream_t s) {
+    return prec == 0 ? launch_stream<double>(a, fk, grid, block, s) : launch_stream<float>(a, fk, grid, block, s);
+}
+
+hipError_t launch_lepton_events(const PushArgs &a, int prec, dim3 grid, dim3 block, hipStream_t s) {
+    if (prec == 0) hipLaunchKernelGGL((k_lepton_events<double>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_lepton_events<float>), grid, block, 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_scan_tiles(const ScanArgs &a, dim3 grid, hipStream_t s) {
