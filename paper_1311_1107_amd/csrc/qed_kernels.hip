@@ -328,38 +328,19 @@ __device__ __forceinline__ void status_need(unsigned long long *st, int which, i
     atomicMax(st + 1 + which, (unsigned long long)v);
 }
 
-// Reduce the per-thread energies of a tile and add them to the tile's slot.
+// Energy sums of one wave's tile into its tally slot, added with an FP64
+// atomic that returns nothing (the wave does not wait for it).  With a slot
+// per tile each slot takes one addition per launch, so the sums do not depend
+// on the schedule; with fewer slots, their order does.
 template <int NE>
-__device__ __forceinline__ void tile_energy(const TallyDev &tal, int64_t tile, bool atomic_slots,
-                                            double (&e)[NE], double *s_red) {
-    const int lane = lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-#pragma unroll
-    for (int k = 0; k < NE; ++k) {
-        double v = e[k];
-        if (__ballot(v != 0.0)) v = wave_sum_f64_dpp(v); else v = 0.0;
-        if (lane == 0) s_red[k * kMaxWaves + wid] = v;
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < NE) {
-        double s = 0.0;
-        for (int w = 0; w < nw; ++w) s += s_red[threadIdx.x * kMaxWaves + w];
-        if (s != 0.0) {
-            double *slot = tal.energy + (tile % tal.n_slots) * kNEnergy + threadIdx.x;
-            if (atomic_slots) atomicAdd(slot, s); else *slot += s;
-        }
-    }
-}
-
-// Energy sums of one wave's tile into its tally slot.
-template <int NE>
-__device__ __forceinline__ void wave_energy(const TallyDev &tal, int64_t tile, bool atomic_slots, double (&e)[NE]) {
+__device__ __forceinline__ void wave_energy(const TallyDev &tal, int64_t tile, double (&e)[NE]) {
 #pragma unroll
     for (int k = 0; k < NE; ++k) {
         if (__ballot(e[k] != 0.0) == 0ull) continue;
         const double s = wave_sum_f64_dpp(e[k]);
         if (lane_id() == 0 && s != 0.0) {
             double *slot = tal.energy + (tile % tal.n_slots) * kNEnergy + k;
-            if (atomic_slots) atomicAdd(slot, s); else *slot += s;
+            unsafeAtomicAdd(slot, s);
         }
     }
 }
@@ -480,7 +461,6 @@ k_lepton_stream(PushArgs a) {
     const R dtr = (R)dt;
     const int64_t n_chunks = (n + blockDim.x - 1) / blockDim.x;
     const int64_t n_tiles = (n + kWave - 1) / kWave;
-    const bool atomic_slots = n_tiles > a.tal.n_slots;
     const R q = (R)a.c.q, hq = R(0.5) * q * dtr;
     const R es_inv = (R)a.c.es_inv, Ah = (R)a.c.A, tau0 = (R)a.c.tau0;
     const R lnchi0 = (R)tb.e_lnchi0, inv_d = (R)tb.e_inv_dlnchi;
@@ -494,12 +474,28 @@ k_lepton_stream(PushArgs a) {
     for (int k = 0; k < N_COUNT_USED; ++k) cnt[k] = 0;
     __syncthreads();
 
-    for (int64_t it = 0;; ++it) {
-        const int64_t chunk = xcd_tile(it, n_chunks);
-        if (chunk < 0) break;
+    // the state of a wave's next tile is loaded before the current one is
+    // stepped, which hides the HBM latency behind the arithmetic
+    int64_t chunk = xcd_tile(0, n_chunks);
+    R n_x = R(0), n_y = R(0), n_z = R(0), n_ux = R(0), n_uy = R(0), n_uz = R(0), n_w = R(0);
+    double n_tau = 0.0;
+    if (chunk >= 0 && chunk * blockDim.x + tid < n) {
+        const int64_t j = chunk * blockDim.x + tid;
+        n_x = X[j]; n_y = Y[j]; n_z = Z[j]; n_ux = UX[j]; n_uy = UY[j]; n_uz = UZ[j]; n_w = Wt[j];
+        n_tau = a.lep.tau[j];
+    }
+    for (int64_t it = 0; chunk >= 0; ++it) {
         const int64_t tile = chunk * nw + wid;             // = i / 64
         const int64_t i = chunk * blockDim.x + tid;
         const bool live = i < n;
+        const R x = n_x, y = n_y, z = n_z, ux = n_ux, uy = n_uy, uz = n_uz, wgt_i = n_w;
+        const double tau_i = n_tau;
+        const int64_t next = xcd_tile(it + 1, n_chunks);
+        if (next >= 0 && next * blockDim.x + tid < n) {
+            const int64_t j = next * blockDim.x + tid;
+            n_x = X[j]; n_y = Y[j]; n_z = Z[j]; n_ux = UX[j]; n_uy = UY[j]; n_uz = UZ[j]; n_w = Wt[j];
+            n_tau = a.lep.tau[j];
+        }
         double en[kNEnergy];
 #pragma unroll
         for (int k = 0; k < kNEnergy; ++k) en[k] = 0.0;
@@ -512,14 +508,12 @@ k_lepton_stream(PushArgs a) {
                 else { Phi = 2.0 * kPi * b_np[b]; inv_Phi = 1.0 / Phi; }
             }
         }
-        const R x = live ? X[i] : R(0), y = live ? Y[i] : R(0), z = live ? Z[i] : R(0);
         R E[3], B[3];
         if constexpr (FK == FIELD_YEE) yee_gather_wave<R>(a.f, live, x, y, z, E, B, s_box + wid * kWBFloats);
         bool event = false;
         R uLx = R(0), uLy = R(0), uLz = R(0), gL = R(1), chi = R(0), W = R(0), wgt = R(0);
         double tau = 0.0;
         if (live) {
-            const R ux = UX[i], uy = UY[i], uz = UZ[i];
             if constexpr (FK != FIELD_YEE) field_at<R, FK>(a.f, t, x, y, z, a0, Phi, inv_Phi, E, B);
             const R g_old = Math<R>::sqrt_(R(1) + (ux * ux + uy * uy + uz * uz));
 
@@ -539,7 +533,7 @@ k_lepton_stream(PushArgs a) {
             const R qz = umz + (px * sy - py * sx);
             uLx = qx + hq * E[0]; uLy = qy + hq * E[1]; uLz = qz + hq * E[2];
             gL = Math<R>::sqrt_(R(1) + (uLx * uLx + uLy * uLy + uLz * uLz));
-            wgt = Wt[i];
+            wgt = wgt_i;
             en[E_WORK] = (double)wgt * (double)(gL - g_old);
 
             chi = chi_of<R>(es_inv, gL, uLx, uLy, uLz, E, B);
@@ -580,7 +574,7 @@ k_lepton_stream(PushArgs a) {
                     W = Math<R>::div_(Ah * h_rad_at<R>(s_lh, tb, lnchi0, inv_d, chi, above), gL);
                     if (above) cnt[C_RANGE]++;
                 }
-                tau = a.lep.tau[i];
+                tau = tau_i;
                 const double Wd = (double)W;
                 if (!(W > R(0)) || tau > Wd * dt) a.lep.tau[i] = tau - Wd * dt;
                 else event = true;                          // finished by the event pass
@@ -606,8 +600,9 @@ k_lepton_stream(PushArgs a) {
         }
         if (tile < n_tiles) {
             if (lane == 0) a.ws.tile_cnt0[tile] = n_items;
-            wave_energy<kNEnergy>(a.tal, tile, atomic_slots, en);
+            wave_energy<kNEnergy>(a.tal, tile, en);
         }
+        chunk = next;
     }
     block_counts(a.tal, cnt, s_cnt);
 }
@@ -631,7 +626,6 @@ k_lepton_events(PushArgs a) {
     for (int k = tid; k < tb.e_n_chi; k += blockDim.x) s_lh[k] = (R)tb.ln_hrad[k];
     const int64_t n_items = a.ws.info->n_items;
     const int64_t n_chunks = (n_items + kWave - 1) / kWave;
-    const bool atomic_slots = n_chunks > a.tal.n_slots;
     const double dt = a.st.dt;
     const R dtr = (R)dt;
     const R es_inv = (R)a.c.es_inv, Ah = (R)a.c.A;
@@ -752,7 +746,7 @@ k_lepton_events(PushArgs a) {
             a.ws.tile_cnt1[c] = t1;
             a.ws.stage.n_rec[c] = (uint32_t)(n_items - c * kWave < kWave ? n_items - c * kWave : kWave);
         }
-        wave_energy<kNEnergy>(a.tal, c, atomic_slots, en);
+        wave_energy<kNEnergy>(a.tal, c, en);
     }
     block_counts(a.tal, cnt, s_cnt);
 }
@@ -985,7 +979,6 @@ k_pair_create(PairArgs a) {
     const R dtr = (R)dt;
     const int64_t n_chunks = (n + blockDim.x - 1) / blockDim.x;
     const int64_t n_tiles = (n + kWave - 1) / kWave;
-    const bool atomic_slots = n_tiles > a.tal.n_slots;
     const R es_inv = (R)a.c.es_inv, Ah = (R)a.c.A;
     const R lnchi0 = (R)tb.p_lnchi0, inv_d = (R)tb.p_inv_dlnchi, chi_min = (R)tb.p_chi_min;
     R *X = (R *)a.ph.x, *Y = (R *)a.ph.y, *Z = (R *)a.ph.z;
@@ -1109,7 +1102,7 @@ k_pair_create(PairArgs a) {
                 a.ws.tile_cnt0[tile] = tot;
                 a.ws.tile_cnt1[tile] = 0u;
             }
-            wave_energy<kNEnergy>(a.tal, tile, atomic_slots, en);
+            wave_energy<kNEnergy>(a.tal, tile, en);
         }
         chunk = next;
     }
