@@ -258,7 +258,7 @@ qed_status qed_tally_reduce(const qed_tally *t, double energy[QED_N_ENERGY] /* [
  * tickets of the scan and compaction kernels, and the sticky device status.
  * max_particles bounds the capacity of any species passed with it;
  * max_leptons bounds the capacity of the lepton species given to
- * qed_push_emit (event items and emission records take about 268 bytes per
+ * qed_push_emit (event items and emission records take about 272 bytes per
  * lepton in FP64).  One
  * workspace per stream; calls sharing a workspace must not overlap in time.
  * ------------------------------------------------------------------------ */

@@ -88,8 +88,7 @@ struct qed_workspace {
     void *d_rec;              // emission records
     uint32_t *d_meta, *d_nrec;
     void *d_item;             // event items of the lepton step
-    double *d_item_tau;
-    uint32_t *d_item_idx, *d_item_map;
+    uint32_t *d_item_map;
     qed::WsDev dev;
 };
 
@@ -228,9 +227,7 @@ qed_status qed_workspace_create(int64_t max_particles, int64_t max_leptons, qed_
         hipMalloc(&w->d_rec, sizeof(double) * qed::kRecReals * slots) != hipSuccess ||
         hipMalloc(&w->d_meta, sizeof(uint32_t) * slots) != hipSuccess ||
         hipMalloc(&w->d_nrec, sizeof(uint32_t) * w->max_tiles) != hipSuccess ||
-        hipMalloc(&w->d_item, sizeof(double) * qed::kItemReals * slots) != hipSuccess ||
-        hipMalloc(&w->d_item_tau, sizeof(double) * slots) != hipSuccess ||
-        hipMalloc(&w->d_item_idx, sizeof(uint32_t) * slots) != hipSuccess ||
+        hipMalloc(&w->d_item, qed::kItemBytes * slots) != hipSuccess ||
         hipMalloc(&w->d_item_map, sizeof(uint32_t) * slots) != hipSuccess) {
         qed_workspace_free(w);
         return fail(QED_ERR_NOMEM, "qed_workspace_create: device allocation failed");
@@ -257,8 +254,6 @@ qed_status qed_workspace_create(int64_t max_particles, int64_t max_leptons, qed_
     w->dev.stage.meta = w->d_meta;
     w->dev.stage.n_rec = w->d_nrec;
     w->dev.stage.item = w->d_item;
-    w->dev.stage.item_tau = w->d_item_tau;
-    w->dev.stage.item_idx = w->d_item_idx;
     w->dev.stage.item_map = w->d_item_map;
     w->dev.stage.slots = slots;
     w->dev.max_tiles = w->max_tiles;
@@ -277,8 +272,6 @@ void qed_workspace_free(qed_workspace *w) {
     (void)hipFree(w->d_meta);
     (void)hipFree(w->d_nrec);
     (void)hipFree(w->d_item);
-    (void)hipFree(w->d_item_tau);
-    (void)hipFree(w->d_item_idx);
     (void)hipFree(w->d_item_map);
     delete w;
 }
@@ -607,9 +600,7 @@ constexpr size_t kOffNrec = kOffTiles + align256(sizeof(uint32_t) * 4 * kStaticT
 constexpr size_t kOffMeta = kOffNrec + align256(sizeof(uint32_t) * kStaticTiles);
 constexpr size_t kOffRec = kOffMeta + align256(sizeof(uint32_t) * kStaticSlots);
 constexpr size_t kOffItem = kOffRec + align256(sizeof(double) * qed::kRecReals * kStaticSlots);
-constexpr size_t kOffItemTau = kOffItem + align256(sizeof(double) * qed::kItemReals * kStaticSlots);
-constexpr size_t kOffItemIdx = kOffItemTau + align256(sizeof(double) * kStaticSlots);
-constexpr size_t kOffItemMap = kOffItemIdx + align256(sizeof(uint32_t) * kStaticSlots);
+constexpr size_t kOffItemMap = kOffItem + align256(qed::kItemBytes * kStaticSlots);
 constexpr size_t kStaticBytes = kOffItemMap + align256(sizeof(uint32_t) * kStaticSlots);
 
 static __device__ __align__(256) unsigned char scratch[kStaticBytes];
@@ -714,8 +705,6 @@ qed_status qed_push_emit_static(const qed_tables *tab, const qed_units *u, doubl
     w.dev.stage.meta = (uint32_t *)(base + kOffMeta);
     w.dev.stage.n_rec = (uint32_t *)(base + kOffNrec);
     w.dev.stage.item = base + kOffItem;
-    w.dev.stage.item_tau = (double *)(base + kOffItemTau);
-    w.dev.stage.item_idx = (uint32_t *)(base + kOffItemIdx);
     w.dev.stage.item_map = (uint32_t *)(base + kOffItemMap);
     w.dev.stage.slots = kStaticSlots;
     w.dev.max_tiles = kStaticTiles;

@@ -16,7 +16,9 @@ constexpr int kMaxChiNodes = 256;
 constexpr int kMaxWaves = 4;      // 256 threads per block
 
 enum { RNG_EMIT = 1, RNG_PAIR = 2, RNG_INIT = 3 };
-enum { FIELD_UNIFORM = 0, FIELD_PLANE = 1, FIELD_YEE = 2, FIELD_BUNCHED = 3 };
+// FIELD_BUNCHED_GLOBAL: the batched form with its bunch table read from global
+// memory (a table too large for LDS); kernels only, never passed by the API
+enum { FIELD_UNIFORM = 0, FIELD_PLANE = 1, FIELD_YEE = 2, FIELD_BUNCHED = 3, FIELD_BUNCHED_GLOBAL = 4 };
 enum { RAD_NONE = 0, RAD_SOKOLOV = 1, RAD_MC = 2, RAD_HYBRID = 3 };
 
 // count tallies (integer, accumulated per block across tiles)

@@ -61,21 +61,28 @@ struct ConstsDev {
 };
 
 // Event items written by the stream pass of the lepton step for its event
-// pass: one per particle whose optical depth runs out in the step, at slot
-// tile * 64 + rank (tiles of one wave).  Reals (SoA, stride `slots`): 0-2
-// position x^n, 3-5 u after the push, 6-8 E, 9-11 B, 12 gamma after the push,
-// 13 chi_e, 14 emission rate W, 15 weight; the optical depth and the
-// particle's index in arrays of their own.
+// pass: one record per particle whose optical depth runs out in the step, at
+// slot tile * 64 + rank (tiles of one wave), so that the items of a tile are
+// adjacent.  A record is whole 16-byte words (80 bytes in FP32, 144 in FP64):
+// the event pass reads each with a few wide loads.
 constexpr int kItemReals = 16;
+template <typename R>
+struct alignas(16) ItemRec {
+    R v[kItemReals];     // 0-2 position x^n, 3-5 u after the push, 6-8 E, 9-11 B,
+                         // 12 gamma after the push, 13 chi_e, 14 emission rate W, 15 weight
+    double tau;          // optical depth at the start of the step
+    uint32_t idx;        // index of the particle
+    uint32_t pad;
+};
+static_assert(sizeof(ItemRec<float>) == 80 && sizeof(ItemRec<double>) == 144, "item record layout");
+constexpr int64_t kItemBytes = sizeof(ItemRec<double>);
 // Emission records written by the event pass for the append pass: one per
 // event item, in item order (dense).  Reals (SoA, stride `slots`): 0-2
 // position x^n, 3-5 direction u_hat, 6 weight, 7-10 gamma_gamma of each event,
 // 11-14 chi_gamma of each event.
 constexpr int kRecReals = 15;
 struct StageDev {
-    void *item;                      // kItemReals * slots reals (double or float)
-    double *item_tau;                // per item slot
-    uint32_t *item_idx;              // per item slot: index of the particle
+    void *item;                      // ItemRec<double> or ItemRec<float> per slot
     uint32_t *item_map;              // item d (dense, in particle order) -> its slot
     void *rec;                       // kRecReals * slots reals (double or float)
     uint32_t *meta;                  // per record: events (bits 0-2), destination of event k (2 bits at 3+2k)

@@ -309,7 +309,7 @@ __device__ __forceinline__ void field_at(const FieldDev &f, double t, R x, R y, 
     if (FK == FIELD_UNIFORM) {
         E[0] = (R)f.E[0]; E[1] = (R)f.E[1]; E[2] = (R)f.E[2];
         B[0] = (R)f.B[0]; B[1] = (R)f.B[1]; B[2] = (R)f.B[2];
-    } else if (FK == FIELD_PLANE || FK == FIELD_BUNCHED) {
+    } else if (FK == FIELD_PLANE || FK == FIELD_BUNCHED || FK == FIELD_BUNCHED_GLOBAL) {
         const R da = plane_wave_da<R>(t, x, a0, Phi, inv_Phi);
         E[0] = R(0); E[1] = -da; E[2] = R(0);
         B[0] = R(0); B[1] = R(0); B[2] = -da;
@@ -429,31 +429,28 @@ k_lepton_stream(PushArgs a) {
     __shared__ int64_t s_cnt[N_COUNT_USED];
     extern __shared__ __align__(16) unsigned char s_dyn[];      // bunch table (batched form)
 
-    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave, nw = blockDim.x / kWave;
+    const int tid = threadIdx.x, lane = lane_id(), nw = blockDim.x / kWave;
+    const int wid = __builtin_amdgcn_readfirstlane(tid / kWave);    // uniform over the wave
     const TablesDev &tb = a.tab;
     for (int k = tid; k < tb.e_n_chi; k += blockDim.x) {
         s_lh[k] = (R)tb.ln_hrad[k];
         s_lg[k] = (R)tb.ln_g[k];
     }
-    // batched form: offsets, amplitudes and phase lengths 2 pi n_periods of the
-    // bunches in LDS when they fit, else read from global memory
+    // batched form: offsets, amplitudes, phase lengths 2 pi n_periods and their
+    // reciprocals of the bunches in LDS (FIELD_BUNCHED), or read from global
+    // memory for a table too large for it (FIELD_BUNCHED_GLOBAL).  The two are
+    // separate instantiations: a global load here would have to wait for the
+    // next tile's loads issued before it.
     const int nb = a.f.n_bunches;
-    const int64_t *b_off = a.f.offsets;
-    const double *b_a0 = a.f.a0s, *b_np = a.f.nper;
-    double *s_phi = nullptr, *s_iphi = nullptr;
-    if (FK == FIELD_BUNCHED && a.f.lds_bunches) {
-        int64_t *so = (int64_t *)s_dyn;
-        double *sa = (double *)(so + nb + 1);
-        s_phi = sa + nb;
-        s_iphi = s_phi + nb;
+    int64_t *so = (int64_t *)s_dyn;
+    double *sa = (double *)(so + nb + 1), *s_phi = sa + nb, *s_iphi = s_phi + nb;
+    if (FK == FIELD_BUNCHED) {
         for (int k = tid; k <= nb; k += blockDim.x) so[k] = a.f.offsets[k];
         for (int k = tid; k < nb; k += blockDim.x) {
             sa[k] = a.f.a0s[k];
             s_phi[k] = 2.0 * kPi * a.f.nper[k];
             s_iphi[k] = 1.0 / s_phi[k];
         }
-        b_off = so;
-        b_a0 = sa;
     }
     const int64_t n = *a.lep.count;
     const double t = a.st.d_step ? a.st.t + (double)(*a.st.d_step) * a.st.dt : a.st.t;
@@ -467,8 +464,7 @@ k_lepton_stream(PushArgs a) {
     R *X = (R *)a.lep.x, *Y = (R *)a.lep.y, *Z = (R *)a.lep.z;
     R *UX = (R *)a.lep.ux, *UY = (R *)a.lep.uy, *UZ = (R *)a.lep.uz;
     const R *Wt = (const R *)a.lep.w;
-    R *item = (R *)a.ws.stage.item;
-    const int64_t slots = a.ws.stage.slots;
+    ItemRec<R> *items = (ItemRec<R> *)a.ws.stage.item;
     int cnt[N_COUNT_USED];
 #pragma unroll
     for (int k = 0; k < N_COUNT_USED; ++k) cnt[k] = 0;
@@ -501,12 +497,11 @@ k_lepton_stream(PushArgs a) {
         for (int k = 0; k < kNEnergy; ++k) en[k] = 0.0;
         double a0 = a.f.a0, Phi = a.f.Phi, inv_Phi = a.f.inv_Phi;
         if (FK == FIELD_BUNCHED) {
-            const int b = lane_bunch(b_off, nb, tile * kWave, i);
-            if (live) {
-                a0 = b_a0[b];
-                if (s_phi) { Phi = s_phi[b]; inv_Phi = s_iphi[b]; }
-                else { Phi = 2.0 * kPi * b_np[b]; inv_Phi = 1.0 / Phi; }
-            }
+            const int b = lane_bunch(so, nb, tile * kWave, i);
+            if (live) { a0 = sa[b]; Phi = s_phi[b]; inv_Phi = s_iphi[b]; }
+        } else if (FK == FIELD_BUNCHED_GLOBAL) {
+            const int b = lane_bunch(a.f.offsets, nb, tile * kWave, i);
+            if (live) { a0 = a.f.a0s[b]; Phi = 2.0 * kPi * a.f.nper[b]; inv_Phi = 1.0 / Phi; }
         }
         R E[3], B[3];
         if constexpr (FK == FIELD_YEE) yee_gather_wave<R>(a.f, live, x, y, z, E, B, s_box + wid * kWBFloats);
@@ -591,12 +586,9 @@ k_lepton_stream(PushArgs a) {
         uint32_t n_items;
         const uint32_t rank = ballot_excl(event, n_items);
         if (event) {
-            const int64_t sl = tile * kWave + rank;
-            const R v[kItemReals] = {x, y, z, uLx, uLy, uLz, E[0], E[1], E[2], B[0], B[1], B[2], gL, chi, W, wgt};
-#pragma unroll
-            for (int k = 0; k < kItemReals; ++k) item[k * slots + sl] = v[k];
-            a.ws.stage.item_tau[sl] = tau;
-            a.ws.stage.item_idx[sl] = (uint32_t)i;
+            const ItemRec<R> r = {{x, y, z, uLx, uLy, uLz, E[0], E[1], E[2], B[0], B[1], B[2], gL, chi, W, wgt},
+                                  tau, (uint32_t)i, 0u};
+            items[tile * kWave + rank] = r;
         }
         if (tile < n_tiles) {
             if (lane == 0) a.ws.tile_cnt0[tile] = n_items;
@@ -621,7 +613,8 @@ k_lepton_events(PushArgs a) {
     __shared__ R s_lh[kMaxChiNodes];
     __shared__ int64_t s_cnt[N_COUNT_USED];
 
-    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave, nw = blockDim.x / kWave;
+    const int tid = threadIdx.x, lane = lane_id(), nw = blockDim.x / kWave;
+    const int wid = __builtin_amdgcn_readfirstlane(tid / kWave);    // uniform over the wave
     const TablesDev &tb = a.tab;
     for (int k = tid; k < tb.e_n_chi; k += blockDim.x) s_lh[k] = (R)tb.ln_hrad[k];
     const int64_t n_items = a.ws.info->n_items;
@@ -633,7 +626,7 @@ k_lepton_events(PushArgs a) {
     const R *qtab = emit_q_ptr<R>(tb);
     R *X = (R *)a.lep.x, *Y = (R *)a.lep.y, *Z = (R *)a.lep.z;
     R *UX = (R *)a.lep.ux, *UY = (R *)a.lep.uy, *UZ = (R *)a.lep.uz;
-    const R *item = (const R *)a.ws.stage.item;
+    const ItemRec<R> *items = (const ItemRec<R> *)a.ws.stage.item;
     R *rec = (R *)a.ws.stage.rec;
     const int64_t slots = a.ws.stage.slots;
     int cnt[N_COUNT_USED];
@@ -652,17 +645,15 @@ k_lepton_events(PushArgs a) {
         em.n = 0;
         R x = R(0), y = R(0), z = R(0), uhx = R(0), uhy = R(0), uhz = R(0), wgt = R(0);
         if (have) {
-            const int64_t sl = a.ws.stage.item_map[d];
-            const int64_t i = a.ws.stage.item_idx[sl];
-            R v[kItemReals];
-#pragma unroll
-            for (int k = 0; k < kItemReals; ++k) v[k] = item[k * slots + sl];
+            const ItemRec<R> r = items[a.ws.stage.item_map[d]];
+            const int64_t i = r.idx;
+            const R *v = r.v;
             x = v[0]; y = v[1]; z = v[2];
             const R uLx = v[3], uLy = v[4], uLz = v[5];
             const R E[3] = {v[6], v[7], v[8]}, B[3] = {v[9], v[10], v[11]};
             R gam = v[12], ce = v[13], W = v[14];
             wgt = v[15];
-            double tau = a.ws.stage.item_tau[sl];
+            double tau = r.tau;
             R p = Math<R>::sqrt_(uLx * uLx + uLy * uLy + uLz * uLz);
             if (p > R(0)) { const R ip = Math<R>::rcp_(p); uhx = uLx * ip; uhy = uLy * ip; uhz = uLz * ip; }
             double t_left = dt;
@@ -970,7 +961,8 @@ k_pair_create(PairArgs a) {
     __shared__ float s_box[FK == FIELD_YEE ? kMaxWaves * kWBFloats : 1];
     __shared__ int64_t s_cnt[N_COUNT_USED];
 
-    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave, nw = blockDim.x / kWave;
+    const int tid = threadIdx.x, lane = lane_id(), nw = blockDim.x / kWave;
+    const int wid = __builtin_amdgcn_readfirstlane(tid / kWave);    // uniform over the wave
     const TablesDev &tb = a.tab;
     for (int i = tid; i < tb.p_n_chi; i += blockDim.x) s_lp[i] = (R)tb.pair_lnh[i];
     const int64_t n = *a.ph.count;
@@ -1206,7 +1198,8 @@ k_compact(CompactArgs a) {
     __shared__ uint64_t s_ticket;
     __shared__ uint32_t s_wc[kItems * kMaxWaves];      // alive photons per (item row, wave)
     __shared__ uint32_t s_pref;
-    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave, nw = blockDim.x / kWave;
+    const int tid = threadIdx.x, lane = lane_id(), nw = blockDim.x / kWave;
+    const int wid = __builtin_amdgcn_readfirstlane(tid / kWave);    // uniform over the wave
     const int64_t n = *a.s.count;
     const int64_t tile_sz = (int64_t)blockDim.x * kItems;
     const int64_t n_tiles = (n + tile_sz - 1) / tile_sz;
@@ -1372,11 +1365,13 @@ hipError_t launch_stream(const PushArgs &a, int fk, dim3 grid, dim3 block, hipSt
     case FIELD_UNIFORM: hipLaunchKernelGGL((k_lepton_stream<R, FIELD_UNIFORM>), grid, block, 0, s, a); break;
     case FIELD_PLANE: hipLaunchKernelGGL((k_lepton_stream<R, FIELD_PLANE>), grid, block, 0, s, a); break;
     case FIELD_YEE: hipLaunchKernelGGL((k_lepton_stream<R, FIELD_YEE>), grid, block, 0, s, a); break;
-    default: {
-        const size_t lds = a.f.lds_bunches ? (size_t)lds_bunch_bytes(a.f.n_bunches) : 0;
-        hipLaunchKernelGGL((k_lepton_stream<R, FIELD_BUNCHED>), grid, block, lds, s, a);
+    default:
+        if (a.f.lds_bunches)
+            hipLaunchKernelGGL((k_lepton_stream<R, FIELD_BUNCHED>), grid, block,
+                               (size_t)lds_bunch_bytes(a.f.n_bunches), s, a);
+        else
+            hipLaunchKernelGGL((k_lepton_stream<R, FIELD_BUNCHED_GLOBAL>), grid, block, 0, s, a);
         break;
-    }
     }
     return hipGetLastError();
 }
