@@ -12,6 +12,7 @@ from __future__ import annotations
 
 import ctypes as C
 import hashlib
+import math
 import os
 import subprocess
 import tempfile
@@ -62,7 +63,8 @@ class Units(C.Structure):
 
 class TableSpec(C.Structure):
     _fields_ = [("chi_min", C.c_double), ("chi_max", C.c_double),
-                ("n_chi", C.c_int32), ("n_q", C.c_int32), ("logit_max", C.c_double)]
+                ("n_chi", C.c_int32), ("n_q", C.c_int32), ("logit_max", C.c_double),
+                ("interp", C.c_int32), ("reserved", C.c_int32)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -79,7 +81,8 @@ class Tables(C.Structure):
                 ("p_n_chi", C.c_int32), ("p_n_q", C.c_int32),
                 ("p_chi_min", C.c_double), ("p_lnchi0", C.c_double),
                 ("p_inv_dlnchi", C.c_double), ("p_logit_max", C.c_double),
-                ("p_inv_dt", C.c_double), ("pair_lnh", _dp), ("pair_q", _dp)]
+                ("p_inv_dt", C.c_double), ("pair_lnh", _dp), ("pair_q", _dp),
+                ("e_interp", C.c_int32), ("p_interp", C.c_int32), ("emit_m", _dp), ("pair_m", _dp)]
 
 
 class Species(C.Structure):
@@ -131,6 +134,8 @@ def lib():
         L.or_tables_compute.argtypes = [C.POINTER(TableSpec), C.POINTER(TableSpec)] + [_dp] * 5 + [C.c_int]
         L.or_tables_compute.restype = C.c_int
         L.or_tables_bind.argtypes = [C.POINTER(Tables), C.POINTER(TableSpec), C.POINTER(TableSpec)] + [_dp] * 5
+        L.or_tables_bind_spline.argtypes = [C.POINTER(Tables), _dp, _dp]
+        L.or_quantile_spline.argtypes = [_dp, C.c_int, C.c_int, C.c_double, C.c_double, _dp]
         L.or_lookup_h_rad.argtypes = [C.POINTER(Tables), d, C.POINTER(C.c_int)]
         L.or_lookup_h_rad.restype = d
         L.or_lookup_g.argtypes = [C.POINTER(Tables), d]
@@ -248,16 +253,37 @@ EMIT_SPEC = dict(chi_min=1e-3, chi_max=1e2, n_chi=128, n_q=128, logit_max=18.0)
 PAIR_SPEC = dict(chi_min=1e-2, chi_max=1e2, n_chi=128, n_q=128, logit_max=18.0)
 
 
+INTERP_LINEAR, INTERP_SPLINE = 0, 1
+
+
 def _spec(d):
-    return TableSpec(d["chi_min"], d["chi_max"], d["n_chi"], d["n_q"], d["logit_max"])
+    return TableSpec(d["chi_min"], d["chi_max"], d["n_chi"], d["n_q"], d["logit_max"], d.get("interp", 0), 0)
+
+
+def quantile_spline(q: np.ndarray, n_chi: int, n_q: int, h_c: float, h_t: float) -> np.ndarray:
+    """Second-derivative tables of the natural bicubic spline through q
+    (or_quantile_spline): shape (3, n_chi, n_q) = d2/dt2, d2/dc2, d4/dc2dt2."""
+    q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
+    m = np.zeros(3 * n_chi * n_q)
+    lib().or_quantile_spline(_ptr(q), n_chi, n_q, h_c, h_t, _ptr(m))
+    return m.reshape(3, n_chi, n_q)
+
+
+def _spacings(spec):
+    h_c = (math.log(spec["chi_max"]) - math.log(spec["chi_min"])) / (spec["n_chi"] - 1)
+    h_t = 2.0 * spec["logit_max"] / (spec["n_q"] - 1)
+    return h_c, h_t
 
 
 def compute_tables(emit=None, pair=None, threads: int | None = None, cache: bool = True) -> dict:
     """Oracle tables as numpy arrays; cached on disk per (source, spec)."""
     emit = dict(EMIT_SPEC if emit is None else emit)
     pair = dict(PAIR_SPEC if pair is None else pair)
-    key = hashlib.sha1((open(SRC).read() + repr(sorted(emit.items())) +
-                        repr(sorted(pair.items()))).encode()).hexdigest()[:16]
+    # the nodes do not depend on the interpolation between them
+    nodes_e = {k: v for k, v in emit.items() if k != "interp"}
+    nodes_p = {k: v for k, v in pair.items() if k != "interp"}
+    key = hashlib.sha1((open(SRC).read() + repr(sorted(nodes_e.items())) +
+                        repr(sorted(nodes_p.items()))).encode()).hexdigest()[:16]
     path = os.path.join(tempfile.gettempdir(), f"qed_oracle_tables_{key}.npz")
     if cache and os.path.exists(path):
         z = np.load(path)
@@ -291,6 +317,11 @@ class BoundTables:
         self.t = Tables()
         lib().or_tables_bind(C.byref(self.t), C.byref(self.se), C.byref(self.sp),
                              *[_ptr(self.arrays[k]) for k in ("ln_hrad", "ln_g", "emit_q", "pair_lnh", "pair_q")])
+        es, ps = tabs["emit_spec"], tabs["pair_spec"]
+        if es.get("interp", 0) or ps.get("interp", 0):
+            self.emit_m = quantile_spline(self.arrays["emit_q"], es["n_chi"], es["n_q"], *_spacings(es))
+            self.pair_m = quantile_spline(self.arrays["pair_q"], ps["n_chi"], ps["n_q"], *_spacings(ps))
+            lib().or_tables_bind_spline(C.byref(self.t), _ptr(self.emit_m.reshape(-1)), _ptr(self.pair_m.reshape(-1)))
 
     def h_rad(self, chi):
         oor = C.c_int(0)

@@ -10,6 +10,7 @@
 #include "qed_oracle.h"
 
 #include <math.h>
+#include <stddef.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -463,6 +464,53 @@ void or_tables_bind(or_tables *t, const or_table_spec *emit, const or_table_spec
     t->p_logit_max = pair->logit_max;
     t->p_inv_dt = (pair->n_q - 1) / (2.0 * pair->logit_max);
     t->pair_lnh = pair_lnh; t->pair_q = pair_q;
+    t->e_interp = emit->interp; t->p_interp = pair->interp;
+    t->emit_m = NULL; t->pair_m = NULL;
+}
+
+void or_tables_bind_spline(or_tables *t, const double *emit_m, const double *pair_m)
+{
+    t->emit_m = emit_m; t->pair_m = pair_m;
+}
+
+/* Natural cubic spline through y[0], y[s], ..., y[(n-1)s] at unit spacing h:
+ * second derivatives M with M_0 = M_{n-1} = 0 and, inside,
+ *   M_{k-1} + 4 M_k + M_{k+1} = 6 (y_{k+1} - 2 y_k + y_{k-1}) / h^2,
+ * solved by forward elimination and back substitution (the tridiagonal
+ * system is diagonally dominant).  cp holds n scratch values. */
+static void natural_spline_m(const double *y, ptrdiff_t s, int n, double h,
+                             double *m, ptrdiff_t ms, double *cp)
+{
+    m[0] = 0.0;
+    m[(n - 1) * ms] = 0.0;
+    if (n < 3) return;
+    /* unknowns k = 1..n-2; row k: 1 M_{k-1} + 4 M_k + 1 M_{k+1} = d_k */
+    double prev_c = 0.0, prev_d = 0.0;
+    for (int k = 1; k <= n - 2; ++k) {
+        double d = 6.0 * (y[(k + 1) * s] - 2.0 * y[k * s] + y[(k - 1) * s]) / (h * h);
+        double den = 4.0 - (k > 1 ? prev_c : 0.0);
+        double c = (k < n - 2) ? 1.0 / den : 0.0;
+        double dd = (d - (k > 1 ? prev_d : 0.0)) / den;
+        cp[k] = c;
+        m[k * ms] = dd;
+        prev_c = c; prev_d = dd;
+    }
+    for (int k = n - 3; k >= 1; --k) m[k * ms] -= cp[k] * m[(k + 1) * ms];
+}
+
+void or_quantile_spline(const double *q, int n_chi, int n_q, double h_c, double h_t, double *m)
+{
+    const size_t N = (size_t)n_chi * n_q;
+    double *mtt = m, *mcc = m + N, *mcctt = m + 2 * N;
+    int nmax = n_chi > n_q ? n_chi : n_q;
+    double *cp = (double *)malloc(sizeof(double) * (size_t)nmax);
+    for (int i = 0; i < n_chi; ++i)             /* along t, each row */
+        natural_spline_m(q + (size_t)i * n_q, 1, n_q, h_t, mtt + (size_t)i * n_q, 1, cp);
+    for (int j = 0; j < n_q; ++j)               /* along ln chi, each column */
+        natural_spline_m(q + j, n_q, n_chi, h_c, mcc + j, n_q, cp);
+    for (int i = 0; i < n_chi; ++i)             /* the columns' curvature, along t */
+        natural_spline_m(mcc + (size_t)i * n_q, 1, n_q, h_t, mcctt + (size_t)i * n_q, 1, cp);
+    free(cp);
 }
 
 /* Linear interpolation in (ln chi, ln h).  Above the last node the end
@@ -537,18 +585,63 @@ static double bilerp_quantile(const double *q, int n_chi, int n_q, double lnchi0
     return a + w * (b - a);
 }
 
+/* One cubic segment of a natural spline at fraction z of a step h:
+ * (1-z) f0 + z f1 + h^2/6 [((1-z)^3 - (1-z)) m0 + (z^3 - z) m1]. */
+static double spline_seg(double f0, double f1, double m0, double m1, double z, double h)
+{
+    double a = 1.0 - z;
+    return a * f0 + z * f1 + ((a * a * a - a) * m0 + (z * z * z - z) * m1) * h * h / 6.0;
+}
+
+/* The tensor-product natural cubic spline of q at (ln chi, logit r), with the
+ * node cell, weights and clamps of bilerp_quantile: the spline along t of
+ * rows i and i+1 (and of their curvature in ln chi), then the spline along
+ * ln chi between the two rows. */
+static double bicubic_quantile(const double *q, const double *m, int n_chi, int n_q,
+                               double lnchi0, double inv_d, double logit_max,
+                               double inv_dt, double chi, double r)
+{
+    double u = (log(chi) - lnchi0) * inv_d;
+    if (!(u > 0.0)) u = 0.0;
+    if (u > (double)(n_chi - 1)) u = (double)(n_chi - 1);
+    int i = (int)u;
+    if (i > n_chi - 2) i = n_chi - 2;
+    double w = u - (double)i;
+    double t = log(r) - log(1.0 - r);
+    if (!(t > -logit_max)) t = -logit_max;
+    if (t > logit_max) t = logit_max;
+    double v = (t + logit_max) * inv_dt;
+    int j = (int)v;
+    if (j > n_q - 2) j = n_q - 2;
+    double z = v - (double)j;
+    const double h_t = 1.0 / inv_dt, h_c = 1.0 / inv_d;
+    const size_t N = (size_t)n_chi * n_q, a0 = (size_t)i * n_q + j, a1 = a0 + n_q;
+    const double *mtt = m, *mcc = m + N, *mcctt = m + 2 * N;
+    double f_i = spline_seg(q[a0], q[a0 + 1], mtt[a0], mtt[a0 + 1], z, h_t);
+    double f_i1 = spline_seg(q[a1], q[a1 + 1], mtt[a1], mtt[a1 + 1], z, h_t);
+    double c_i = spline_seg(mcc[a0], mcc[a0 + 1], mcctt[a0], mcctt[a0 + 1], z, h_t);
+    double c_i1 = spline_seg(mcc[a1], mcc[a1 + 1], mcctt[a1], mcctt[a1 + 1], z, h_t);
+    return spline_seg(f_i, f_i1, c_i, c_i1, w, h_c);
+}
+
 double or_sample_xi(const or_tables *t, double chi, double r)
 {
-    double lnxi = bilerp_quantile(t->emit_q, t->e_n_chi, t->e_n_q, t->e_lnchi0, t->e_inv_dlnchi,
-                                  t->e_logit_max, t->e_inv_dt, chi, r);
+    double lnxi = t->e_interp
+        ? bicubic_quantile(t->emit_q, t->emit_m, t->e_n_chi, t->e_n_q, t->e_lnchi0, t->e_inv_dlnchi,
+                           t->e_logit_max, t->e_inv_dt, chi, r)
+        : bilerp_quantile(t->emit_q, t->e_n_chi, t->e_n_q, t->e_lnchi0, t->e_inv_dlnchi,
+                          t->e_logit_max, t->e_inv_dt, chi, r);
     double xi = exp(lnxi);
     return xi < 1.0 ? xi : 1.0;
 }
 
 double or_sample_eta(const or_tables *t, double chi, double r)
 {
-    double s = bilerp_quantile(t->pair_q, t->p_n_chi, t->p_n_q, t->p_lnchi0, t->p_inv_dlnchi,
-                               t->p_logit_max, t->p_inv_dt, chi, r);
+    double s = t->p_interp
+        ? bicubic_quantile(t->pair_q, t->pair_m, t->p_n_chi, t->p_n_q, t->p_lnchi0, t->p_inv_dlnchi,
+                           t->p_logit_max, t->p_inv_dt, chi, r)
+        : bilerp_quantile(t->pair_q, t->p_n_chi, t->p_n_q, t->p_lnchi0, t->p_inv_dlnchi,
+                          t->p_logit_max, t->p_inv_dt, chi, r);
     return 1.0 / (1.0 + exp(-s));
 }
 

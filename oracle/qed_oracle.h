@@ -71,10 +71,13 @@ double or_pair_cdf(double chi_g, double eta);
  *   emit_q[i*n_q+k] = ln xi  with P_gamma(xi; chi_i) = r_k
  *   pair_lnh[i]     = ln h_pair(chi_i) + 8/(3 chi_i)
  *   pair_q[i*n_q+k] = logit eta with P_pm(eta; chi_i) = r_k               */
+/* interp: 0 bilinear in (ln chi, logit r); 1 the tensor-product natural
+ * cubic spline through the same nodes (READING: the paper gives neither). */
 typedef struct {
     double chi_min, chi_max;
     int32_t n_chi, n_q;
     double logit_max;
+    int32_t interp, reserved;
 } or_table_spec;
 
 int or_tables_compute(const or_table_spec *emit, const or_table_spec *pair,
@@ -90,11 +93,25 @@ typedef struct {
     int32_t p_n_chi, p_n_q;
     double p_chi_min, p_lnchi0, p_inv_dlnchi, p_logit_max, p_inv_dt;
     const double *pair_lnh, *pair_q;
+    /* quantile interpolation (or_table_spec.interp) and, for the spline, the
+     * second-derivative tables of or_quantile_spline */
+    int32_t e_interp, p_interp;
+    const double *emit_m, *pair_m;
 } or_tables;
 
 void or_tables_bind(or_tables *t, const or_table_spec *emit, const or_table_spec *pair,
                     const double *ln_hrad, const double *ln_g, const double *emit_q,
                     const double *pair_lnh, const double *pair_q);
+
+/* Second derivatives of the natural cubic splines through a quantile table
+ * q[i*n_q+j] (n_chi rows at spacing h_c in ln chi, n_q columns at spacing h_t
+ * in logit r), into m[3*n_chi*n_q]: m[0..N) = d2q/dt2 along each row,
+ * m[N..2N) = d2q/dc2 along each column, m[2N..3N) = d2/dt2 along each row of
+ * the second block (N = n_chi*n_q). */
+void or_quantile_spline(const double *q, int n_chi, int n_q, double h_c, double h_t, double *m);
+/* Attach the second-derivative tables of both quantile tables (needed when
+ * the specs given to or_tables_bind ask for the spline). */
+void or_tables_bind_spline(or_tables *t, const double *emit_m, const double *pair_m);
 
 /* table lookups as the step uses them */
 double or_lookup_h_rad(const or_tables *t, double chi, int *out_of_range);
