@@ -612,7 +612,7 @@ def main():
                  + (tal["N_push"] + tal["N_rec"]) * rec_bytes)
     ph_bytes = photon_steps * (9 * es + 16) + tal["N_pair"] * (7 * es + 8 + 2 * rec_bytes)
     calls = {
-        "qed_push_emit (lepton step: k_push_emit, k_scan_tiles, k_push_append; electrons and positrons)":
+        "qed_push_emit (lepton step: k_lepton_stream, k_scan_tiles, k_lepton_events, k_scan_tiles, k_push_append; electrons and positrons)":
             (lep_bytes, kernel_ms.get("push_e", 0.0) + kernel_ms.get("push_p", 0.0),
              n_launch.get("push_e", 0) + n_launch.get("push_p", 0), "push"),
         "qed_pair_create (photon step: k_pair_create, k_scan_tiles, k_pair_append)":

@@ -19,6 +19,7 @@ QED_OK, QED_ERR_ARG, QED_ERR_HIP, QED_ERR_CAPACITY, QED_ERR_RANGE, QED_ERR_NOMEM
 QED_F64, QED_F32 = 0, 1
 QED_FIELD_UNIFORM, QED_FIELD_PLANE_WAVE, QED_FIELD_YEE = 0, 1, 2
 QED_RAD_NONE, QED_RAD_SOKOLOV, QED_RAD_MC, QED_RAD_HYBRID = 0, 1, 2, 3
+QED_INTERP_LINEAR, QED_INTERP_SPLINE = 0, 1
 QED_N_ENERGY, QED_N_COUNT = 8, 16
 
 ENERGY_NAMES = ["work", "erad", "epush", "erec", "edrop", "esub", "epair", "_e7"]
@@ -43,7 +44,7 @@ class qed_units(C.Structure):
 
 class qed_table_spec(C.Structure):
     _fields_ = [("chi_min", C.c_double), ("chi_max", C.c_double), ("n_chi", C.c_int32),
-                ("n_q", C.c_int32), ("logit_max", C.c_double)]
+                ("n_q", C.c_int32), ("logit_max", C.c_double), ("interp", C.c_int32), ("reserved", C.c_int32)]
 
 
 class qed_species(C.Structure):
@@ -192,7 +193,8 @@ def qed_units_init(lambda_m: float) -> qed_units:
 def _spec(d) -> qed_table_spec:
     if isinstance(d, qed_table_spec):
         return d
-    return qed_table_spec(d["chi_min"], d["chi_max"], d["n_chi"], d["n_q"], d["logit_max"])
+    return qed_table_spec(d["chi_min"], d["chi_max"], d["n_chi"], d["n_q"], d["logit_max"],
+                          d.get("interp", QED_INTERP_LINEAR), 0)
 
 
 def qed_tables_compute_host(emit: dict, pair: dict) -> dict:

@@ -21,6 +21,7 @@ namespace qedtab {
 int build_tables(double e_chi_min, double e_chi_max, int e_n_chi, int e_n_q, double e_logit,
                  double p_chi_min, double p_chi_max, int p_n_chi, int p_n_q, double p_logit,
                  double *ln_hrad, double *ln_g, double *emit_q, double *pair_lnh, double *pair_q);
+void spline_quads(const double *q, int n_chi, int n_q, double h_c, double h_t, double *quad);
 }
 
 namespace {
@@ -45,7 +46,8 @@ qed_status fail(qed_status code, const char *fmt, ...) {
 
 bool spec_ok(const qed_table_spec *s) {
     return s && s->n_chi >= 2 && s->n_chi <= qed::kMaxChiNodes && s->n_q >= 2 && s->n_q <= 256 &&
-           s->chi_min > 0.0 && s->chi_max > s->chi_min && std::isfinite(s->chi_max) && s->logit_max > 0.0;
+           s->chi_min > 0.0 && s->chi_max > s->chi_min && std::isfinite(s->chi_max) && s->logit_max > 0.0 &&
+           (s->interp == QED_INTERP_LINEAR || s->interp == QED_INTERP_SPLINE) && s->reserved == 0;
 }
 
 }  // namespace
@@ -56,6 +58,8 @@ struct qed_tables {
     double *d64;      // ln_hrad | ln_g | emit_q | pair_lnh | pair_q
     float *d32;
     size_t off[6];    // element offsets of the five tables (and the total)
+    double *s64;      // spline node quads (f, f_tt, f_cc, f_cctt): emission | pair
+    float *s32;
     qed::TablesDev dev;
 };
 
@@ -154,12 +158,42 @@ qed_status qed_tables_load(const qed_table_spec *emit, const qed_table_spec *pai
         }
     if (hipMalloc(&t->d64, sizeof(double) * t->off[5]) != hipSuccess ||
         hipMalloc(&t->d32, sizeof(float) * t->off[5]) != hipSuccess) {
-        delete t;
+        qed_tables_free(t);
         return fail(QED_ERR_NOMEM, "qed_tables_load: device allocation failed");
     }
     HIP_TRY(hipMemcpy(t->d64, h64.data(), sizeof(double) * t->off[5], hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(t->d32, h32.data(), sizeof(float) * t->off[5], hipMemcpyHostToDevice));
     qed::TablesDev &d = t->dev;
+    // spline form: each node of a quantile table as four adjacent values
+    const double eh_c = (std::log(emit->chi_max) - std::log(emit->chi_min)) / (emit->n_chi - 1);
+    const double eh_t = 2.0 * emit->logit_max / (emit->n_q - 1);
+    const double ph_c = (std::log(pair->chi_max) - std::log(pair->chi_min)) / (pair->n_chi - 1);
+    const double ph_t = 2.0 * pair->logit_max / (pair->n_q - 1);
+    const size_t sq_e = emit->interp == QED_INTERP_SPLINE ? 4 * ne * nq : 0;
+    const size_t sq_p = pair->interp == QED_INTERP_SPLINE ? 4 * np * npq : 0;
+    if (sq_e + sq_p > 0) {
+        std::vector<double> s64(sq_e + sq_p);
+        if (sq_e) qedtab::spline_quads(emit_q, emit->n_chi, emit->n_q, eh_c, eh_t, s64.data());
+        if (sq_p) qedtab::spline_quads(pair_q, pair->n_chi, pair->n_q, ph_c, ph_t, s64.data() + sq_e);
+        std::vector<float> s32(s64.size());
+        for (size_t k = 0; k < s64.size(); ++k) {
+            if (!std::isfinite(s64[k])) { qed_tables_free(t); return fail(QED_ERR_ARG, "qed_tables_load: non-finite spline curvature"); }
+            s32[k] = (float)s64[k];
+        }
+        if (hipMalloc(&t->s64, sizeof(double) * s64.size()) != hipSuccess ||
+            hipMalloc(&t->s32, sizeof(float) * s32.size()) != hipSuccess) {
+            qed_tables_free(t);
+            return fail(QED_ERR_NOMEM, "qed_tables_load: device allocation failed");
+        }
+        HIP_TRY(hipMemcpy(t->s64, s64.data(), sizeof(double) * s64.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(t->s32, s32.data(), sizeof(float) * s32.size(), hipMemcpyHostToDevice));
+    }
+    d.emit_qs = sq_e ? t->s64 : nullptr;
+    d.emit_qs_f = sq_e ? t->s32 : nullptr;
+    d.pair_qs = sq_p ? t->s64 + sq_e : nullptr;
+    d.pair_qs_f = sq_p ? t->s32 + sq_e : nullptr;
+    d.e_ht26 = eh_t * eh_t / 6.0; d.e_hc26 = eh_c * eh_c / 6.0;
+    d.p_ht26 = ph_t * ph_t / 6.0; d.p_hc26 = ph_c * ph_c / 6.0;
     d.ln_hrad = t->d64 + t->off[0]; d.ln_g = t->d64 + t->off[1]; d.emit_q = t->d64 + t->off[2];
     d.pair_lnh = t->d64 + t->off[3]; d.pair_q = t->d64 + t->off[4];
     d.ln_hrad_f = t->d32 + t->off[0]; d.ln_g_f = t->d32 + t->off[1]; d.emit_q_f = t->d32 + t->off[2];
@@ -204,6 +238,8 @@ void qed_tables_free(qed_tables *t) {
     if (!t) return;
     (void)hipFree(t->d64);
     (void)hipFree(t->d32);
+    (void)hipFree(t->s64);
+    (void)hipFree(t->s32);
     delete t;
 }
 

@@ -99,6 +99,11 @@ struct TablesDev {
     double e_chi_min, e_inv_chi_min, e_h0;   // first emission node, 1/chi there, h_rad there
     double e_lnchi0, e_inv_dlnchi, e_logit_max, e_inv_dt;
     double p_chi_min, p_lnchi0, p_inv_dlnchi, p_logit_max, p_inv_dt;
+    // spline form of the quantile tables (null when bilinear): per node the
+    // value and its curvatures f_tt, f_cc, f_cctt; h^2/6 of both node spacings
+    const double *emit_qs, *pair_qs;
+    const float *emit_qs_f, *pair_qs_f;
+    double e_ht26, e_hc26, p_ht26, p_hc26;
 };
 
 template <typename R> __device__ __forceinline__ const R *emit_q_ptr(const TablesDev &t);
@@ -107,6 +112,12 @@ template <> __device__ __forceinline__ const float *emit_q_ptr<float>(const Tabl
 template <typename R> __device__ __forceinline__ const R *pair_q_ptr(const TablesDev &t);
 template <> __device__ __forceinline__ const double *pair_q_ptr<double>(const TablesDev &t) { return t.pair_q; }
 template <> __device__ __forceinline__ const float *pair_q_ptr<float>(const TablesDev &t) { return t.pair_q_f; }
+template <typename R> __device__ __forceinline__ const R *emit_qs_ptr(const TablesDev &t);
+template <> __device__ __forceinline__ const double *emit_qs_ptr<double>(const TablesDev &t) { return t.emit_qs; }
+template <> __device__ __forceinline__ const float *emit_qs_ptr<float>(const TablesDev &t) { return t.emit_qs_f; }
+template <typename R> __device__ __forceinline__ const R *pair_qs_ptr(const TablesDev &t);
+template <> __device__ __forceinline__ const double *pair_qs_ptr<double>(const TablesDev &t) { return t.pair_qs; }
+template <> __device__ __forceinline__ const float *pair_qs_ptr<float>(const TablesDev &t) { return t.pair_qs_f; }
 template <typename R> __device__ __forceinline__ const R *rate_ptr(const TablesDev &t, int which);
 template <> __device__ __forceinline__ const double *rate_ptr<double>(const TablesDev &t, int w) {
     return w == 0 ? t.ln_hrad : (w == 1 ? t.ln_g : t.pair_lnh);
@@ -150,12 +161,23 @@ __device__ __forceinline__ R g_at(const R *s_lg, const TablesDev &tb, R lnchi0, 
     return Math<R>::exp_(lerp_rate<R>(s_lg, tb.e_n_chi, lnchi0, inv_d, Math<R>::log_(chi), above));
 }
 
-// Bilinear lookup in (ln chi, logit r) of a quantile table in global memory
+// One cubic segment of a natural spline at fraction z of its step:
+// (1-z) f0 + z f1 + (h^2/6) [((1-z)^3 - (1-z)) m0 + (z^3 - z) m1].
+template <typename R>
+__device__ __forceinline__ R spline_seg(R f0, R f1, R m0, R m1, R z, R h26) {
+    const R a = R(1) - z;
+    return a * f0 + z * f1 + ((a * a - R(1)) * a * m0 + (z * z - R(1)) * z * m1) * h26;
+}
+
+// Lookup in (ln chi, logit r) of a quantile table in global memory
 // (L2-resident); chi is clamped to the node range.  The logit of r is taken
 // in FP64 so that the extreme levels keep their resolution in both forms.
+// With qs null: bilinear in the node cell.  With qs (four values per node:
+// f, f_tt, f_cc, f_cctt): the tensor-product natural cubic spline, first
+// along t in the cell's two rows (for f and for f_cc), then along ln chi.
 template <typename R>
-__device__ __forceinline__ R quantile(const R *q, int n_chi, int n_q, R lnchi0, R inv_d,
-                                      double logit_max, double inv_dt, R lnchi, double r) {
+__device__ __forceinline__ R quantile(const R *q, const R *qs, R ht26, R hc26, int n_chi, int n_q, R lnchi0,
+                                      R inv_d, double logit_max, double inv_dt, R lnchi, double r) {
     R u = (lnchi - lnchi0) * inv_d;
     if (!(u > R(0))) u = R(0);
     if (u > R(n_chi - 1)) u = R(n_chi - 1);
@@ -169,6 +191,14 @@ __device__ __forceinline__ R quantile(const R *q, int n_chi, int n_q, R lnchi0, 
     int j = (int)v;
     if (j > n_q - 2) j = n_q - 2;
     const R z = (R)(v - (double)j);
+    if (qs) {
+        const R *n0 = qs + 4 * ((size_t)i * n_q + j), *n1 = n0 + 4 * (size_t)n_q;
+        const R f0 = spline_seg<R>(n0[0], n0[4], n0[1], n0[5], z, ht26);
+        const R f1 = spline_seg<R>(n1[0], n1[4], n1[1], n1[5], z, ht26);
+        const R c0 = spline_seg<R>(n0[2], n0[6], n0[3], n0[7], z, ht26);
+        const R c1 = spline_seg<R>(n1[2], n1[6], n1[3], n1[7], z, ht26);
+        return spline_seg<R>(f0, f1, c0, c1, w, hc26);
+    }
     const R *r0 = q + (size_t)i * n_q + j;
     const R *r1 = r0 + n_q;
     const R a = r0[0] + z * (r0[1] - r0[0]);
@@ -217,12 +247,14 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t &total) 
 
 // Sum over the wave, on every lane: row sums through DPP (quad permutations,
 // row rotations), then the four rows.  The wave must be fully active.
+// (The DPP patterns used below read a valid source lane for every lane, so
+// the moves need no prior value in their destination.)
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
     int x = (int)v;
-    x += __builtin_amdgcn_update_dpp(x, x, 0xb1, 0xf, 0xf, false);    // quad_perm 1,0,3,2
-    x += __builtin_amdgcn_update_dpp(x, x, 0x4e, 0xf, 0xf, false);    // quad_perm 2,3,0,1
-    x += __builtin_amdgcn_update_dpp(x, x, 0x124, 0xf, 0xf, false);   // row_ror 4
-    x += __builtin_amdgcn_update_dpp(x, x, 0x128, 0xf, 0xf, false);   // row_ror 8
+    x += __builtin_amdgcn_mov_dpp(x, 0xb1, 0xf, 0xf, false);     // quad_perm 1,0,3,2
+    x += __builtin_amdgcn_mov_dpp(x, 0x4e, 0xf, 0xf, false);     // quad_perm 2,3,0,1
+    x += __builtin_amdgcn_mov_dpp(x, 0x124, 0xf, 0xf, false);    // row_ror 4
+    x += __builtin_amdgcn_mov_dpp(x, 0x128, 0xf, 0xf, false);    // row_ror 8
     return (uint32_t)__builtin_amdgcn_readlane(x, 0) + (uint32_t)__builtin_amdgcn_readlane(x, 16) +
            (uint32_t)__builtin_amdgcn_readlane(x, 32) + (uint32_t)__builtin_amdgcn_readlane(x, 48);
 }
@@ -233,8 +265,8 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 __device__ __forceinline__ double wave_sum_f64_dpp(double v) {
     auto step = [](double x, auto ctrl) {
         const uint64_t b = __builtin_bit_cast(uint64_t, x);
-        const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, decltype(ctrl)::value, 0xf, 0xf, false);
-        const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), decltype(ctrl)::value, 0xf, 0xf, false);
+        const int lo = __builtin_amdgcn_mov_dpp((int)b, decltype(ctrl)::value, 0xf, 0xf, false);
+        const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), decltype(ctrl)::value, 0xf, 0xf, false);
         return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
     };
     v += step(v, std::integral_constant<int, 0xb1>{});    // quad_perm 1,0,3,2

@@ -205,10 +205,10 @@ constexpr int kWBFloats = 6 * kWBVol;
 // active.
 __device__ __forceinline__ int wave_min_i32(int v) {
     auto mn = [](int a, int b) { return a < b ? a : b; };
-    v = mn(v, __builtin_amdgcn_update_dpp(v, v, 0xb1, 0xf, 0xf, false));    // quad_perm 1,0,3,2
-    v = mn(v, __builtin_amdgcn_update_dpp(v, v, 0x4e, 0xf, 0xf, false));    // quad_perm 2,3,0,1
-    v = mn(v, __builtin_amdgcn_update_dpp(v, v, 0x124, 0xf, 0xf, false));   // row_ror 4
-    v = mn(v, __builtin_amdgcn_update_dpp(v, v, 0x128, 0xf, 0xf, false));   // row_ror 8
+    v = mn(v, __builtin_amdgcn_mov_dpp(v, 0xb1, 0xf, 0xf, false));     // quad_perm 1,0,3,2
+    v = mn(v, __builtin_amdgcn_mov_dpp(v, 0x4e, 0xf, 0xf, false));     // quad_perm 2,3,0,1
+    v = mn(v, __builtin_amdgcn_mov_dpp(v, 0x124, 0xf, 0xf, false));    // row_ror 4
+    v = mn(v, __builtin_amdgcn_mov_dpp(v, 0x128, 0xf, 0xf, false));    // row_ror 8
     return mn(mn(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
               mn(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
@@ -339,8 +339,9 @@ __device__ __forceinline__ void wave_energy(const TallyDev &tal, int64_t tile, d
         if (__ballot(e[k] != 0.0) == 0ull) continue;
         const double s = wave_sum_f64_dpp(e[k]);
         if (lane_id() == 0 && s != 0.0) {
-            double *slot = tal.energy + (tile % tal.n_slots) * kNEnergy + k;
-            unsafeAtomicAdd(slot, s);
+            // a tally sized for the launch has a slot per tile: no division then
+            const int64_t sl = tile < tal.n_slots ? tile : tile % tal.n_slots;
+            unsafeAtomicAdd(tal.energy + sl * kNEnergy + k, s);
         }
     }
 }
@@ -395,6 +396,17 @@ struct Emitted {
         n = k + 1;
     }
 };
+
+// The address of element `first` of p in scalar registers (`first` is uniform
+// over the wave): an access to element first + lane then takes a fixed 32-bit
+// lane offset from it, with no 64-bit vector address arithmetic.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *wave_base(T *p, int64_t first) {
+    const uint64_t v = (uint64_t)(p + first);
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (__attribute__((address_space(1))) T *)((hi << 32) | lo);
+}
 
 // Bunch of each lane in the batched form (bunch b holds [offsets[b],
 // offsets[b+1])): the wave counts the offsets at or below its first particle,
@@ -475,10 +487,12 @@ k_lepton_stream(PushArgs a) {
     int64_t chunk = xcd_tile(0, n_chunks);
     R n_x = R(0), n_y = R(0), n_z = R(0), n_ux = R(0), n_uy = R(0), n_uz = R(0), n_w = R(0);
     double n_tau = 0.0;
+    const uint32_t ul = (uint32_t)lane;
     if (chunk >= 0 && chunk * blockDim.x + tid < n) {
-        const int64_t j = chunk * blockDim.x + tid;
-        n_x = X[j]; n_y = Y[j]; n_z = Z[j]; n_ux = UX[j]; n_uy = UY[j]; n_uz = UZ[j]; n_w = Wt[j];
-        n_tau = a.lep.tau[j];
+        const int64_t b = (chunk * nw + wid) * kWave;
+        n_x = wave_base(X, b)[ul]; n_y = wave_base(Y, b)[ul]; n_z = wave_base(Z, b)[ul];
+        n_ux = wave_base(UX, b)[ul]; n_uy = wave_base(UY, b)[ul]; n_uz = wave_base(UZ, b)[ul];
+        n_w = wave_base(Wt, b)[ul]; n_tau = wave_base(a.lep.tau, b)[ul];
     }
     for (int64_t it = 0; chunk >= 0; ++it) {
         const int64_t tile = chunk * nw + wid;             // = i / 64
@@ -488,10 +502,12 @@ k_lepton_stream(PushArgs a) {
         const double tau_i = n_tau;
         const int64_t next = xcd_tile(it + 1, n_chunks);
         if (next >= 0 && next * blockDim.x + tid < n) {
-            const int64_t j = next * blockDim.x + tid;
-            n_x = X[j]; n_y = Y[j]; n_z = Z[j]; n_ux = UX[j]; n_uy = UY[j]; n_uz = UZ[j]; n_w = Wt[j];
-            n_tau = a.lep.tau[j];
+            const int64_t b = (next * nw + wid) * kWave;
+            n_x = wave_base(X, b)[ul]; n_y = wave_base(Y, b)[ul]; n_z = wave_base(Z, b)[ul];
+            n_ux = wave_base(UX, b)[ul]; n_uy = wave_base(UY, b)[ul]; n_uz = wave_base(UZ, b)[ul];
+            n_w = wave_base(Wt, b)[ul]; n_tau = wave_base(a.lep.tau, b)[ul];
         }
+        const int64_t tile0 = tile * kWave;                 // = i - lane
         double en[kNEnergy];
 #pragma unroll
         for (int k = 0; k < kNEnergy; ++k) en[k] = 0.0;
@@ -571,16 +587,16 @@ k_lepton_stream(PushArgs a) {
                 }
                 tau = tau_i;
                 const double Wd = (double)W;
-                if (!(W > R(0)) || tau > Wd * dt) a.lep.tau[i] = tau - Wd * dt;
+                if (!(W > R(0)) || tau > Wd * dt) wave_base(a.lep.tau, tile0)[ul] = tau - Wd * dt;
                 else event = true;                          // finished by the event pass
             }
             if (!event) {
                 const R gn = Math<R>::sqrt_(R(1) + (unx * unx + uny * uny + unz * unz));
                 const R ign = Math<R>::rcp_(gn);
-                X[i] = x + dtr * (unx * ign + dvx);
-                Y[i] = y + dtr * (uny * ign + dvy);
-                Z[i] = z + dtr * (unz * ign + dvz);
-                UX[i] = unx; UY[i] = uny; UZ[i] = unz;
+                wave_base(X, tile0)[ul] = x + dtr * (unx * ign + dvx);
+                wave_base(Y, tile0)[ul] = y + dtr * (uny * ign + dvy);
+                wave_base(Z, tile0)[ul] = z + dtr * (unz * ign + dvz);
+                wave_base(UX, tile0)[ul] = unx; wave_base(UY, tile0)[ul] = uny; wave_base(UZ, tile0)[ul] = unz;
             }
         }
         uint32_t n_items;
@@ -606,8 +622,10 @@ k_lepton_stream(PushArgs a) {
 // after it; then the particle's new momentum, position, tau and event
 // counter.  Photons to be stored go to an emission record at the item's
 // dense position; the counts of each 64-item chunk go to tile_cnt0/1 for the
-// scan of the appends.
-template <typename R>
+// scan of the appends.  kSpline: the quantile table is read through the
+// spline (a separate instantiation, so that the bilinear form keeps its
+// registers).
+template <typename R, bool kSpline>
 __global__ void __launch_bounds__(256)
 k_lepton_events(PushArgs a) {
     __shared__ R s_lh[kMaxChiNodes];
@@ -623,7 +641,7 @@ k_lepton_events(PushArgs a) {
     const R dtr = (R)dt;
     const R es_inv = (R)a.c.es_inv, Ah = (R)a.c.A;
     const R lnchi0 = (R)tb.e_lnchi0, inv_d = (R)tb.e_inv_dlnchi;
-    const R *qtab = emit_q_ptr<R>(tb);
+    const R *qtab = emit_q_ptr<R>(tb), *qspl = kSpline ? emit_qs_ptr<R>(tb) : nullptr;
     R *X = (R *)a.lep.x, *Y = (R *)a.lep.y, *Z = (R *)a.lep.z;
     R *UX = (R *)a.lep.ux, *UY = (R *)a.lep.uy, *UZ = (R *)a.lep.uz;
     const ItemRec<R> *items = (const ItemRec<R> *)a.ws.stage.item;
@@ -667,8 +685,8 @@ k_lepton_events(PushArgs a) {
                 t_left -= (tau > 0.0 ? tau : 0.0) / Wd;
                 const U64x4 o = philox4x64_10(uid, (uint64_t)nev, (uint64_t)RNG_EMIT, 0ull, a.st.seed, 0ull);
                 const double r1 = u01(o.a), r2 = u01(o.b);
-                R xi = Math<R>::exp_(quantile<R>(qtab, tb.e_n_chi, tb.e_n_q, lnchi0, inv_d,
-                                                 tb.e_logit_max, tb.e_inv_dt, Math<R>::log_(ce), r1));
+                R xi = Math<R>::exp_(quantile<R>(qtab, qspl, (R)tb.e_ht26, (R)tb.e_hc26, tb.e_n_chi, tb.e_n_q,
+                                                 lnchi0, inv_d, tb.e_logit_max, tb.e_inv_dt, Math<R>::log_(ce), r1));
                 if (xi > R(1)) xi = R(1);
                 const R gg = xi * gam;
                 cnt[C_EMIT]++;
@@ -1101,8 +1119,9 @@ k_pair_create(PairArgs a) {
     block_counts(a.tal, cnt, s_cnt);
 }
 
-// Append pass of the photon step: e- and e+ of each marked photon.
-template <typename R, int FK>
+// Append pass of the photon step: e- and e+ of each marked photon (kSpline as
+// for the lepton event pass).
+template <typename R, int FK, bool kSpline>
 __global__ void __launch_bounds__(256)
 k_pair_append(PairArgs a) {
     __shared__ uint32_t s_wave[3 * kMaxWaves];
@@ -1119,7 +1138,7 @@ k_pair_append(PairArgs a) {
     const R dtr = (R)a.st.dt;
     const R es_inv = (R)a.c.es_inv;
     const R lnchi0 = (R)tb.p_lnchi0, inv_d = (R)tb.p_inv_dlnchi;
-    const R *qtab = pair_q_ptr<R>(tb);
+    const R *qtab = pair_q_ptr<R>(tb), *qspl = kSpline ? pair_qs_ptr<R>(tb) : nullptr;
     int cnt[N_COUNT_USED];
 #pragma unroll
     for (int k = 0; k < N_COUNT_USED; ++k) cnt[k] = 0;
@@ -1144,8 +1163,8 @@ k_pair_append(PairArgs a) {
                 const R khx = kx / kk, khy = ky / kk, khz = kz / kk;
                 const U64x4 o = philox4x64_10(a.ph.uid[i], (uint64_t)a.ph.n_ev[i], (uint64_t)RNG_PAIR, 0ull,
                                               a.st.seed, 0ull);
-                const R s = quantile<R>(qtab, tb.p_n_chi, tb.p_n_q, lnchi0, inv_d, tb.p_logit_max,
-                                        tb.p_inv_dt, Math<R>::log_(chig), u01(o.a));
+                const R s = quantile<R>(qtab, qspl, (R)tb.p_ht26, (R)tb.p_hc26, tb.p_n_chi, tb.p_n_q, lnchi0,
+                                        inv_d, tb.p_logit_max, tb.p_inv_dt, Math<R>::log_(chig), u01(o.a));
                 const R eta = R(1) / (R(1) + Math<R>::exp_(-s));
                 const R chim = eta * chig;
                 const R chip = chig - chim;
@@ -1381,8 +1400,14 @@ hipError_t launch_lepton_stream(const PushArgs &a, int prec, int fk, dim3 grid, 
 }
 
 hipError_t launch_lepton_events(const PushArgs &a, int prec, dim3 grid, dim3 block, hipStream_t s) {
-    if (prec == 0) hipLaunchKernelGGL((k_lepton_events<double>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_lepton_events<float>), grid, block, 0, s, a);
+    const bool spl = a.tab.emit_qs != nullptr;
+    if (prec == 0) {
+        if (spl) hipLaunchKernelGGL((k_lepton_events<double, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_lepton_events<double, false>), grid, block, 0, s, a);
+    } else {
+        if (spl) hipLaunchKernelGGL((k_lepton_events<float, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_lepton_events<float, false>), grid, block, 0, s, a);
+    }
     return hipGetLastError();
 }
 
@@ -1415,18 +1440,22 @@ hipError_t launch_pair_create(const PairArgs &a, int prec, int fk, dim3 grid, di
     return prec == 0 ? launch_pair<double>(a, fk, grid, block, s) : launch_pair<float>(a, fk, grid, block, s);
 }
 
-template <typename R>
+template <typename R, bool kSpline>
 hipError_t launch_pair_app(const PairArgs &a, int fk, dim3 grid, dim3 block, hipStream_t s) {
     switch (fk) {
-    case FIELD_UNIFORM: hipLaunchKernelGGL((k_pair_append<R, FIELD_UNIFORM>), grid, block, 0, s, a); break;
-    case FIELD_PLANE: hipLaunchKernelGGL((k_pair_append<R, FIELD_PLANE>), grid, block, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_pair_append<R, FIELD_YEE>), grid, block, 0, s, a); break;
+    case FIELD_UNIFORM: hipLaunchKernelGGL((k_pair_append<R, FIELD_UNIFORM, kSpline>), grid, block, 0, s, a); break;
+    case FIELD_PLANE: hipLaunchKernelGGL((k_pair_append<R, FIELD_PLANE, kSpline>), grid, block, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_pair_append<R, FIELD_YEE, kSpline>), grid, block, 0, s, a); break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_pair_append(const PairArgs &a, int prec, int fk, dim3 grid, dim3 block, hipStream_t s) {
-    return prec == 0 ? launch_pair_app<double>(a, fk, grid, block, s) : launch_pair_app<float>(a, fk, grid, block, s);
+    if (a.tab.pair_qs != nullptr)
+        return prec == 0 ? launch_pair_app<double, true>(a, fk, grid, block, s)
+                         : launch_pair_app<float, true>(a, fk, grid, block, s);
+    return prec == 0 ? launch_pair_app<double, false>(a, fk, grid, block, s)
+                     : launch_pair_app<float, false>(a, fk, grid, block, s);
 }
 
 hipError_t launch_compact(const CompactArgs &a, int prec, dim3 grid, dim3 block, hipStream_t s) {

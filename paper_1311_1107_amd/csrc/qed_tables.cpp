@@ -296,4 +296,43 @@ int build_tables(double e_chi_min, double e_chi_max, int e_n_chi, int e_n_q, dou
     return 0;
 }
 
+// Curvature of the natural cubic spline (zero second derivative at both
+// ends) through n values spaced h apart, read with stride `step`: the
+// interior second derivatives solve the tridiagonal system
+//   c[k-1] + 4 c[k] + c[k+1] = 6 (y[k-1] - 2 y[k] + y[k+1]) / h^2.
+// Gaussian elimination down the band, then back substitution.
+static void spline_curvature(const double *y, size_t step, int n, double h, double *c, size_t cstep) {
+    std::vector<double> diag(n, 4.0), rhs(n, 0.0);
+    c[0] = 0.0;
+    c[(size_t)(n - 1) * cstep] = 0.0;
+    if (n < 3) return;
+    for (int k = 1; k < n - 1; ++k)
+        rhs[k] = 6.0 * (y[(k - 1) * step] - 2.0 * y[k * step] + y[(k + 1) * step]) / (h * h);
+    for (int k = 2; k < n - 1; ++k) {          // eliminate the sub-diagonal (all ones)
+        const double f = 1.0 / diag[k - 1];
+        diag[k] -= f;
+        rhs[k] -= f * rhs[k - 1];
+    }
+    double next = 0.0;
+    for (int k = n - 2; k >= 1; --k) {
+        next = (rhs[k] - next) / diag[k];
+        c[k * cstep] = next;
+    }
+}
+
+void spline_quads(const double *q, int n_chi, int n_q, double h_c, double h_t, double *quad) {
+    const size_t N = (size_t)n_chi * n_q;
+    std::vector<double> ctt(N), ccc(N), cccc(N);
+    for (int i = 0; i < n_chi; ++i) spline_curvature(q + (size_t)i * n_q, 1, n_q, h_t, &ctt[(size_t)i * n_q], 1);
+    for (int j = 0; j < n_q; ++j) spline_curvature(q + j, n_q, n_chi, h_c, &ccc[j], n_q);
+    for (int i = 0; i < n_chi; ++i)
+        spline_curvature(&ccc[(size_t)i * n_q], 1, n_q, h_t, &cccc[(size_t)i * n_q], 1);
+    for (size_t k = 0; k < N; ++k) {
+        quad[4 * k + 0] = q[k];
+        quad[4 * k + 1] = ctt[k];
+        quad[4 * k + 2] = ccc[k];
+        quad[4 * k + 3] = cccc[k];
+    }
+}
+
 }  // namespace qedtab

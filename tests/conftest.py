@@ -23,3 +23,13 @@ def oracle_tables():
 def bound_tables(oracle_tables):
     from oracle import oracle as O
     return O.BoundTables(oracle_tables)
+
+
+@pytest.fixture(scope="session")
+def spline_tables(oracle_tables):
+    """The same tables read through the natural bicubic spline (interp = 1)."""
+    from oracle import oracle as O
+    t = dict(oracle_tables)
+    t["emit_spec"] = dict(oracle_tables["emit_spec"], interp=O.INTERP_SPLINE)
+    t["pair_spec"] = dict(oracle_tables["pair_spec"], interp=O.INTERP_SPLINE)
+    return O.BoundTables(t)

@@ -47,6 +47,21 @@ def gpu_oracle_tables(oracle_tables):
     return D.Tables(O.EMIT_SPEC, O.PAIR_SPEC, arrays=oracle_tables)
 
 
+@pytest.fixture(scope="module")
+def gpu_spline_tables(oracle_tables):
+    _need_gpu()
+    return D.Tables(dict(O.EMIT_SPEC, interp=B.QED_INTERP_SPLINE), dict(O.PAIR_SPEC, interp=B.QED_INTERP_SPLINE),
+                    arrays=oracle_tables)
+
+
+def _tables_for(case, request):
+    """(oracle tables, device tables) of a case; '_spline' cases read the
+    quantile tables through the natural bicubic spline on both sides."""
+    if case.endswith("_spline"):
+        return request.getfixturevalue("spline_tables"), request.getfixturevalue("gpu_spline_tables")
+    return request.getfixturevalue("bound_tables"), request.getfixturevalue("gpu_oracle_tables")
+
+
 def _to_f32(state: dict) -> dict:
     out = {k: np.array(v, copy=True) for k, v in state.items()}
     for k in REALS:
@@ -108,9 +123,10 @@ def _lepton_case(name, tabs):
     return wl, k, mid
 
 
-@pytest.mark.parametrize("case", ["plane", "yee"])
-def test_fp32_lepton_one_step(gpu_oracle_tables, bound_tables, case):
-    wl, k, mid = _lepton_case(case, bound_tables)
+@pytest.mark.parametrize("case", ["plane", "yee", "plane_spline"])
+def test_fp32_lepton_one_step(request, case):
+    bound_tables, gpu_oracle_tables = _tables_for(case, request)
+    wl, k, mid = _lepton_case(case.replace("_spline", ""), bound_tables)
     print(f"case: FP32 lepton one step, {case}, step {k}", flush=True)
     state = _to_f32(mid["electrons"])
     m0 = len(state["x"])
@@ -177,11 +193,12 @@ def _photon_case(name, tabs):
     return wl, k, mid
 
 
-@pytest.mark.parametrize("case", ["constant_b", "yee"])
-def test_fp32_photon_and_pair_one_step(gpu_oracle_tables, bound_tables, case):
+@pytest.mark.parametrize("case", ["constant_b", "yee", "constant_b_spline"])
+def test_fp32_photon_and_pair_one_step(request, case):
     """Photon step of the FP32 form (chi_gamma, pair rate, Breit-Wheeler pair
     creation, push) from identical state against the FP64 oracle."""
-    wl, k, mid = _photon_case(case, bound_tables)
+    bound_tables, gpu_oracle_tables = _tables_for(case, request)
+    wl, k, mid = _photon_case(case.replace("_spline", ""), bound_tables)
     print(f"case: FP32 photon one step, {case}, step {k}", flush=True)
     phs = _to_f32(mid["photons"])
     m0 = len(phs["x"])
