@@ -324,7 +324,7 @@ qed_status qed_push_emit(const qed_tables *tab, qed_workspace *ws, const qed_uni
 /* The same step as qed_push_emit for callers that cannot allocate (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * no qed_workspace; the look-back words, per-tile counts and emission
- * records live in a static device array of the library (about 17.7 MB,
+ * records live in a static device array of the library (about 18.0 MB,
  * held on each GPU the library runs on until the process ends), and the call
  * makes no allocation.  lep->capacity must not exceed 65536 (QED_ERR_ARG
  * otherwise).  d_status [device] is 6 words the caller zeroes once: the call

@@ -214,9 +214,11 @@ __device__ __forceinline__ int wave_min_i32(int v) {
 }
 
 // Called by all lanes of the wave; act marks lanes that need the field.
-template <typename R>
+// after_loads() runs once, as soon as the gather's own grid loads have been
+// consumed: memory operations it issues are not waited for by the gather.
+template <typename R, typename AfterLoads>
 __device__ __forceinline__ void yee_gather_wave(const FieldDev &f, bool act, R x, R y, R z, R E[3], R B[3],
-                                                float *box) {
+                                                float *box, AfterLoads &&after_loads) {
     const int64_t nx = f.nx, ny = f.ny, nz = f.nz, ncell = nx * ny * nz;
     Stencil<R> st;
     make_stencil<R>(f, x, y, z, st);
@@ -233,6 +235,7 @@ __device__ __forceinline__ void yee_gather_wave(const FieldDev &f, bool act, R x
     const uint64_t m_near = __ballot(near);
     if (m_near == 0ull) {                                   // the whole wave sees a zero field
         E[0] = E[1] = E[2] = B[0] = B[1] = B[2] = R(0);
+        after_loads();
         return;
     }
     int o[3], ext[3];
@@ -244,6 +247,7 @@ __device__ __forceinline__ void yee_gather_wave(const FieldDev &f, bool act, R x
     if (ext[0] > kWBX || ext[1] > kWBY || ext[2] > kWBZ) {
         if (near) yee_gather<R>(f, x, y, z, E, B);
         else E[0] = E[1] = E[2] = B[0] = B[1] = B[2] = R(0);
+        after_loads();
         return;
     }
     // stage the box: node e = (p kWBY + q) kWBZ + r; every load of the lane is
@@ -277,6 +281,7 @@ __device__ __forceinline__ void yee_gather_wave(const FieldDev &f, bool act, R x
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    after_loads();
     R out[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
@@ -377,6 +382,9 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t it, int64_t n_tiles) {
     const int64_t t = lo + l + it * g8;
     return t < hi ? t : -1;
 }
+
+// s_waitcnt vmcnt(0), leaving the other counters free (expcnt 7, lgkmcnt 15)
+constexpr int kWaitVmem = 0x0F70;
 
 // ------------------------------------------------------------------------
 // Lepton step: Boris push, chi_e, Sokolov or optical-depth Monte Carlo.
@@ -501,12 +509,16 @@ k_lepton_stream(PushArgs a) {
         const R x = n_x, y = n_y, z = n_z, ux = n_ux, uy = n_uy, uz = n_uz, wgt_i = n_w;
         const double tau_i = n_tau;
         const int64_t next = xcd_tile(it + 1, n_chunks);
-        if (next >= 0 && next * blockDim.x + tid < n) {
-            const int64_t b = (next * nw + wid) * kWave;
-            n_x = wave_base(X, b)[ul]; n_y = wave_base(Y, b)[ul]; n_z = wave_base(Z, b)[ul];
-            n_ux = wave_base(UX, b)[ul]; n_uy = wave_base(UY, b)[ul]; n_uz = wave_base(UZ, b)[ul];
-            n_w = wave_base(Wt, b)[ul]; n_tau = wave_base(a.lep.tau, b)[ul];
-        }
+        auto prefetch = [&]() {
+            if (next >= 0 && next * blockDim.x + tid < n) {
+                const int64_t b = (next * nw + wid) * kWave;
+                n_x = wave_base(X, b)[ul]; n_y = wave_base(Y, b)[ul]; n_z = wave_base(Z, b)[ul];
+                n_ux = wave_base(UX, b)[ul]; n_uy = wave_base(UY, b)[ul]; n_uz = wave_base(UZ, b)[ul];
+                n_w = wave_base(Wt, b)[ul]; n_tau = wave_base(a.lep.tau, b)[ul];
+            }
+        };
+        // with a grid the loads go out after the gather's (whose wait would include them)
+        if constexpr (FK != FIELD_YEE) prefetch();
         const int64_t tile0 = tile * kWave;                 // = i - lane
         double en[kNEnergy];
 #pragma unroll
@@ -520,10 +532,11 @@ k_lepton_stream(PushArgs a) {
             if (live) { a0 = a.f.a0s[b]; Phi = 2.0 * kPi * a.f.nper[b]; inv_Phi = 1.0 / Phi; }
         }
         R E[3], B[3];
-        if constexpr (FK == FIELD_YEE) yee_gather_wave<R>(a.f, live, x, y, z, E, B, s_box + wid * kWBFloats);
-        bool event = false;
+        if constexpr (FK == FIELD_YEE) yee_gather_wave<R>(a.f, live, x, y, z, E, B, s_box + wid * kWBFloats, prefetch);
+        bool event = false, put_tau = false;
         R uLx = R(0), uLy = R(0), uLz = R(0), gL = R(1), chi = R(0), W = R(0), wgt = R(0);
-        double tau = 0.0;
+        R xn = R(0), yn = R(0), zn = R(0), unx = R(0), uny = R(0), unz = R(0);
+        double tau = 0.0, tau_new = 0.0;
         if (live) {
             if constexpr (FK != FIELD_YEE) field_at<R, FK>(a.f, t, x, y, z, a0, Phi, inv_Phi, E, B);
             const R g_old = Math<R>::sqrt_(R(1) + (ux * ux + uy * uy + uz * uz));
@@ -548,7 +561,7 @@ k_lepton_stream(PushArgs a) {
             en[E_WORK] = (double)wgt * (double)(gL - g_old);
 
             chi = chi_of<R>(es_inv, gL, uLx, uLy, uLz, E, B);
-            R unx = uLx, uny = uLy, unz = uLz;
+            unx = uLx; uny = uLy; unz = uLz;
             R dvx = R(0), dvy = R(0), dvz = R(0);
             int rad = a.st.rad;
             if (!isfinite((double)chi) || !isfinite((double)gL)) { cnt[C_NAN]++; rad = RAD_NONE; status_flag(a.ws.status, 2ull); }
@@ -587,17 +600,26 @@ k_lepton_stream(PushArgs a) {
                 }
                 tau = tau_i;
                 const double Wd = (double)W;
-                if (!(W > R(0)) || tau > Wd * dt) wave_base(a.lep.tau, tile0)[ul] = tau - Wd * dt;
+                if (!(W > R(0)) || tau > Wd * dt) { put_tau = true; tau_new = tau - Wd * dt; }
                 else event = true;                          // finished by the event pass
             }
             if (!event) {
                 const R gn = Math<R>::sqrt_(R(1) + (unx * unx + uny * uny + unz * unz));
                 const R ign = Math<R>::rcp_(gn);
-                wave_base(X, tile0)[ul] = x + dtr * (unx * ign + dvx);
-                wave_base(Y, tile0)[ul] = y + dtr * (uny * ign + dvy);
-                wave_base(Z, tile0)[ul] = z + dtr * (unz * ign + dvz);
-                wave_base(UX, tile0)[ul] = unx; wave_base(UY, tile0)[ul] = uny; wave_base(UZ, tile0)[ul] = unz;
+                xn = x + dtr * (unx * ign + dvx);
+                yn = y + dtr * (uny * ign + dvy);
+                zn = z + dtr * (unz * ign + dvz);
             }
+        }
+        // The next tile's loads went out before the arithmetic above.  Wait for
+        // them here, before this tile's stores: the memory counter retires in
+        // issue order, so a wait placed after the stores (where the loaded
+        // registers are next read) would wait for the stores as well.
+        __builtin_amdgcn_s_waitcnt(kWaitVmem);
+        if (put_tau) wave_base(a.lep.tau, tile0)[ul] = tau_new;
+        if (live && !event) {
+            wave_base(X, tile0)[ul] = xn; wave_base(Y, tile0)[ul] = yn; wave_base(Z, tile0)[ul] = zn;
+            wave_base(UX, tile0)[ul] = unx; wave_base(UY, tile0)[ul] = uny; wave_base(UZ, tile0)[ul] = unz;
         }
         uint32_t n_items;
         const uint32_t rank = ballot_excl(event, n_items);
@@ -1001,11 +1023,12 @@ k_pair_create(PairArgs a) {
     int64_t chunk = xcd_tile(0, n_chunks);
     double n_tau = HUGE_VAL;
     R n_x = R(0), n_y = R(0), n_z = R(0), n_kx = R(0), n_ky = R(0), n_kz = R(0);
+    const uint32_t ul = (uint32_t)lane;
     if (chunk >= 0 && chunk * blockDim.x + tid < n) {
-        const int64_t j = chunk * blockDim.x + tid;
-        n_tau = a.ph.tau[j];
-        n_x = X[j]; n_y = Y[j]; n_z = Z[j];
-        n_kx = KX[j]; n_ky = KY[j]; n_kz = KZ[j];
+        const int64_t b = (chunk * nw + wid) * kWave;
+        n_tau = wave_base(a.ph.tau, b)[ul];
+        n_x = wave_base(X, b)[ul]; n_y = wave_base(Y, b)[ul]; n_z = wave_base(Z, b)[ul];
+        n_kx = wave_base(KX, b)[ul]; n_ky = wave_base(KY, b)[ul]; n_kz = wave_base(KZ, b)[ul];
     }
     for (int64_t it = 0; chunk >= 0; ++it) {
         const int64_t tile = chunk * nw + wid;              // = i / 64
@@ -1019,16 +1042,21 @@ k_pair_create(PairArgs a) {
         const bool live = i < n && tau != HUGE_VAL;
         if (!live) x = y = z = kx = ky = kz = R(0);
         const int64_t next = xcd_tile(it + 1, n_chunks);
-        n_tau = HUGE_VAL;
-        if (next >= 0 && next * blockDim.x + tid < n) {
-            const int64_t j = next * blockDim.x + tid;
-            n_tau = a.ph.tau[j];
-            n_x = X[j]; n_y = Y[j]; n_z = Z[j];
-            n_kx = KX[j]; n_ky = KY[j]; n_kz = KZ[j];
-        }
+        auto prefetch = [&]() {
+            n_tau = HUGE_VAL;
+            if (next >= 0 && next * blockDim.x + tid < n) {
+                const int64_t b = (next * nw + wid) * kWave;
+                n_tau = wave_base(a.ph.tau, b)[ul];
+                n_x = wave_base(X, b)[ul]; n_y = wave_base(Y, b)[ul]; n_z = wave_base(Z, b)[ul];
+                n_kx = wave_base(KX, b)[ul]; n_ky = wave_base(KY, b)[ul]; n_kz = wave_base(KZ, b)[ul];
+            }
+        };
+        // with a grid the loads go out after the gather's (whose wait would include them)
+        if constexpr (FK != FIELD_YEE) prefetch();
+        const int64_t tile0 = tile * kWave;                 // = i - lane
         // |k| = gamma_gamma, with one rounding order whatever the kernel variant
         const R kk = Math<R>::sqrt_(fma(kz, kz, fma(ky, ky, kx * kx)));
-        R E[3], B[3];
+        R E[3], B[3], xn = R(0), yn = R(0), zn = R(0);
         if constexpr (FK == FIELD_YEE) {
             // a wave whose photons all have a pair rate of exactly zero whatever the
             // field skips the gather: chi_gamma <= |k| (|E| + |B|) / E_s, bounded over
@@ -1077,8 +1105,9 @@ k_pair_create(PairArgs a) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) { E[d] = R(0); B[d] = R(0); }
                 if (live) cnt[C_NOGATHER]++;
+                prefetch();
             } else {
-                yee_gather_wave<R>(a.f, live, x, y, z, E, B, s_box + (tid / kWave) * kWBFloats);
+                yee_gather_wave<R>(a.f, live, x, y, z, E, B, s_box + (tid / kWave) * kWBFloats, prefetch);
             }
         }
         if (live) {
@@ -1097,13 +1126,21 @@ k_pair_create(PairArgs a) {
             if (Wp > R(0) && tau <= 0.0) {
                 event = true;
                 cnt[C_PAIR]++;
+                tau = -HUGE_VAL;
                 en[E_PAIR] = (double)((const R *)a.ph.w)[i] * (double)kk;
-                a.ph.tau[i] = -HUGE_VAL;
             } else {
-                X[i] = x + dtr * (kx * ik);
-                Y[i] = y + dtr * (ky * ik);
-                Z[i] = z + dtr * (kz * ik);
-                a.ph.tau[i] = tau;
+                xn = x + dtr * (kx * ik);
+                yn = y + dtr * (ky * ik);
+                zn = z + dtr * (kz * ik);
+            }
+        }
+        // the next tile's loads are waited for before this tile's stores, not after
+        // them (the memory counter retires in issue order)
+        __builtin_amdgcn_s_waitcnt(kWaitVmem);
+        if (live) {
+            wave_base(a.ph.tau, tile0)[ul] = tau;
+            if (!event) {
+                wave_base(X, tile0)[ul] = xn; wave_base(Y, tile0)[ul] = yn; wave_base(Z, tile0)[ul] = zn;
             }
         }
         const uint32_t tot = (uint32_t)__popcll(__ballot(event));
