@@ -248,17 +248,25 @@ def batched_comparison(steps: int, seed: int = 4):
                        bun.rec.a["uz"][idx].double() ** 2)
         return g.cpu().numpy()
 
-    def finish(bun, ms):
+    def finish(bun, ms, prec):
         rc, _ = bun.ws.status(raise_on_error=False)
         tal = bun.tally.reduce()
         ps = tal["N_mc"] + tal["N_sokolov"] + tal["N_nan"]
+        # algorithmic bytes, as for the lepton call of the Yee line: x, u read and written and w
+        # read per lepton-step; tau read and written per Monte Carlo step; id and event counter
+        # per emission; x, k, w, chi, tau, id, event counter per recorded photon
+        es = 4 if prec == B.QED_F32 else 8
+        byts = ps * 13 * es + tal["N_mc"] * 16 + tal["N_emit"] * 16 + tal["N_rec"] * (8 * es + 20)
+        gbs = byts / (ms * 1e-3) / 1e9
         return {"ms_per_step": ms / steps, "particle_steps_per_s": ps / (ms * 1e-3), "photons": bun.rec.n(),
-                "emissions": tal["N_emit"], "status": int(rc)}
+                "emissions": tal["N_emit"], "status": int(rc),
+                "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": gbs / HBM_PEAK_GBS, "bytes_per_step": byts / steps}}
 
     # FP64 plain
     plain = BT.Bunches(e, off, a0s, B.QED_F64, tabs, seed=seed, record_capacity=cap)
     ms = timed(lambda: [plain.step_plain(k) for k in range(steps)])
-    r_plain = finish(plain, ms)
+    r_plain = finish(plain, ms, B.QED_F64)
     g_plain = photon_gamma(plain)
     del plain
     torch.cuda.empty_cache()
@@ -270,7 +278,7 @@ def batched_comparison(steps: int, seed: int = 4):
         chunk = 10
         bun.capture(chunk)
         ms = timed(lambda: [bun.replay() for _ in range(steps // chunk)])
-        out = finish(bun, ms)
+        out = finish(bun, ms, prec)
         out["schedule"] = {"block": best.block, "blocks_per_cu": best.blocks_per_cu}
         out["graph_steps"] = chunk
         return bun, out
