@@ -282,6 +282,33 @@ __device__ __forceinline__ double wave_sum_f64_dpp(double v) {
     return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 
+// Sums over the wave of two doubles, a and b, through one DPP chain: the first
+// step adds lane pairs (l, l xor 1) so that even lanes hold pair sums of a and
+// odd lanes pair sums of b; every later step combines lanes of equal parity.
+// Each sum is formed in the order of wave_sum_f64_dpp (addition commutes), so
+// the results are those of two separate calls.  The wave must be fully active.
+__device__ __forceinline__ void wave_sum2_f64_dpp(double a, double b, double &sa, double &sb) {
+    auto mov = [](double x, auto ctrl) {
+        const uint64_t u = __builtin_bit_cast(uint64_t, x);
+        const int lo = __builtin_amdgcn_mov_dpp((int)u, decltype(ctrl)::value, 0xf, 0xf, false);
+        const int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), decltype(ctrl)::value, 0xf, 0xf, false);
+        return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+    };
+    const bool odd = (lane_id() & 1) != 0;
+    double v = (odd ? b : a) + mov(odd ? a : b, std::integral_constant<int, 0xb1>{});   // quad_perm 1,0,3,2
+    v += mov(v, std::integral_constant<int, 0x4e>{});                                   // quad_perm 2,3,0,1
+    v += mov(v, std::integral_constant<int, 0x124>{});                                  // row_ror 4
+    v += mov(v, std::integral_constant<int, 0x128>{});                                  // row_ror 8
+    auto lane_value = [](double x, int l) {
+        const uint64_t u = __builtin_bit_cast(uint64_t, x);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)u, l);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(u >> 32), l);
+        return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+    };
+    sa = (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+    sb = (lane_value(v, 1) + lane_value(v, 17)) + (lane_value(v, 33) + lane_value(v, 49));
+}
+
 __device__ __forceinline__ double wave_sum_f64(double v) {
 #pragma unroll
     for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);

@@ -339,14 +339,17 @@ __device__ __forceinline__ void status_need(unsigned long long *st, int which, i
 // on the schedule; with fewer slots, their order does.
 template <int NE>
 __device__ __forceinline__ void wave_energy(const TallyDev &tal, int64_t tile, double (&e)[NE]) {
+    static_assert(NE % 2 == 0, "energies are summed in pairs");
+    // a tally sized for the launch has a slot per tile: no division then
+    const int64_t sl = tile < tal.n_slots ? tile : tile % tal.n_slots;
 #pragma unroll
-    for (int k = 0; k < NE; ++k) {
-        if (__ballot(e[k] != 0.0) == 0ull) continue;
-        const double s = wave_sum_f64_dpp(e[k]);
-        if (lane_id() == 0 && s != 0.0) {
-            // a tally sized for the launch has a slot per tile: no division then
-            const int64_t sl = tile < tal.n_slots ? tile : tile % tal.n_slots;
-            unsafeAtomicAdd(tal.energy + sl * kNEnergy + k, s);
+    for (int k = 0; k < NE; k += 2) {
+        if (__ballot(e[k] != 0.0 || e[k + 1] != 0.0) == 0ull) continue;
+        double s0, s1;
+        wave_sum2_f64_dpp(e[k], e[k + 1], s0, s1);
+        if (lane_id() == 0) {
+            if (s0 != 0.0) unsafeAtomicAdd(tal.energy + sl * kNEnergy + k, s0);
+            if (s1 != 0.0) unsafeAtomicAdd(tal.energy + sl * kNEnergy + k + 1, s1);
         }
     }
 }
@@ -564,7 +567,7 @@ k_lepton_stream(PushArgs a) {
             unx = uLx; uny = uLy; unz = uLz;
             R dvx = R(0), dvy = R(0), dvz = R(0);
             int rad = a.st.rad;
-            if (!isfinite((double)chi) || !isfinite((double)gL)) { cnt[C_NAN]++; rad = RAD_NONE; status_flag(a.ws.status, 2ull); }
+            if (!__builtin_isfinite(chi) || !__builtin_isfinite(gL)) { cnt[C_NAN]++; rad = RAD_NONE; status_flag(a.ws.status, 2ull); }
 
             if (rad == RAD_SOKOLOV || (rad == RAD_HYBRID && (double)chi < a.st.chi_switch)) {
                 // Sokolov scheme (Eq. 4) with P_rad of Eq. 5
