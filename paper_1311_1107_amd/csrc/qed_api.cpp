@@ -253,7 +253,8 @@ qed_status qed_workspace_create(int64_t max_particles, int64_t max_leptons, qed_
     HIP_TRY(hipGetDevice(&w->device));
     HIP_TRY(hipDeviceGetAttribute(&w->n_cu, hipDeviceAttributeMultiprocessorCount, w->device));
     // smallest tile is 64 threads x 1 particle
-    w->max_tiles = (max_particles + 63) / 64 + 1;
+    // rounded up to 16 tiles so that every per-tile array starts 64-byte aligned (wide loads in the scans)
+    w->max_tiles = ((max_particles + 63) / 64 + 1 + 15) / 16 * 16;
     w->max_leptons = max_leptons;
     if (w->max_tiles > 0xffffffffll) { delete w; return fail(QED_ERR_ARG, "qed_workspace_create: too many tiles"); }
     const int64_t slots = ((max_leptons + 255) / 256 + 1) * 256;
@@ -623,7 +624,7 @@ qed_status qed_push_emit_batched(const qed_tables *tab, qed_workspace *ws, const
 namespace {
 
 constexpr int64_t kStaticMaxLeptons = 65536;                       // per call
-constexpr int64_t kStaticTiles = kStaticMaxLeptons / 64 + 1;      // tiles of 64 at the smallest block
+constexpr int64_t kStaticTiles = (kStaticMaxLeptons / 64 + 1 + 15) / 16 * 16;  // tiles of 64, rounded to 16
 constexpr int64_t kStaticSlots = ((kStaticMaxLeptons + 255) / 256 + 1) * 256;
 
 constexpr size_t align256(size_t b) { return (b + 255) / 256 * 256; }

@@ -690,6 +690,8 @@ k_lepton_events(PushArgs a) {
         if (have) {
             const ItemRec<R> r = items[a.ws.stage.item_map[d]];
             const int64_t i = r.idx;
+            uint32_t nev = a.lep.n_ev[i];
+            const uint64_t uid = a.lep.uid[i];
             const R *v = r.v;
             x = v[0]; y = v[1]; z = v[2];
             const R uLx = v[3], uLy = v[4], uLz = v[5];
@@ -700,8 +702,6 @@ k_lepton_events(PushArgs a) {
             R p = Math<R>::sqrt_(uLx * uLx + uLy * uLy + uLz * uLz);
             if (p > R(0)) { const R ip = Math<R>::rcp_(p); uhx = uLx * ip; uhy = uLy * ip; uhz = uLz * ip; }
             double t_left = dt;
-            uint32_t nev = a.lep.n_ev[i];
-            const uint64_t uid = a.lep.uid[i];
             int k = 0;
             for (;;) {
                 const double Wd = (double)W;
@@ -855,11 +855,32 @@ k_scan_tiles(ScanArgs a) {
         const int64_t b = st * per + (int64_t)tid * kScanItems;
         uint32_t v0[kScanItems], v1[kScanItems];
         uint32_t s0 = 0, s1 = 0;
+        const bool whole = b + kScanItems <= n_tiles;
+        if (whole) {
+            // a thread's 16 counts are 64 contiguous bytes (the per-tile arrays start 64-byte
+            // aligned): four 16-byte loads instead of sixteen strided ones
+            const uint4 *p0 = (const uint4 *)(a.ws.tile_cnt0 + b), *p1 = (const uint4 *)(a.ws.tile_cnt1 + b);
+#pragma unroll
+            for (int q = 0; q < kScanItems / 4; ++q) {
+                const uint4 c0 = p0[q];
+                v0[4 * q] = c0.x; v0[4 * q + 1] = c0.y; v0[4 * q + 2] = c0.z; v0[4 * q + 3] = c0.w;
+                if (a.mode != 2) {
+                    const uint4 c1 = p1[q];
+                    v1[4 * q] = c1.x; v1[4 * q + 1] = c1.y; v1[4 * q + 2] = c1.z; v1[4 * q + 3] = c1.w;
+                } else {
+                    v1[4 * q] = v1[4 * q + 1] = v1[4 * q + 2] = v1[4 * q + 3] = 0u;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kScanItems; ++j) {
+                const int64_t idx = b + j;
+                v0[j] = idx < n_tiles ? a.ws.tile_cnt0[idx] : 0u;
+                v1[j] = idx < n_tiles && a.mode != 2 ? a.ws.tile_cnt1[idx] : 0u;
+            }
+        }
 #pragma unroll
         for (int j = 0; j < kScanItems; ++j) {
-            const int64_t idx = b + j;
-            v0[j] = idx < n_tiles ? a.ws.tile_cnt0[idx] : 0u;
-            v1[j] = idx < n_tiles && a.mode != 2 ? a.ws.tile_cnt1[idx] : 0u;
             s0 += v0[j];
             s1 += v1[j];
         }
@@ -872,19 +893,30 @@ k_scan_tiles(ScanArgs a) {
         }
         __syncthreads();
         uint32_t r0 = s_pref[0] + e0, r1 = s_pref[1] + e1;
+        uint32_t q0[kScanItems], q1[kScanItems];
 #pragma unroll
         for (int j = 0; j < kScanItems; ++j) {
             const int64_t idx = b + j;
-            if (idx < n_tiles) {
-                a.ws.tile_pre0[idx] = r0;
-                a.ws.tile_pre1[idx] = r1;
-                // mode 2: item r0 + m of the list is the tile's m-th, at slot idx * tile_sz + m
-                if (a.mode == 2)
-                    for (uint32_t m = 0; m < v0[j]; ++m)
-                        a.ws.stage.item_map[r0 + m] = (uint32_t)(idx * a.tile_sz + m);
-            }
+            q0[j] = r0;
+            q1[j] = r1;
+            // mode 2: item r0 + m of the list is the tile's m-th, at slot idx * tile_sz + m
+            if (a.mode == 2 && idx < n_tiles)
+                for (uint32_t m = 0; m < v0[j]; ++m)
+                    a.ws.stage.item_map[r0 + m] = (uint32_t)(idx * a.tile_sz + m);
             r0 += v0[j];
             r1 += v1[j];
+        }
+        if (whole) {
+            uint4 *p0 = (uint4 *)(a.ws.tile_pre0 + b), *p1 = (uint4 *)(a.ws.tile_pre1 + b);
+#pragma unroll
+            for (int q = 0; q < kScanItems / 4; ++q) {
+                p0[q] = make_uint4(q0[4 * q], q0[4 * q + 1], q0[4 * q + 2], q0[4 * q + 3]);
+                p1[q] = make_uint4(q1[4 * q], q1[4 * q + 1], q1[4 * q + 2], q1[4 * q + 3]);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kScanItems; ++j)
+                if (b + j < n_tiles) { a.ws.tile_pre0[b + j] = q0[j]; a.ws.tile_pre1[b + j] = q1[j]; }
         }
         __syncthreads();
     }
