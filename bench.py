@@ -128,14 +128,16 @@ def oracle_threads() -> int:
     return int(v) if v.isdigit() and int(v) > 0 else len(os.sched_getaffinity(0))
 
 
-def cpu_baseline(wl, n_sample: int, start: int, steps: int, min_seconds: float):
+def cpu_baseline(wl, n_sample: int, start: int, steps: int, min_seconds: float, caps=(2, 1, 80, 20)):
     """The oracle on a fixed uid subset of the same workload.  The subset is
     advanced (untimed, on all host cores) to the first timed step; the timed
     window [start, start + steps) then runs single-threaded (the oracle as
     written) and on all host cores (its OpenMP driver: the same particles),
     each repeated from a copy of the start state until min_seconds have
     passed.  Leptons are independent in an external field with id-keyed
-    draws, so the subset evolves as it does inside the full run."""
+    draws, so the subset evolves as it does inside the full run.  caps: the
+    electron, positron, pushed- and recorded-photon buffers in units of the
+    subset's size."""
     import numpy as np
 
     from oracle import oracle as O
@@ -146,11 +148,11 @@ def cpu_baseline(wl, n_sample: int, start: int, steps: int, min_seconds: float):
     sub = W.subset(wl, idx)
     bt = O.BoundTables(O.compute_tables())
     m = len(idx)
-    el = O.species_from(sub.electrons, capacity=m * 2)
+    el = O.species_from(sub.electrons, capacity=m * caps[0])
     O.init_tau(el, wl.seed)
-    po = O.new_species(m)
-    ph = O.new_species(80 * m) if wl.push_photons else None
-    rec = O.new_species(20 * m) if wl.record_photons else None
+    po = O.new_species(m * caps[1])
+    ph = O.new_species(caps[2] * m) if wl.push_photons else None
+    rec = O.new_species(caps[3] * m) if wl.record_photons else None
     un = [n]
     f = wl.field
     threads = oracle_threads()
@@ -208,7 +210,61 @@ def cpu_baseline(wl, n_sample: int, start: int, steps: int, min_seconds: float):
                           "speedup_over_one_core": va / v1}}
 
 
-def batched_comparison(steps: int, seed: int = 4):
+def cpu_bunch_baseline(steps: int, seed: int = 4, every: int = 8, per_bunch: int = 2000, min_seconds: float = 1.0):
+    """The oracle on a fixed subset of the bunch workload: every `every`-th of
+    the 64 bunches, up to per_bunch electrons of each (evenly spaced ids), each
+    bunch in its own plane wave, steps [0, steps), photons recorded; one oracle
+    call per bunch per step (about 75 us of call overhead each, included);
+    single-threaded and on all host cores, repeated from the initial state
+    until min_seconds have passed."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_1311_1107_amd import workloads as W
+
+    e, off, a0s, _ = W.bunches(n_bunches=64, seed=seed)
+    n = len(e["x"])
+    bt = O.BoundTables(O.compute_tables())
+    threads = oracle_threads()
+    parts = []
+    for b in range(0, len(a0s), every):
+        idx = np.linspace(off[b], off[b + 1] - 1, min(per_bunch, int(off[b + 1] - off[b]))).astype(np.int64)
+        parts.append(({k: v[idx] for k, v in e.items()}, O.make_field(O.FIELD_PLANE_WAVE, a0=float(a0s[b]),
+                                                                       n_periods=10.0)))
+    m = sum(len(p[0]["x"]) for p in parts)
+
+    def window(th):
+        total_s, total_ps, reps = 0.0, 0, 0
+        while reps == 0 or total_s < min_seconds:
+            tally = O.Tally()
+            states = []
+            for el_d, _ in parts:
+                el = O.species_from(el_d, capacity=len(el_d["x"]))
+                O.init_tau(el, seed)
+                states.append((el, O.new_species(40 * len(el_d["x"]))))
+            un = [n]
+            t1 = time.perf_counter()
+            for k in range(steps):
+                st = O.make_step(k * W.DT, W.DT, seed)
+                for (el, rec), (_, field) in zip(states, parts):
+                    O.push_emit(bt, W.LAMBDA_M, -1.0, el, field, None, rec, st, un, tally, threads=th)
+            total_s += time.perf_counter() - t1
+            c = tally.as_dict()
+            total_ps += c["N_mc"] + c["N_sokolov"] + c["N_nan"]
+            reps += 1
+        return total_ps / total_s, total_ps // reps, reps, total_s
+
+    v1, ps1, r1, s1 = window(0)
+    va, psa, ra, sa = window(threads)
+    return {"value": v1, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{m} electrons (up to {per_bunch} evenly spaced ids of each of {len(parts)} of the "
+                      f"{len(a0s)} bunches, every {every}th, each in its own plane wave), steps [0, {steps}): "
+                      f"{ps1} particle-steps per pass, {r1} passes in {s1:.2f} s, single thread",
+            "all_cores": {"value": va, "unit": "particle-steps/s", "cores": threads, "kind": "oracle (OpenMP driver)",
+                          "sample": f"the same subset, {psa} particle-steps per pass, {ra} passes in {sa:.2f} s"}}
+
+
+def batched_comparison(steps: int, seed: int = 4, cpu: bool = True):
     """The batched-form bunches (64 bunches, sizes log-uniform 1e3..1e6,
     a0 ~ U(50, 500), gamma0 ~ U(500, 5000), plane waves): FP64 plain (one
     launch per bunch per step, eager) against FP32 batched (one persistent
@@ -307,6 +363,7 @@ def batched_comparison(steps: int, seed: int = 4):
         "ks_photon_gamma_same_seed_p": float(stats.ks_2samp(g_plain, g_b).pvalue),
         "ks_photon_gamma_seed_plus_1000_p": float(stats.ks_2samp(g_plain, g_c).pvalue),
         "ks_sample": len(g_plain),
+        "cpu_baseline": cpu_bunch_baseline(steps, seed) if cpu else None,
     }
 
 
@@ -501,6 +558,9 @@ def bench_cascade(args):
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
         "detail": {"growth": growth, "stopped_at_capacity": stopped, "kernel_ms": kms, "launches": nl,
                    "merges": run.merges, "status": int(rc), "tally": t},
+        # the oracle on 1000 of the electrons over the same steps (the subset's cascade grows
+        # about tenfold in leptons and photons; its buffers hold that without merging)
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(wl, 1000, 0, K, 1.0, caps=(12, 12, 40, 0)),
     }
 
 
@@ -544,7 +604,7 @@ def main():
         elif args.workload == "cascade":
             out = bench_cascade(args)
         else:
-            out = batched_comparison(args.steps or 1000)
+            out = batched_comparison(args.steps or 1000, cpu=not args.no_cpu_baseline)
         print(json.dumps(out), flush=True)
         return
     coupled = args.workload == "coupled"
@@ -670,7 +730,7 @@ def main():
     del run
     torch.cuda.empty_cache()
     if args.batched_steps > 0 and not coupled:
-        out["batched_vs_plain"] = batched_comparison(args.batched_steps)
+        out["batched_vs_plain"] = batched_comparison(args.batched_steps, cpu=not args.no_cpu_baseline)
     # measured copy bandwidth on this GPU (after the timed region), for the ratio to it
     copy_gbs = device_copy_gbs()
     out["roofline"]["copy_GBs"] = copy_gbs

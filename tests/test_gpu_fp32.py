@@ -270,6 +270,52 @@ def test_fp32_pair_spectrum_ks(gpu_oracle_tables, bound_tables):
         assert p > 0.01
 
 
+def test_fp32_reduced_cascade_ks(gpu_oracle_tables, bound_tables):
+    """The high-chi cascade (a0 = 1000 plane wave against gamma0 = 1e4
+    electrons, 500 steps, photons with chi_gamma < 0.2 not stored) reduced to
+    5000 electrons, in the FP32 form against the FP64 oracle: the gamma
+    spectra of the created pairs, of the surviving photons and of all
+    electrons pass a two-sample KS test, with the same seed and with seed +
+    1000; pair and emission counts agree within 3 %.  The oracle creates
+    about 3e4 pairs here."""
+    from scipy.stats import ks_2samp
+    n0 = 5000
+    wl = W.cascade_beam(n=n0, steps=500)
+    caps = dict(photon_capacity=200 * n0, pair_capacity=20 * n0)
+    want = oracle_run(wl, bound_tables, wl.steps, compact_every=1, **caps)
+    wt = want["tally"]
+    assert wt["N_pair"] > 10_000 and wt["N_overflow"] == 0
+
+    def gammas(sp, mask=None):
+        u = [np.asarray(sp[k], np.float64) for k in ("ux", "uy", "uz")]
+        if mask is not None:
+            u = [c[mask] for c in u]
+        return np.sqrt(1.0 + u[0] ** 2 + u[1] ** 2 + u[2] ** 2)
+
+    def spectra(r):
+        e, po, ph = r["electrons"], r["positrons"], r["photons"]
+        created = np.asarray(e["uid"]) >= n0
+        pair = np.concatenate([gammas(e, created), gammas(po)])
+        k = [np.asarray(ph[c], np.float64) for c in ("ux", "uy", "uz")]
+        return {"pairs": pair, "photons": np.sqrt(k[0] ** 2 + k[1] ** 2 + k[2] ** 2), "electrons": gammas(e)}
+
+    sw = spectra(want)
+    for seed in (wl.seed, wl.seed + 1000):
+        wl_s = W.cascade_beam(n=n0, steps=500, seed=wl.seed)
+        wl_s.seed = seed
+        run = S.Run(wl_s, prec=B.QED_F32, tables=gpu_oracle_tables, compact_every=1, **caps)
+        run.run(wl.steps)
+        run.ws.status()
+        t = run.tally.reduce()
+        sg = spectra(run.result())
+        dn = {k: t[k] / wt[k] - 1.0 for k in ("N_pair", "N_emit")}
+        ps = {k: ks_2samp(sg[k], sw[k]).pvalue for k in sw}
+        print(f"FP32 reduced cascade seed {seed}: " + ", ".join(f"{k} {v:+.2%}" for k, v in dn.items()) + "; KS "
+              + ", ".join(f"{k} p = {v:.3g} ({len(sg[k])} vs {len(sw[k])})" for k, v in ps.items()), flush=True)
+        assert all(abs(v) < 0.03 for v in dn.values()), dn
+        assert all(v > 0.01 for v in ps.values()), ps
+
+
 def test_fp32_radiation_off_momentum_error(gpu_oracle_tables, bound_tables):
     """With radiation off (Lorentz force only) the FP32 form is deterministic:
     its momentum error against the FP64 oracle over a 700-step run through the
