@@ -335,7 +335,7 @@ def batched_comparison(steps: int, seed: int = 4, cpu: bool = True):
         bun.capture(chunk)
         ms = timed(lambda: [bun.replay() for _ in range(steps // chunk)])
         out = finish(bun, ms, prec)
-        out["schedule"] = {"block": best.block, "blocks_per_cu": best.blocks_per_cu}
+        out["schedule"] = {"block": best.block, "blocks_per_cu": best.blocks_per_cu, "max_blocks": best.max_blocks}
         out["graph_steps"] = chunk
         return bun, out
 

@@ -382,7 +382,8 @@ qed_status qed_push_emit_batched(const qed_tables *tab, qed_workspace *ws, const
  * particles, counters and tallies are left as they were) and returns the
  * fastest in *best.  candidates [host] has n_candidates entries; if cache_path
  * is not NULL, a result stored there for the same problem is reused and a new
- * one is written. */
+ * one is written (one text line per problem: its key, then block,
+ * items_per_thread, blocks_per_cu, max_blocks and the time per step). */
 qed_status qed_autotune_batched(const qed_tables *tab, qed_workspace *ws, const qed_units *u,
                                 double charge, qed_species *lep, const qed_bunches *b,
                                 qed_species *ph_rec, const qed_step *st,

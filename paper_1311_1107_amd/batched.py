@@ -22,8 +22,10 @@ from . import binding as B
 from . import device as D
 from .workloads import DT, LAMBDA_M
 
-# schedules the autotuner chooses from: block size and workgroups per CU
-CANDIDATES = [(64, 8), (128, 8), (256, 8), (256, 4), (256, 2), (128, 16), (64, 16)]
+# schedules the autotuner chooses from: block size, workgroups per CU and a cap
+# on the persistent grid (0 = none; a cap makes each block walk more tiles)
+CANDIDATES = [(64, 8, 0), (128, 8, 0), (256, 8, 0), (256, 4, 0), (256, 2, 0), (128, 16, 0), (64, 16, 0),
+              (256, 16, 0), (256, 8, 1024), (256, 8, 512), (128, 8, 1024)]
 
 
 class Bunches:
@@ -82,7 +84,7 @@ class Bunches:
         scratch copy of the state at trial_time, by default one pulse length
         (2 pi n_periods): the pulse then covers about half of each bunch's
         box, so the trial steps emit as the run does in the pulse."""
-        cands = [D.schedule(b, 1, bpc) for b, bpc in CANDIDATES]
+        cands = [D.schedule(b, 1, bpc, cap) for b, bpc, cap in CANDIDATES]
         t = trial_time if trial_time is not None else 2.0 * np.pi * self.n_periods
         st = D.step(t, DT, self.seed, rad_model=self.rad_model)
         best, ms = B.qed_autotune_batched(self.tables.h, self.ws.h, self.units, -1.0, self.el.struct(), self.bun,

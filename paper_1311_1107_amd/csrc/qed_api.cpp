@@ -1073,8 +1073,9 @@ qed_status qed_autotune_batched(const qed_tables *tab, qed_workspace *ws, const 
                 qed_schedule c{};
                 double ms = 0;
                 char k2[256];
-                if (std::sscanf(line, "%255[^|]| %d %d %d %lf", k2, &c.block, &c.items_per_thread, &c.blocks_per_cu, &ms) == 5 &&
-                    std::strncmp(k2, key, std::strlen(key)) == 0) {
+                if (std::sscanf(line, "%255[^|]| %d %d %d %d %lf", k2, &c.block, &c.items_per_thread, &c.blocks_per_cu,
+                                &c.max_blocks, &ms) == 6 &&
+                    std::strcmp(k2, key) == 0) {
                     std::fclose(fp);
                     *best = c;
                     if (best_ms) *best_ms = ms;
@@ -1178,8 +1179,8 @@ qed_status qed_autotune_batched(const qed_tables *tab, qed_workspace *ws, const 
     if (best_ms) *best_ms = best_t / trial_steps;
     if (cache_path) {
         if (FILE *fp = std::fopen(cache_path, "a")) {
-            std::fprintf(fp, "%s| %d %d %d %.6f\n", key, best->block, best->items_per_thread, best->blocks_per_cu,
-                         best_t / trial_steps);
+            std::fprintf(fp, "%s| %d %d %d %d %.6f\n", key, best->block, best->items_per_thread, best->blocks_per_cu,
+                         best->max_blocks, best_t / trial_steps);
             std::fclose(fp);
         }
     }

@@ -484,10 +484,11 @@ def test_autotune_leaves_state_and_caches(gpu_oracle_tables, tmp_path):
     before = _snapshot(bun)
     cache = str(tmp_path / "tune.txt")
     best, ms = bun.autotune(trial_steps=2, cache_path=cache)
-    assert (best.block, best.blocks_per_cu) in BT.CANDIDATES and ms > 0
+    assert (best.block, best.blocks_per_cu, best.max_blocks) in BT.CANDIDATES and ms > 0
     _same(_snapshot(bun), before)                                  # trials run on scratch state
     best2, ms2 = bun.autotune(trial_steps=2, cache_path=cache)     # read back from the cache
-    assert (best2.block, best2.blocks_per_cu) == (best.block, best.blocks_per_cu) and ms2 == pytest.approx(ms, rel=1e-3)
+    assert (best2.block, best2.blocks_per_cu, best2.max_blocks) == (best.block, best.blocks_per_cu, best.max_blocks)
+    assert ms2 == pytest.approx(ms, rel=1e-3)
     # the tuned schedule gives the same result as the default one
     ref = _small_bunches(B.QED_F32, gpu_oracle_tables)
     for _ in range(4):
