@@ -378,12 +378,21 @@ __device__ __forceinline__ void block_counts(const TallyDev &tal, int (&c)[N_COU
 // run of particles.  Tiles are independent here: appends are placed later by
 // the scan and append passes, so no tile waits for another.
 // ------------------------------------------------------------------------
-__device__ __forceinline__ int64_t xcd_tile(int64_t it, int64_t n_tiles) {
+__device__ __forceinline__ int64_t xcd_tile(int64_t it, int64_t n_tiles, bool rev = false) {
     const int64_t g8 = gridDim.x >> 3;             // the grid is a multiple of 8
     const int64_t x = blockIdx.x & 7, l = blockIdx.x >> 3;
     const int64_t lo = n_tiles * x / 8, hi = n_tiles * (x + 1) / 8;
-    const int64_t t = lo + l + it * g8;
-    return t < hi ? t : -1;
+    const int64_t k = l + it * g8;
+    return lo + k < hi ? (rev ? hi - 1 - k : lo + k) : -1;
+}
+
+// Successive steps walk the tiles in opposite directions, so that a step
+// starts on the lines that the previous one wrote last (those are still in
+// the memory-side cache).  The direction follows the parity of the step
+// number t / dt; results do not depend on it.
+__device__ __forceinline__ bool walk_reverse(double t, double dt) {
+    const int odd = dt > 0.0 && (llrint(t / dt) & 1) != 0;
+    return __builtin_amdgcn_readfirstlane(odd) != 0;
 }
 
 // s_waitcnt vmcnt(0), leaving the other counters free (expcnt 7, lgkmcnt 15)
@@ -479,6 +488,7 @@ k_lepton_stream(PushArgs a) {
     const double t = a.st.d_step ? a.st.t + (double)(*a.st.d_step) * a.st.dt : a.st.t;
     const double dt = a.st.dt;
     const R dtr = (R)dt;
+    const bool rev = walk_reverse(t, dt);
     const int64_t n_chunks = (n + blockDim.x - 1) / blockDim.x;
     const int64_t n_tiles = (n + kWave - 1) / kWave;
     const R q = (R)a.c.q, hq = R(0.5) * q * dtr;
@@ -495,7 +505,7 @@ k_lepton_stream(PushArgs a) {
 
     // the state of a wave's next tile is loaded before the current one is
     // stepped, which hides the HBM latency behind the arithmetic
-    int64_t chunk = xcd_tile(0, n_chunks);
+    int64_t chunk = xcd_tile(0, n_chunks, rev);
     R n_x = R(0), n_y = R(0), n_z = R(0), n_ux = R(0), n_uy = R(0), n_uz = R(0), n_w = R(0);
     double n_tau = 0.0;
     const uint32_t ul = (uint32_t)lane;
@@ -511,7 +521,7 @@ k_lepton_stream(PushArgs a) {
         const bool live = i < n;
         const R x = n_x, y = n_y, z = n_z, ux = n_ux, uy = n_uy, uz = n_uz, wgt_i = n_w;
         const double tau_i = n_tau;
-        const int64_t next = xcd_tile(it + 1, n_chunks);
+        const int64_t next = xcd_tile(it + 1, n_chunks, rev);
         auto prefetch = [&]() {
             if (next >= 0 && next * blockDim.x + tid < n) {
                 const int64_t b = (next * nw + wid) * kWave;
@@ -678,7 +688,11 @@ k_lepton_events(PushArgs a) {
     __syncthreads();
 
     const int64_t waves = (int64_t)gridDim.x * nw;
-    for (int64_t c = (int64_t)blockIdx.x * nw + wid; c < n_chunks; c += waves) {
+    // the streaming pass wrote the far end of its walk last: start there
+    const double t_ev = a.st.d_step ? a.st.t + (double)(*a.st.d_step) * a.st.dt : a.st.t;
+    const bool fwd = walk_reverse(t_ev, a.st.dt);
+    for (int64_t w = (int64_t)blockIdx.x * nw + wid; w < n_chunks; w += waves) {
+        const int64_t c = fwd ? w : n_chunks - 1 - w;
         const int64_t d = c * kWave + lane;
         const bool have = d < n_items;
         double en[kNEnergy];
