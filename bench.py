@@ -200,7 +200,8 @@ def cpu_baseline(wl, n_sample: int, start: int, steps: int, min_seconds: float, 
     va, psa, ra, sa = window(threads)
     cpu = host_cpu()
     return {"value": v1, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{m} electrons (uid subset) of the same workload, advanced to step {start} "
+            "sample": (f"all {m} electrons of the workload" if m == n else
+                       f"{m} electrons (uid subset) of the same workload") + f", advanced to step {start} "
                       f"({live0['electrons']} e-, {live0['positrons']} e+, {live0['photons']} pushed photons there, "
                       f"{advance_s:.1f} s on {threads} threads, untimed), then steps [{start}, {start + steps}): "
                       f"{ps1} particle-steps per pass, {r1} passes in {s1:.2f} s, single thread",
@@ -466,6 +467,10 @@ def bench_plane(args):
                       "photons_f64": f64["photons"], "photons_f32": f32["photons"],
                       "energy_balance_f64": f64["energy_balance"], "energy_balance_f32": f32["energy_balance"]},
         "detail": {k: {kk: vv for kk, vv in v.items() if kk != "gamma"} for k, v in res.items()},
+        # the oracle on the whole workload (every electron, every step), one thread and all cores
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(
+            W.plane_wave_beam(n=args.electrons or 100_000), args.electrons or 100_000, 0,
+            min(args.steps or 1000, 1000), 1.0, caps=(1, 1, 0, 40)),
     }
     return out
 
