@@ -38,7 +38,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--start", type=int, default=1000,
                    help="first timed step (Yee workloads): the run is advanced untimed to start - warmup")
-    p.add_argument("--workload", default="yee", choices=["yee", "coupled", "plane", "batched", "cascade"])
+    p.add_argument("--workload", default="yee", choices=["yee", "coupled", "plane", "batched", "batched-fp32",
+                                                          "cascade"])
     p.add_argument("--electrons", type=int, default=None, help="override the electron count")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=1500, help="electrons in the oracle sample")
@@ -57,6 +58,8 @@ def parse():
                         "pair skip the gather; 0 = off")
     p.add_argument("--batched-steps", type=int, default=1000,
                    help="steps of the FP32-batched vs FP64-plain comparison (0 skips it)")
+    p.add_argument("--no-graph", action="store_true",
+                   help="batched forms: eager launches instead of HIP-graph replays (for counter collection)")
     return p.parse_args()
 
 
@@ -265,7 +268,7 @@ def cpu_bunch_baseline(steps: int, seed: int = 4, every: int = 8, per_bunch: int
                           "sample": f"the same subset, {psa} particle-steps per pass, {ra} passes in {sa:.2f} s"}}
 
 
-def batched_comparison(steps: int, seed: int = 4, cpu: bool = True):
+def batched_comparison(steps: int, seed: int = 4, cpu: bool = True, graph: bool = True, only_fp32: bool = False):
     """The batched-form bunches (64 bunches, sizes log-uniform 1e3..1e6,
     a0 ~ U(50, 500), gamma0 ~ U(500, 5000), plane waves): FP64 plain (one
     launch per bunch per step, eager) against FP32 batched (one persistent
@@ -320,6 +323,25 @@ def batched_comparison(steps: int, seed: int = 4, cpu: bool = True):
                 "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": gbs / HBM_PEAK_GBS, "bytes_per_step": byts / steps}}
 
+    def batched(sd, prec=B.QED_F32):
+        bun = BT.Bunches(e, off, a0s, prec, tabs, seed=sd, record_capacity=cap)
+        best, _ = bun.autotune(trial_steps=3)
+        chunk = 10
+        if graph:
+            bun.capture(chunk)
+            ms = timed(lambda: [bun.replay() for _ in range(steps // chunk)])
+        else:
+            ms = timed(lambda: [bun.step_batched() for _ in range(steps // chunk * chunk)])
+        out = finish(bun, ms, prec)
+        out["schedule"] = {"block": best.block, "blocks_per_cu": best.blocks_per_cu, "max_blocks": best.max_blocks}
+        out["graph_steps"] = chunk if graph else 0
+        return bun, out
+
+    if only_fp32:
+        # the FP32 batched form alone (counter collection on its kernels)
+        bun, r_b = batched(seed)
+        return {"workload": f"{len(a0s)} bunches, {n} e-, {steps} steps, FP32 batched form only",
+                "fp32_batched_graph" if graph else "fp32_batched_eager": r_b}
     # FP64 plain
     plain = BT.Bunches(e, off, a0s, B.QED_F64, tabs, seed=seed, record_capacity=cap)
     ms = timed(lambda: [plain.step_plain(k) for k in range(steps)])
@@ -328,17 +350,6 @@ def batched_comparison(steps: int, seed: int = 4, cpu: bool = True):
     del plain
     torch.cuda.empty_cache()
     print("bench: FP64 plain bunches done", file=sys.stderr, flush=True)
-
-    def batched(sd, prec=B.QED_F32):
-        bun = BT.Bunches(e, off, a0s, prec, tabs, seed=sd, record_capacity=cap)
-        best, _ = bun.autotune(trial_steps=3)
-        chunk = 10
-        bun.capture(chunk)
-        ms = timed(lambda: [bun.replay() for _ in range(steps // chunk)])
-        out = finish(bun, ms, prec)
-        out["schedule"] = {"block": best.block, "blocks_per_cu": best.blocks_per_cu, "max_blocks": best.max_blocks}
-        out["graph_steps"] = chunk
-        return bun, out
 
     bun, r_b = batched(seed)
     g_b = photon_gamma(bun)
@@ -603,13 +614,14 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    if args.workload in ("plane", "cascade", "batched"):
+    if args.workload in ("plane", "cascade", "batched", "batched-fp32"):
         if args.workload == "plane":
             out = bench_plane(args)
         elif args.workload == "cascade":
             out = bench_cascade(args)
         else:
-            out = batched_comparison(args.steps or 1000, cpu=not args.no_cpu_baseline)
+            out = batched_comparison(args.steps or 1000, cpu=not args.no_cpu_baseline, graph=not args.no_graph,
+                                     only_fp32=args.workload == "batched-fp32")
         print(json.dumps(out), flush=True)
         return
     coupled = args.workload == "coupled"
@@ -735,7 +747,8 @@ def main():
     del run
     torch.cuda.empty_cache()
     if args.batched_steps > 0 and not coupled:
-        out["batched_vs_plain"] = batched_comparison(args.batched_steps, cpu=not args.no_cpu_baseline)
+        out["batched_vs_plain"] = batched_comparison(args.batched_steps, cpu=not args.no_cpu_baseline,
+                                                     graph=not args.no_graph)
     # measured copy bandwidth on this GPU (after the timed region), for the ratio to it
     copy_gbs = device_copy_gbs()
     out["roofline"]["copy_GBs"] = copy_gbs
