@@ -716,7 +716,12 @@ def main():
     default_cfg = (n0 == 10_000_000 and start == 1000 and K == 20 and W_ == 5 and args.sort_every == 16
                    and run.photon_sort_every == 16 and args.compact_every == 16 and not coupled
                    and args.bound_block == 0)
-    tr = measured_traffic(dom) if default_cfg else None
+    for key, pc in per_call.items():
+        t_ = measured_traffic(key) if default_cfg else None
+        pc["traffic"] = t_
+        if t_:
+            pc["traffic_ratio"] = t_ / pc["bytes_per_launch"]
+    tr = per_call[dom]["traffic"]
     roof["traffic"] = tr
     if tr:
         roof["traffic_ratio"] = tr / roof["bytes_per_launch"]
