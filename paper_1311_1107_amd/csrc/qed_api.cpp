@@ -817,7 +817,7 @@ qed_status qed_sorter_create(int64_t max_particles, qed_sorter **out) {
         return fail(QED_ERR_ARG, "qed_sorter_create: max_particles must be in [1, 2^32-1)");
     qed_sorter *s = new qed_sorter();
     s->max_particles = max_particles;
-    s->hist_len = 16 * ((max_particles + 4095) / 4096 + 1);
+    s->hist_len = qed::radix_hist_len(max_particles);
     if (hipMalloc(&s->keys, sizeof(uint32_t) * 4 * max_particles) != hipSuccess ||
         hipMalloc(&s->hist, sizeof(uint32_t) * 2 * s->hist_len) != hipSuccess ||
         hipMalloc(&s->live, 64) != hipSuccess) {
@@ -870,7 +870,6 @@ qed_status qed_sort_by_cell_bands(qed_sorter *so, qed_workspace *ws, qed_species
     a.key_out = (uint32_t)ncell;
     a.key_dead = (uint32_t)(((uint64_t)1 << bits) - 1);
     a.bands = bands;
-    const int passes = (bits + 3) / 4;
     a.x0 = grid->x0; a.y0 = grid->y0; a.z0 = grid->z0;
     a.inv_dx = 1.0 / grid->dx; a.inv_dy = 1.0 / grid->dy; a.inv_dz = 1.0 / grid->dz;
     a.nx = grid->nx; a.ny = grid->ny; a.nz = grid->nz;
@@ -879,7 +878,7 @@ qed_status qed_sort_by_cell_bands(qed_sorter *so, qed_workspace *ws, qed_species
     a.hist = so->hist; a.hoff = so->hist + so->hist_len;
     a.live = so->live;
     a.ws = ws->dev;
-    HIP_TRY(qed::launch_sort(a, src->prec, passes, ws->n_cu, src->capacity, (hipStream_t)stream));
+    HIP_TRY(qed::launch_sort(a, src->prec, bits, ws->n_cu, src->capacity, (hipStream_t)stream));
     return QED_OK;
 }
 

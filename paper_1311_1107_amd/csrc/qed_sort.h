@@ -29,6 +29,12 @@ struct RadixBufs {
 int launch_radix_passes(const RadixBufs &b, int cur, const int64_t *count, int64_t cap, int first_pass, int passes,
                         int n_cu, WsDev ws, hipStream_t s);
 
+// The same with 8-bit digits (digit p at bit 8p), tiles of 2048 keys; hist and
+// hoff hold radix_hist_len(cap) entries each.
+int launch_radix_passes8(const RadixBufs &b, int cur, const int64_t *count, int64_t cap, int passes, int n_cu,
+                         WsDev ws, hipStream_t s);
+int64_t radix_hist_len(int64_t cap);
+
 // exclusive scan of the first *count (clamped to cap) entries of in
 void launch_scan_u32(const uint32_t *in, uint32_t *out, const int64_t *count, int64_t cap, int n_cu, WsDev ws,
                      hipStream_t s);
@@ -51,6 +57,7 @@ struct MergeArgs {
 
 hipError_t launch_merge(MergeArgs a, int prec, int mbin_passes, int cell_passes, int n_cu, hipStream_t s);
 
-hipError_t launch_sort(const SortArgs &a, int prec, int passes, int n_cu, int64_t capacity, hipStream_t s);
+// cell sort of keys of `bits` bits (8-bit radix passes)
+hipError_t launch_sort(const SortArgs &a, int prec, int bits, int n_cu, int64_t capacity, hipStream_t s);
 
 }  // namespace qed

@@ -246,6 +246,132 @@ k_radix_scatter(const uint32_t *kin, const uint32_t *iin, uint32_t *kout, uint32
     }
 }
 
+// ------------------------------------------------------------------------
+// 8-bit digits: half the passes of the 4-bit form (three for keys of up to
+// 24 bits).  Tiles of 2048 keys, eight rounds of 256.  Within a round each
+// wave finds the lanes that share a lane's digit with nine ballots (the
+// digit's bits and a bit for keys past the end), so a lane's rank among its
+// wave's equal digits is a popcount and each distinct digit takes one LDS
+// update per wave, however the digits repeat (cell-ordered keys repeat a
+// lot).  Ranks are taken in key order (round, wave, lane), so the pass is
+// stable.
+// ------------------------------------------------------------------------
+constexpr int kTile8 = 2048;
+constexpr int kRounds8 = kTile8 / kSortThreads;      // 8
+constexpr int kDigits8 = 256;
+
+// lanes of the wave whose 9-bit digit d equals this lane's (every lane active)
+__device__ __forceinline__ uint64_t match_digit9(uint32_t d) {
+    uint64_t m = ~0ull;
+#pragma unroll
+    for (int b = 0; b < 9; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
+        m &= bit ? bal : ~bal;
+    }
+    return m;
+}
+
+// per-tile histograms of one 8-bit digit, digit-major: hist[d * n_tiles + tile]
+__global__ void __launch_bounds__(256)
+k_radix_count8(const uint32_t *keys, const int64_t *count, int64_t cap, int shift, uint32_t *hist) {
+    __shared__ uint32_t s_h[kDigits8];
+    const int tid = threadIdx.x, lane = lane_id();
+    const int64_t n = sort_count(count, cap);
+    const int64_t n_tiles = (n + kTile8 - 1) / kTile8;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        s_h[tid] = 0u;                                    // one digit per thread
+        __syncthreads();
+        const int64_t b = tile * kTile8;
+#pragma unroll
+        for (int j = 0; j < kRounds8; ++j) {
+            const int64_t i = b + j * kSortThreads + tid;
+            const uint32_t d = i < n ? (keys[i] >> shift) & (kDigits8 - 1) : (uint32_t)kDigits8;
+            const uint64_t m = match_digit9(d);
+            if (d < (uint32_t)kDigits8 && lane == __ffsll((long long)m) - 1) atomicAdd(&s_h[d], (uint32_t)__popcll(m));
+        }
+        __syncthreads();
+        hist[(int64_t)tid * n_tiles + tile] = s_h[tid];
+        __syncthreads();
+    }
+}
+
+// stable scatter of one 8-bit digit through LDS (coalesced loads and stores)
+__global__ void __launch_bounds__(256)
+k_radix_scatter8(const uint32_t *kin, const uint32_t *iin, uint32_t *kout, uint32_t *iout, const int64_t *count,
+                 int64_t cap, int shift, const uint32_t *hoff) {
+    __shared__ __align__(16) uint8_t s_cnt[kRounds8 * kMaxWaves * kDigits8];   // per (round, wave, digit) counts
+    __shared__ uint16_t s_off[kRounds8 * kMaxWaves * kDigits8];    // their offsets within the digit's run
+    __shared__ uint32_t s_k[kTile8], s_v[kTile8];
+    __shared__ uint32_t s_start[kDigits8], s_go[kDigits8];
+    __shared__ uint32_t s_wave[2 * kMaxWaves];
+    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int64_t n = sort_count(count, cap);
+    const int64_t n_tiles = (n + kTile8 - 1) / kTile8;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t base = tile * kTile8;
+        const int nv = (int)(n - base < (int64_t)kTile8 ? n - base : (int64_t)kTile8);
+        // zero the counts: 8 KB, 32 bytes per thread
+        {
+            uint4 *c4 = (uint4 *)s_cnt;
+            c4[2 * tid] = make_uint4(0u, 0u, 0u, 0u);
+            c4[2 * tid + 1] = make_uint4(0u, 0u, 0u, 0u);
+        }
+        uint32_t k[kRounds8], v[kRounds8], rk[kRounds8];
+#pragma unroll
+        for (int j = 0; j < kRounds8; ++j) {
+            const int p = j * kSortThreads + tid;
+            k[j] = p < nv ? kin[base + p] : 0u;
+            v[j] = p < nv ? iin[base + p] : 0u;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kRounds8; ++j) {
+            const int p = j * kSortThreads + tid;
+            const uint32_t d = p < nv ? (k[j] >> shift) & (kDigits8 - 1) : (uint32_t)kDigits8;
+            const uint64_t m = match_digit9(d);
+            rk[j] = (uint32_t)__popcll(m & below);
+            if (d < (uint32_t)kDigits8 && rk[j] == 0u) s_cnt[(j * kMaxWaves + wid) * kDigits8 + d] = (uint8_t)__popcll(m);
+        }
+        __syncthreads();
+        // thread d: offsets of its digit's (round, wave) groups in key order, and the digit's count
+        uint32_t run = 0;
+#pragma unroll
+        for (int g = 0; g < kRounds8 * kMaxWaves; ++g) {
+            s_off[g * kDigits8 + tid] = (uint16_t)run;
+            run += s_cnt[g * kDigits8 + tid];
+        }
+        uint32_t e, e1, tot, tot1;
+        block_scan2(run, 0u, e, e1, tot, tot1, s_wave);
+        s_start[tid] = e;
+        s_go[tid] = hoff[(int64_t)tid * n_tiles + tile] - e;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kRounds8; ++j) {
+            const int p = j * kSortThreads + tid;
+            if (p < nv) {
+                const uint32_t d = (k[j] >> shift) & (kDigits8 - 1);
+                const uint32_t pos = s_start[d] + s_off[(j * kMaxWaves + wid) * kDigits8 + d] + rk[j];
+                s_k[pos] = k[j];
+                s_v[pos] = v[j];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kRounds8; ++j) {
+            const int p = j * kSortThreads + tid;
+            if (p < nv) {
+                const uint32_t key = s_k[p];
+                const uint32_t g = s_go[(key >> shift) & (kDigits8 - 1)] + (uint32_t)p;
+                kout[g] = key;
+                iout[g] = s_v[p];
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // gather the live particles into the destination, in sorted order; each
 // thread keeps four gathers in flight
 template <typename R>
@@ -298,19 +424,39 @@ int launch_radix_passes(const RadixBufs &b, int cur, const int64_t *count, int64
     return cur;
 }
 
+int launch_radix_passes8(const RadixBufs &b, int cur, const int64_t *count, int64_t cap, int passes, int n_cu,
+                         WsDev ws, hipStream_t s) {
+    const int64_t tiles = (cap + kTile8 - 1) / kTile8;
+    const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)n_cu * 8));
+    const unsigned gs = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tiles * kDigits8 + kSortTile - 1) / kSortTile, n_cu));
+    for (int p = 0; p < passes; ++p, cur ^= 1) {
+        const int shift = 8 * p;
+        hipLaunchKernelGGL(k_radix_count8, dim3(gb), dim3(256), 0, s, b.key[cur], count, cap, shift, b.hist);
+        hipLaunchKernelGGL(k_scan_u32, dim3(gs), dim3(256), 0, s, b.hist, b.hoff, count, cap, (int64_t)kTile8,
+                           (int64_t)kDigits8, ws);
+        hipLaunchKernelGGL(k_radix_scatter8, dim3(gb), dim3(256), 0, s, b.key[cur], b.idx[cur], b.key[cur ^ 1],
+                           b.idx[cur ^ 1], count, cap, shift, b.hoff);
+    }
+    return cur;
+}
+
+int64_t radix_hist_len(int64_t cap) {
+    return std::max<int64_t>(16 * ((cap + kSortTile - 1) / kSortTile + 1), (int64_t)kDigits8 * ((cap + kTile8 - 1) / kTile8 + 1));
+}
+
 void launch_scan_u32(const uint32_t *in, uint32_t *out, const int64_t *count, int64_t cap, int n_cu, WsDev ws,
                      hipStream_t s) {
     const unsigned gs = (unsigned)std::max<int64_t>(1, std::min<int64_t>((cap + kSortTile - 1) / kSortTile, (int64_t)n_cu));
     hipLaunchKernelGGL(k_scan_u32, dim3(gs), dim3(256), 0, s, in, out, count, cap, (int64_t)1, (int64_t)1, ws);
 }
 
-hipError_t launch_sort(const SortArgs &a, int prec, int passes, int n_cu, int64_t capacity, hipStream_t s) {
+hipError_t launch_sort(const SortArgs &a, int prec, int bits, int n_cu, int64_t capacity, hipStream_t s) {
     const unsigned ge = (unsigned)std::max<int64_t>(1, std::min<int64_t>((capacity + 255) / 256, (int64_t)n_cu * 16));
     hipLaunchKernelGGL(k_sort_zero, dim3(1), dim3(64), 0, s, a.live);
     if (prec == 0) hipLaunchKernelGGL((k_sort_keys<double>), dim3(ge), dim3(256), 0, s, a);
     else hipLaunchKernelGGL((k_sort_keys<float>), dim3(ge), dim3(256), 0, s, a);
     RadixBufs b = {{a.key0, a.key1}, {a.idx0, a.idx1}, a.hist, a.hoff};
-    const int fin = launch_radix_passes(b, 0, a.src.count, a.src.cap, 0, passes, n_cu, a.ws, s);
+    const int fin = launch_radix_passes8(b, 0, a.src.count, a.src.cap, (bits + 7) / 8, n_cu, a.ws, s);
     SortArgs c = a;
     c.idx_final = b.idx[fin];
     if (prec == 0) hipLaunchKernelGGL((k_sort_permute<double>), dim3(ge), dim3(256), 0, s, c);
