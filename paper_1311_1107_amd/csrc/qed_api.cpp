@@ -890,7 +890,7 @@ qed_status qed_merger_create(int64_t max_particles, qed_merger **out) {
         return fail(QED_ERR_ARG, "qed_merger_create: max_particles must be in [1, 2^32-1)");
     qed_merger *m = new qed_merger();
     m->max_particles = max_particles;
-    m->hist_len = 16 * ((max_particles + 4095) / 4096 + 1);
+    m->hist_len = qed::radix_hist_len(max_particles);
     if (hipMalloc(&m->buf, sizeof(uint32_t) * (7 * max_particles + 2)) != hipSuccess ||
         hipMalloc(&m->hist, sizeof(uint32_t) * 2 * m->hist_len) != hipSuccess ||
         hipMalloc(&m->cnt, 64) != hipSuccess) {
@@ -961,7 +961,7 @@ qed_status qed_merge(qed_merger *mg, qed_workspace *ws, const qed_merge_spec *sp
     a.hist = mg->hist; a.hoff = mg->hist + mg->hist_len;
     a.cnt = mg->cnt;
     a.ws = ws->dev;
-    HIP_TRY(qed::launch_merge(a, src->prec, (mbits + 3) / 4, (cbits + 3) / 4, ws->n_cu, (hipStream_t)stream));
+    HIP_TRY(qed::launch_merge(a, src->prec, (mbits + 7) / 8, (cbits + 7) / 8, ws->n_cu, (hipStream_t)stream));
     return QED_OK;
 }
 

@@ -299,9 +299,9 @@ hipError_t launch_merge(MergeArgs a, int prec, int mbin_passes, int cell_passes,
     if (prec == 0) hipLaunchKernelGGL((k_merge_keys<double>), dim3(ge), dim3(256), 0, s, a);
     else hipLaunchKernelGGL((k_merge_keys<float>), dim3(ge), dim3(256), 0, s, a);
     RadixBufs b = {{a.key[0], a.key[1]}, {a.idx[0], a.idx[1]}, a.hist, a.hoff};
-    int cur = launch_radix_passes(b, 0, a.src.count, cap, 0, mbin_passes, n_cu, a.ws, s);
+    int cur = launch_radix_passes8(b, 0, a.src.count, cap, mbin_passes, n_cu, a.ws, s);
     hipLaunchKernelGGL(k_merge_rekey, dim3(ge), dim3(256), 0, s, a.g, b.idx[cur], b.key[cur], a.src.count, cap);
-    cur = launch_radix_passes(b, cur, a.src.count, cap, 0, cell_passes, n_cu, a.ws, s);
+    cur = launch_radix_passes8(b, cur, a.src.count, cap, cell_passes, n_cu, a.ws, s);
     // sorted keys and order in (key[cur], idx[cur]); the other pair, g and o are free
     const uint32_t *kf = b.key[cur], *idx = b.idx[cur];
     uint32_t *head = b.key[cur ^ 1], *hscan = b.idx[cur ^ 1], *gstart = a.g, *ooff = a.o;

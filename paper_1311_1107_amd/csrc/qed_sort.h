@@ -20,17 +20,13 @@ struct SortArgs {
 };
 
 // LSD radix passes over (key, index) pairs: the first *count entries (clamped
-// to cap) of key[cur], idx[cur], 4-bit digits from digit first_pass on,
-// ping-ponging between the two buffers; returns the buffer holding the result.
+// to cap) of key[cur], idx[cur], 8-bit digits (digit p at bit 8p), tiles of
+// 2048 keys, ping-ponging between the two buffers; returns the buffer holding
+// the result.  hist and hoff hold radix_hist_len(cap) entries each.
 struct RadixBufs {
     uint32_t *key[2], *idx[2];
-    uint32_t *hist, *hoff;           // 16 * ceil(cap / 4096) entries each
+    uint32_t *hist, *hoff;
 };
-int launch_radix_passes(const RadixBufs &b, int cur, const int64_t *count, int64_t cap, int first_pass, int passes,
-                        int n_cu, WsDev ws, hipStream_t s);
-
-// The same with 8-bit digits (digit p at bit 8p), tiles of 2048 keys; hist and
-// hoff hold radix_hist_len(cap) entries each.
 int launch_radix_passes8(const RadixBufs &b, int cur, const int64_t *count, int64_t cap, int passes, int n_cu,
                          WsDev ws, hipStream_t s);
 int64_t radix_hist_len(int64_t cap);
@@ -55,6 +51,7 @@ struct MergeArgs {
     WsDev ws;
 };
 
+// mbin_passes, cell_passes: 8-bit radix passes of the momentum-bin and cell keys
 hipError_t launch_merge(MergeArgs a, int prec, int mbin_passes, int cell_passes, int n_cu, hipStream_t s);
 
 // cell sort of keys of `bits` bits (8-bit radix passes)

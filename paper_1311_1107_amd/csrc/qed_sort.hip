@@ -7,12 +7,11 @@
 // of the cell holding the particle, nx ny nz for particles outside the grid,
 // and the largest key for decayed photons (tau = +inf), which are dropped.
 //
-// LSD radix sort, 4-bit digits: per pass a count kernel (per-tile digit
+// LSD radix sort, 8-bit digits: per pass a count kernel (per-tile digit
 // histograms, digit-major), an exclusive scan of the histograms, and a scatter
-// kernel that ranks each tile in LDS (every thread ranks 16 consecutive keys;
-// per-thread digit counts and a block scan over (digit, thread) give each key
-// its stable slot) and writes it out coalesced.  A final kernel gathers the
-// particles into the destination arrays.
+// kernel that ranks each tile in LDS in stable order and writes it out
+// coalesced.  A final kernel gathers the particles into the destination
+// arrays.
 #include "qed_sort.h"
 
 namespace qed {
@@ -20,7 +19,6 @@ namespace qed {
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;   // 4096 keys per tile
-constexpr int kDigits = 16;
 
 // particle count of the source, clamped to its capacity (every pass agrees on it)
 __device__ __forceinline__ int64_t sort_count(const int64_t *count, int64_t cap) {
@@ -72,39 +70,6 @@ __global__ void k_sort_zero(unsigned long long *live) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *live = 0ull;
 }
 
-// per-tile digit histograms, stored digit-major: hist[d * n_tiles + tile].
-// Counted with wave ballots: the keys of a tile are often all equal (the
-// particles were in cell order already), which would serialise LDS atomics on
-// one counter.
-__global__ void __launch_bounds__(256)
-k_radix_count(const uint32_t *keys, const int64_t *count, int64_t cap, int shift, uint32_t *hist) {
-    __shared__ uint32_t s_h[kMaxWaves * kDigits];
-    const int tid = threadIdx.x, lane = lane_id(), wid = tid / kWave;
-    const int64_t n = sort_count(count, cap);
-    const int64_t n_tiles = (n + kSortTile - 1) / kSortTile;
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const int64_t b = tile * kSortTile;
-        uint32_t mine = 0;                                  // lane q < 16: the wave's count of digit q
-        for (int j = 0; j < kSortItems; ++j) {
-            const int64_t i = b + j * kSortThreads + tid;
-            const uint32_t d = i < n ? (keys[i] >> shift) & (kDigits - 1) : (uint32_t)kDigits;
-#pragma unroll
-            for (int q = 0; q < kDigits; ++q) {
-                const uint32_t c = (uint32_t)__popcll(__ballot(d == (uint32_t)q));
-                if (lane == q) mine += c;
-            }
-        }
-        if (lane < kDigits) s_h[wid * kDigits + lane] = mine;
-        __syncthreads();
-        if (tid < kDigits) {
-            uint32_t t = 0;
-            for (int w = 0; w < kSortThreads / kWave; ++w) t += s_h[w * kDigits + tid];
-            hist[(int64_t)tid * n_tiles + tile] = t;
-        }
-        __syncthreads();
-    }
-}
-
 // exclusive scan of a u32 array of ceil(*count / div) * mult items
 // (decoupled look-back over blocks of 4096)
 __global__ void __launch_bounds__(256)
@@ -148,99 +113,6 @@ k_scan_u32(const uint32_t *in, uint32_t *out, const int64_t *count, int64_t cap,
         for (int j = 0; j < kSortItems; ++j) {
             if (b + j < n_items) out[b + j] = r;
             r += v[j];
-        }
-        __syncthreads();
-    }
-}
-
-// Stable scatter of one 4-bit digit.  The tile goes through LDS so that the
-// global loads and stores are coalesced: the keys are loaded in order, each
-// thread ranks 16 consecutive keys of the tile (per-thread digit counts and a
-// block scan over (digit, thread) give every key its slot in the tile's
-// stable order), the keys are placed in LDS in that order and written out in
-// runs that are contiguous per digit.  The staging copy has one pad word per
-// 16 keys, so that the ranking threads read it without bank conflicts.
-constexpr int kPadTile = kSortTile + kSortTile / 16;
-
-__global__ void __launch_bounds__(256)
-k_radix_scatter(const uint32_t *kin, const uint32_t *iin, uint32_t *kout, uint32_t *iout,
-                const int64_t *count, int64_t cap, int shift, const uint32_t *hoff) {
-    __shared__ uint32_t s_c[kDigits * kSortThreads];     // (digit, thread) counts, then offsets
-    __shared__ uint32_t s_k[kPadTile], s_v[kPadTile];   // the tile: in order (padded), then sorted
-    __shared__ uint32_t s_go[kDigits];                   // global slot of digit d minus its slot in the tile
-    __shared__ uint32_t s_wave[2 * kMaxWaves];
-    const int tid = threadIdx.x;
-    const int64_t n = sort_count(count, cap);
-    const int64_t n_tiles = (n + kSortTile - 1) / kSortTile;
-    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const int64_t base = tile * kSortTile;
-        const int nv = (int)(n - base < (int64_t)kSortTile ? n - base : (int64_t)kSortTile);   // keys in the tile
-#pragma unroll
-        for (int j = 0; j < kSortItems; ++j) {
-            const int p = j * kSortThreads + tid;
-            if (p < nv) {
-                s_k[p + (p >> 4)] = kin[base + p];
-                s_v[p + (p >> 4)] = iin[base + p];
-            }
-        }
-        __syncthreads();
-        uint32_t k[kSortItems], v[kSortItems];
-        uint32_t c[kDigits];
-#pragma unroll
-        for (int d = 0; d < kDigits; ++d) c[d] = 0u;
-#pragma unroll
-        for (int j = 0; j < kSortItems; ++j) {
-            const int p = tid * kSortItems + j;               // padded slot: 17 tid + j
-            const bool in = p < nv;
-            k[j] = in ? s_k[p + (p >> 4)] : 0u;
-            v[j] = in ? s_v[p + (p >> 4)] : 0u;
-            if (in) {
-                const uint32_t d = (k[j] >> shift) & (kDigits - 1);
-#pragma unroll
-                for (int q = 0; q < kDigits; ++q) c[q] += (d == (uint32_t)q);
-            }
-        }
-#pragma unroll
-        for (int d = 0; d < kDigits; ++d) s_c[d * kSortThreads + tid] = c[d];
-        __syncthreads();
-        // exclusive scan of s_c in (digit, thread) order: thread t owns entries 16t .. 16t+15
-        uint32_t part[kSortItems], sum = 0;
-#pragma unroll
-        for (int j = 0; j < kSortItems; ++j) { part[j] = s_c[tid * kSortItems + j]; sum += part[j]; }
-        uint32_t e, e1, tot, tot1;
-        block_scan2(sum, 0u, e, e1, tot, tot1, s_wave);
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < kSortItems; ++j) { s_c[tid * kSortItems + j] = e; e += part[j]; }
-        __syncthreads();
-        // this thread's keys of digit d take the tile slots from s_c[d * 256 + tid] on; the
-        // tile's keys of digit d start at s_c[d * 256] and globally at hoff[d * n_tiles + tile]
-#pragma unroll
-        for (int d = 0; d < kDigits; ++d) c[d] = s_c[d * kSortThreads + tid];
-        if (tid < kDigits) s_go[tid] = hoff[(int64_t)tid * n_tiles + tile] - s_c[tid * kSortThreads];
-        // every thread read its keys from the staging copy before the scan's barriers
-#pragma unroll
-        for (int j = 0; j < kSortItems; ++j) {
-            if (tid * kSortItems + j < nv) {
-                const uint32_t d = (k[j] >> shift) & (kDigits - 1);
-                uint32_t pos = 0;
-#pragma unroll
-                for (int q = 0; q < kDigits; ++q)
-                    if (d == (uint32_t)q) { pos = c[q]; c[q] = pos + 1; }
-                s_k[pos] = k[j];
-                s_v[pos] = v[j];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < kSortItems; ++j) {
-            const int p = j * kSortThreads + tid;
-            if (p < nv) {
-                const uint32_t key = s_k[p];
-                const uint32_t g = s_go[(key >> shift) & (kDigits - 1)] + (uint32_t)p;
-                kout[g] = key;
-                iout[g] = s_v[p];
-            }
         }
         __syncthreads();
     }
@@ -403,27 +275,6 @@ k_sort_permute(SortArgs a) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *a.dst.count = live;
 }
 
-static unsigned radix_grid(int64_t capacity, int n_cu) {
-    const int64_t tiles = (capacity + kSortTile - 1) / kSortTile;
-    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)n_cu * 8));
-}
-
-int launch_radix_passes(const RadixBufs &b, int cur, const int64_t *count, int64_t cap, int first_pass, int passes,
-                        int n_cu, WsDev ws, hipStream_t s) {
-    const int64_t tiles = (cap + kSortTile - 1) / kSortTile;
-    const unsigned gb = radix_grid(cap, n_cu);
-    const unsigned gs = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tiles * kDigits + kSortTile - 1) / kSortTile, n_cu));
-    for (int p = 0; p < passes; ++p, cur ^= 1) {
-        const int shift = 4 * (first_pass + p);
-        hipLaunchKernelGGL(k_radix_count, dim3(gb), dim3(256), 0, s, b.key[cur], count, cap, shift, b.hist);
-        hipLaunchKernelGGL(k_scan_u32, dim3(gs), dim3(256), 0, s, b.hist, b.hoff, count, cap, (int64_t)kSortTile,
-                           (int64_t)kDigits, ws);
-        hipLaunchKernelGGL(k_radix_scatter, dim3(gb), dim3(256), 0, s, b.key[cur], b.idx[cur], b.key[cur ^ 1],
-                           b.idx[cur ^ 1], count, cap, shift, b.hoff);
-    }
-    return cur;
-}
-
 int launch_radix_passes8(const RadixBufs &b, int cur, const int64_t *count, int64_t cap, int passes, int n_cu,
                          WsDev ws, hipStream_t s) {
     const int64_t tiles = (cap + kTile8 - 1) / kTile8;
@@ -440,9 +291,7 @@ int launch_radix_passes8(const RadixBufs &b, int cur, const int64_t *count, int6
     return cur;
 }
 
-int64_t radix_hist_len(int64_t cap) {
-    return std::max<int64_t>(16 * ((cap + kSortTile - 1) / kSortTile + 1), (int64_t)kDigits8 * ((cap + kTile8 - 1) / kTile8 + 1));
-}
+int64_t radix_hist_len(int64_t cap) { return (int64_t)kDigits8 * ((cap + kTile8 - 1) / kTile8 + 1); }
 
 void launch_scan_u32(const uint32_t *in, uint32_t *out, const int64_t *count, int64_t cap, int n_cu, WsDev ws,
                      hipStream_t s) {
