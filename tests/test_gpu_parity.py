@@ -236,12 +236,13 @@ def _sort_particles(n, seed, prec):
     return p
 
 
-@pytest.mark.parametrize("prec,n", [(B.QED_F64, 0), (B.QED_F64, 1), (B.QED_F64, 3 * 4096 + 77),
-                                    (B.QED_F64, 1_200_013), (B.QED_F32, 50_001)])
+@pytest.mark.parametrize("prec,n", [(B.QED_F64, 0), (B.QED_F64, 1), (B.QED_F64, 2048), (B.QED_F64, 2049),
+                                    (B.QED_F64, 3 * 4096 + 77), (B.QED_F64, 1_200_013), (B.QED_F32, 50_001)])
 def test_sort_by_cell_matches_oracle(prec, n):
     """qed_sort_by_cell against the oracle's stable cell sort of the live
     particles: bit-exact permutation and fields; decayed photons dropped.
-    1.2e6 particles take the histogram scan over several look-back blocks."""
+    2048 and 2049 sit at the edge of a radix tile; 1.2e6 particles take the
+    histogram scan over several look-back blocks."""
     _need_gpu()
     print(f"case: sort prec={prec} n={n}", flush=True)
     p = _sort_particles(n, seed=21 + n, prec=prec)
